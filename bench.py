@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the alpha_{2,3} generator on one MI355X.
+
+One step is the whole plain path over the bulk workload: seed a starting
+index (Eq. 2), generate 2^30 binary64 variates and then 2^28 raw uint64
+states from that seed (Eq. 3 with per-thread skip-ahead), with the outputs
+resident in HBM.  The JSON line reports whole-job variates/s, the
+roofline of the dominant kernel (the f64 generator) measured with HIP events
+on the launch stream, the paper's "Constant" write ceiling for the same
+store pattern (Section 4.2), a comparison of the exact reductions, and the
+CPU oracle timed on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+METRIC = "uniform variates/sec at 1 GPU and % of HBM write BW; batched/served vs plain"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _timed_kernel(fn, reps, torch):
+    """Average duration (s) of fn() enqueued on the current stream."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    return sum(ms) / len(ms) / 1e3
+
+
+def cpu_baseline(case):
+    """The oracle on all host threads over one whole step of the workload,
+    streamed through one 2^25-element host buffer; plus one thread on a
+    2^24-element prefix."""
+    import numpy as np
+
+    import oracle as orc
+
+    chunk = 1 << 25
+    threads = orc.max_threads()
+    z0 = orc.seed(case.index)
+    t0 = time.perf_counter()
+    for count, dt in ((case.count_f64, np.float64), (case.count_u64, np.uint64)):
+        buf = np.empty(chunk, dtype=dt)
+        z = z0
+        for _ in range(count // chunk):
+            z = orc.gen_into(z, buf, threads=0)
+    wall = time.perf_counter() - t0
+    total = case.count_f64 + case.count_u64
+    one = np.empty(1 << 24, dtype=np.float64)
+    t1 = time.perf_counter()
+    orc.gen_into(z0, one, threads=1)
+    wall1 = time.perf_counter() - t1
+    return {
+        "value": total / wall,
+        "unit": "variates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "one full step (2^30 f64 + 2^28 u64 from the same seed index) in 2^25-element "
+                  "chunks, OpenMP skip-ahead partition over %d threads; %.2f s wall" % (threads, wall),
+        "single_thread_value": float(one.size / wall1),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the fill ceiling and reduction comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log("bench.py measures one GPU only: this build has no multi-GPU path "
+            "(--gpus %d requested)." % args.gpus)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        log("bench.py runs as a single process on one GPU.")
+        sys.exit(2)
+
+    import torch
+
+    import paper_1206_1187_amd as nn
+    from paper_1206_1187_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    nn.init(0)
+    case = wl.plain_bulk()
+    out_f = torch.empty(case.count_f64, dtype=torch.float64, device="cuda")
+    out_u = torch.empty(case.count_u64, dtype=torch.uint64, device="cuda")
+    cfg_f = nn.default_cfg("f64", case.count_f64)
+    cfg_u = nn.default_cfg("u64", case.count_u64)
+    log("workload", case, "cfg f64", cfg_f.as_dict(), "cfg u64", cfg_u.as_dict())
+
+    def step(ev=None):
+        s = nn.seed(case.index)
+        if ev is not None:
+            ev[0].record()
+        nn.generate_into(s, out_f)
+        if ev is not None:
+            ev[1].record()
+        nn.generate_into(s, out_u)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    f64_ms = [a.elapsed_time(b) for a, b in evs]
+    f64_s = sum(f64_ms) / len(f64_ms) / 1e3
+    per_step = case.count_f64 + case.count_u64
+    value = per_step * args.steps / elapsed
+    achieved = 8.0 * case.count_f64 / f64_s / 1e9
+    log("timed %d steps in %.3f s: %.4g variates/s; f64 kernel %.3f ms = %.1f GB/s"
+        % (args.steps, elapsed, value, f64_s * 1e3, achieved))
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "variates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain bulk: seed index %d (numpy default_rng(1) over [3^33+100, 2^53]), "
+                        "2^30 f64 variates then 2^28 u64 states per step" % case.index,
+            "count_f64": case.count_f64,
+            "count_u64": case.count_u64,
+            "launch_f64": cfg_f.as_dict(),
+            "launch_u64": cfg_u.as_dict(),
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "kernel": "k_generate f64 (%s)" % ["", "fp64", "barrett", "shoup", "montgomery"][cfg_f.mulmod],
+            "algorithmic_bytes_per_launch": 8 * case.count_f64,
+        },
+    }
+
+    if not args.no_extras:
+        extras = {}
+        reps = 20
+        u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u), reps, torch)
+        extras["generate_u64_GBps"] = 8.0 * case.count_u64 / u_s / 1e9
+        fill_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000), reps, torch)
+        fill_gbps = 8.0 * case.count_f64 / fill_s / 1e9
+        extras["fill_ceiling_GBps"] = fill_gbps
+        extras["f64_frac_of_fill_ceiling"] = achieved / fill_gbps
+        # Paper's Table 2: generation time net of the store time.
+        net = f64_s - fill_s
+        extras["net_generation_ms"] = net * 1e3
+        shoot = {}
+        for name in ("fp64", "barrett", "shoup", "montgomery"):
+            for kind, out in (("f64", out_f), ("u64", out_u)):
+                cfg = nn.make_cfg(mulmod=name)
+                s = _timed_kernel(
+                    lambda: nn.generate_into(nn.seed(case.index), out, cfg=cfg), 10, torch)
+                shoot["%s_%s_GBps" % (name, kind)] = 8.0 * out.numel() / s / 1e9
+        extras["mulmod_shootout"] = shoot
+        result["extras"] = extras
+        log("extras", json.dumps(extras))
+
+    del out_f, out_u
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(case)
+        log("cpu_baseline", json.dumps(cb))
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

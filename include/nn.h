@@ -1,0 +1,160 @@
+/*
+ * nn.h -- C ABI of the MI355X (gfx950) alpha_{2,3} normal-number generator.
+ *
+ * The generator is the linear congruential form of Bailey and Borwein's
+ * alpha_{2,3} digit generator studied by Beliakov, Johnstone, Creighton and
+ * Wilkin, "Parallel random variates generator for GPUs based on normal
+ * numbers" (Section 2, Algorithm BB):
+ *
+ *   seed     z_0 = 2^(a - 3^33) * floor(3^33 / 2)  mod 3^33      (Eq. 2)
+ *   step     z_k = 2^53 * z_(k-1)                  mod 3^33      (Eq. 3)
+ *   variate  u_k = z_k * 3^-33 in (0,1)                           (Alg. BB step 3)
+ *
+ * with period 2 * 3^32 (Section 2).  Every function is extern "C", takes
+ * plain integers and pointers, never throws, and returns an nn_status
+ * (0 = NN_OK).  On any error nothing is enqueued and no output argument is
+ * written.  A failing call leaves a human-readable detail retrievable with
+ * nn_last_error() on the same host thread.
+ *
+ * States.  A state is a unit modulo 3^33: 1 <= s < 3^33 and s mod 3 != 0.
+ * Every unit lies on the single cycle of Eq. 3 (2^53 generates the unit
+ * group), so any unit is a valid state; anything else is NN_EINVAL.
+ *
+ * Output convention.  A call that emits n values after state s emits
+ * z_1..z_n (Eq. 3 applied before each output, as Algorithm BB returns z_k
+ * for k >= 1) and leaves s = z_n, so consecutive calls concatenate to the
+ * serial sequence.  F64 outputs are RN(double(z) * RN(1/3^33)), the product
+ * with the rounded reciprocal that the paper's listings multiply by; U64
+ * outputs are the raw states z.
+ */
+#ifndef NN_H
+#define NN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nn_status {
+    NN_OK = 0,
+    NN_EINVAL = 1, /* invalid argument: state, index, kind, pointer, config */
+    NN_ERANGE = 2, /* count too large for the address space or a descriptor */
+    NN_EHIP = 3,   /* a HIP runtime call or kernel launch failed */
+    NN_ENOMEM = 4, /* device or host allocation failed */
+    NN_ENODEV = 5  /* no usable gfx950 device */
+} nn_status;
+
+typedef enum nn_out_kind {
+    NN_OUT_U64 = 0, /* raw states z_k (uint64) */
+    NN_OUT_F64 = 1  /* variates RN(z_k * RN(3^-33)) (IEEE binary64) */
+} nn_out_kind;
+
+/* 106-bit modular multiplication used by the step loop.  All are exact;
+ * they differ only in speed (Section 3.1 discusses the paper's own
+ * choices; these are the gfx950 candidates). */
+typedef enum nn_mulmod {
+    NN_MULMOD_DEFAULT = 0,
+    NN_MULMOD_FP64 = 1,     /* FP64 FMA two-product, FP64 quotient estimate */
+    NN_MULMOD_BARRETT = 2,  /* integer Barrett, k = 53, mu = floor(2^106/m) */
+    NN_MULMOD_SHOUP = 3,    /* integer fixed-multiplier quotient (Shoup)    */
+    NN_MULMOD_MONTGOMERY = 4 /* integer Montgomery, R = 2^64, pre-scaled   */
+} nn_mulmod;
+
+#define NN_MODULUS 5559060566555523ULL   /* 3^33 */
+#define NN_PERIOD 3706040377703682ULL    /* 2 * 3^32 */
+#define NN_INDEX_MIN 5559060566555623ULL /* 3^33 + 100 (Algorithm BB step 1) */
+#define NN_INDEX_MAX 9007199254740992ULL /* 2^53       (Algorithm BB step 1) */
+
+/* Launch configuration.  Any field left 0 takes the library default for the
+ * call's size.  block: threads per workgroup, a multiple of 64 in [64,1024].
+ * grid: workgroups (the total thread count block*grid must not exceed 2^24).
+ * unroll: 1, 2, 4 or 8 iterations of the step loop per trip.
+ * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable (default is
+ * non-temporal streaming stores). */
+typedef struct nn_launch_cfg {
+    uint32_t block;
+    uint32_t grid;
+    uint32_t mulmod; /* nn_mulmod */
+    uint32_t unroll;
+    uint32_t flags;
+} nn_launch_cfg;
+#define NN_CFG_TEMPORAL_STORES 1u
+
+/* ---------------------------------------------------------------- host -- */
+
+/* nn_seed -- Eq. 2 (Algorithm BB steps 1-2): the state z_0 of starting index
+ * `index`.  index must lie in [NN_INDEX_MIN, NN_INDEX_MAX] (inclusive, as
+ * Algorithm BB step 1 states the range); otherwise NN_EINVAL.  state_out must
+ * be non-NULL.  Pure host computation, thread-safe, no device needed. */
+int nn_seed(uint64_t index, uint64_t *state_out);
+
+/* nn_skip -- skip-ahead (Section 2, last paragraph: any iterate is computable
+ * directly): *state_out = the state k steps after `state`, i.e.
+ * state * (2^53)^k mod 3^33.  Any 64-bit k is accepted; it is reduced modulo
+ * the period 2*3^32.  NN_EINVAL for an invalid state or NULL state_out.
+ * Pure host computation, thread-safe, no device needed. */
+int nn_skip(uint64_t state, uint64_t k, uint64_t *state_out);
+
+/* --------------------------------------------------------------- device -- */
+
+/* nn_init -- set up the library on HIP device `device` (uploads the
+ * immutable skip-ahead tables, ~0.8 MB, owned by the library until process
+ * exit).  Optional: the first generating call on a device does it.  The
+ * caller's current device is left unchanged.  Thread-safe. */
+int nn_init(int device);
+
+/* nn_generate -- Algorithm BB step 3 for `count` outputs (Eq. 3 iterated).
+ * Writes z_1..z_count after *state, in serial order, to out_dev[0..count)
+ * as uint64 (NN_OUT_U64) or binary64 (NN_OUT_F64), then sets *state to
+ * z_count.  out_dev: device memory owned by the caller on the current HIP
+ * device, 8-byte aligned, holding count*8 bytes; the library keeps no
+ * reference to it.  stream: a hipStream_t (NULL = the legacy default
+ * stream).  Asynchronous: the kernel is enqueued on `stream` and the host
+ * state is advanced by skip-ahead without waiting.  count == 0 is a no-op
+ * (out_dev may then be NULL).  Errors: NN_EINVAL (state, kind, NULL or
+ * misaligned pointers), NN_ERANGE (count*8 overflows), NN_EHIP (launch
+ * failed; *state unchanged). */
+int nn_generate(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream);
+
+/* nn_generate_ex -- nn_generate with an explicit launch configuration
+ * (cfg may be NULL for the defaults).  The output is identical for every
+ * valid configuration.  NN_EINVAL for an invalid configuration. */
+int nn_generate_ex(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream,
+                   const nn_launch_cfg *cfg);
+
+/* nn_default_cfg -- the configuration nn_generate would use for `count`
+ * outputs of `kind` on the current device (fields all filled in). */
+int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg *cfg_out);
+
+/* nn_fill -- the paper's "Constant" measurement kernel (Section 4.2,
+ * Table 1): writes `value` to out_dev[0..count) with exactly the store
+ * pattern nn_generate_ex uses for the same cfg, giving the write-bandwidth
+ * ceiling of that pattern.  Same pointer rules and errors as nn_generate. */
+int nn_fill(uint64_t count, void *out_dev, uint64_t value, void *stream,
+            const nn_launch_cfg *cfg);
+
+/* ------------------------------------------------------------- status -- */
+
+/* Static description of a status code (never NULL). */
+const char *nn_strerror(int status);
+/* Detail of the last failing call on this host thread ("" if none). */
+const char *nn_last_error(void);
+/* Library version string. */
+const char *nn_version(void);
+
+/* ---------------------------------------------------------- diagnostic -- */
+
+/* nn_debug_mulmod -- runs the host build of a step-loop modular
+ * multiplication (the same source the device compiles) on n pairs:
+ * out[i] = a[i] * b[i] mod 3^33, with b[i] taking the role of the fixed
+ * multiplier.  Every a[i] and b[i] must be a valid state.  For testing the
+ * arithmetic on a CPU; host pointers. */
+int nn_debug_mulmod(int mulmod, const uint64_t *a, const uint64_t *b, uint64_t n,
+                    uint64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NN_H */

@@ -1,0 +1,137 @@
+"""MI355X-native alpha_{2,3} normal-number uniform generator.
+
+Python binding over ``libnn.so`` (include/nn.h): argument marshalling only.
+Every output value is computed by the HIP kernels; torch supplies device
+memory and the current stream.  The generator is Algorithm BB of Beliakov
+et al. (Section 2): seed z_0 by Eq. 2 from a starting index, step
+z -> 2^53 z mod 3^33 (Eq. 3), variates z * 3^-33.
+
+    import paper_1206_1187_amd as nn
+    s = nn.seed(3**33 + 100)
+    u, s = nn.generate(s, 1 << 20)          # float64 tensor on cuda, new state
+"""
+import ctypes
+
+from . import _native
+from ._native import (NN_OUT_F64, NN_OUT_U64, LaunchCfg, NativeLibraryMissing, NNError,
+                      MULMOD_NAMES)
+
+MODULUS = 5559060566555523
+PERIOD = 2 * 3 ** 32
+INDEX_MIN = MODULUS + 100
+INDEX_MAX = 2 ** 53
+
+__all__ = [
+    "seed", "skip", "generate", "generate_into", "fill", "default_cfg", "make_cfg",
+    "init", "version", "NNError", "NativeLibraryMissing", "MODULUS", "PERIOD",
+    "INDEX_MIN", "INDEX_MAX",
+]
+
+
+def version():
+    return _native.lib().nn_version().decode()
+
+
+def seed(index):
+    """Eq. 2: state of starting index ``index`` in [3^33+100, 2^53]."""
+    out = ctypes.c_uint64(0)
+    if not 0 <= int(index) < 2 ** 64:
+        raise NNError(_native.NN_EINVAL, "index out of the 64-bit range")
+    _native.check(_native.lib().nn_seed(int(index), ctypes.byref(out)))
+    return int(out.value)
+
+
+def skip(state, k):
+    """State ``k`` steps after ``state`` (k reduced modulo the period)."""
+    out = ctypes.c_uint64(0)
+    _native.check(_native.lib().nn_skip(int(state), int(k) % 2 ** 64, ctypes.byref(out)))
+    return int(out.value)
+
+
+def init(device=0):
+    _native.check(_native.lib().nn_init(int(device)))
+
+
+def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False):
+    if isinstance(mulmod, str):
+        mulmod = MULMOD_NAMES[mulmod]
+    return LaunchCfg(int(block), int(grid), int(mulmod), int(unroll),
+                     _native.NN_CFG_TEMPORAL_STORES if temporal else 0)
+
+
+def default_cfg(kind, count):
+    cfg = LaunchCfg()
+    _native.check(_native.lib().nn_default_cfg(_kind(kind), int(count), ctypes.byref(cfg)))
+    return cfg
+
+
+def _kind(kind):
+    if kind in (NN_OUT_U64, "u64", "uint64"):
+        return NN_OUT_U64
+    if kind in (NN_OUT_F64, "f64", "float64"):
+        return NN_OUT_F64
+    import torch
+    if kind == torch.uint64:
+        return NN_OUT_U64
+    if kind == torch.float64:
+        return NN_OUT_F64
+    raise NNError(_native.NN_EINVAL, "unknown output kind %r" % (kind,))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def generate_into(state, out, stream=None, cfg=None):
+    """Fill the contiguous cuda tensor ``out`` (uint64 or float64) with the
+    next ``out.numel()`` outputs after ``state``; returns the new state.
+    Asynchronous on ``stream`` (default: torch's current stream)."""
+    import torch
+    if not out.is_cuda or not out.is_contiguous():
+        raise NNError(_native.NN_EINVAL, "out must be a contiguous cuda tensor")
+    kind = _kind(out.dtype)
+    st = ctypes.c_uint64(int(state))
+    with torch.cuda.device(out.device):
+        rc = _native.lib().nn_generate_ex(
+            ctypes.byref(st), out.numel(), ctypes.c_void_p(out.data_ptr()), kind,
+            _stream_handle(stream), ctypes.byref(cfg) if cfg is not None else None)
+    _native.check(rc)
+    return int(st.value)
+
+
+def generate(state, count, dtype="f64", device="cuda", stream=None, cfg=None):
+    """Allocate and fill ``count`` outputs; returns (tensor, new_state)."""
+    import torch
+    tdtype = torch.uint64 if _kind(dtype) == NN_OUT_U64 else torch.float64
+    out = torch.empty(int(count), dtype=tdtype, device=device)
+    return out, generate_into(state, out, stream=stream, cfg=cfg)
+
+
+def fill(out, value, stream=None, cfg=None):
+    """The paper's "Constant" kernel: write ``value`` (a 64-bit pattern) with
+    the generator's store pattern."""
+    import torch
+    if not out.is_cuda or not out.is_contiguous() or out.element_size() != 8:
+        raise NNError(_native.NN_EINVAL, "out must be a contiguous 8-byte cuda tensor")
+    with torch.cuda.device(out.device):
+        rc = _native.lib().nn_fill(out.numel(), ctypes.c_void_p(out.data_ptr()),
+                                   int(value) % 2 ** 64, _stream_handle(stream),
+                                   ctypes.byref(cfg) if cfg is not None else None)
+    _native.check(rc)
+
+
+def debug_mulmod(variant, a, b):
+    """Host build of a step-loop reduction: a[i]*b[i] mod 3^33 (numpy uint64)."""
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    out = np.empty_like(a)
+    if isinstance(variant, str):
+        variant = MULMOD_NAMES[variant]
+    p = ctypes.POINTER(ctypes.c_uint64)
+    _native.check(_native.lib().nn_debug_mulmod(
+        int(variant), a.ctypes.data_as(p), b.ctypes.data_as(p), a.size, out.ctypes.data_as(p)))
+    return out

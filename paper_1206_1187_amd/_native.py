@@ -1,0 +1,103 @@
+"""ctypes loader for ``libnn.so`` (the C ABI declared in include/nn.h).
+
+The library must have been built in-tree (``paper_1206_1187_amd/build.py``);
+there is no fallback: a missing library raises ``NativeLibraryMissing``.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnn.so")
+
+NN_OK, NN_EINVAL, NN_ERANGE, NN_EHIP, NN_ENOMEM, NN_ENODEV = range(6)
+NN_OUT_U64, NN_OUT_F64 = 0, 1
+NN_MULMOD_DEFAULT, NN_MULMOD_FP64, NN_MULMOD_BARRETT, NN_MULMOD_SHOUP, NN_MULMOD_MONTGOMERY = range(5)
+NN_CFG_TEMPORAL_STORES = 1
+
+MULMOD_NAMES = {
+    "default": NN_MULMOD_DEFAULT,
+    "fp64": NN_MULMOD_FP64,
+    "barrett": NN_MULMOD_BARRETT,
+    "shoup": NN_MULMOD_SHOUP,
+    "montgomery": NN_MULMOD_MONTGOMERY,
+}
+
+
+class NativeLibraryMissing(RuntimeError):
+    pass
+
+
+class NNError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__("nn status %d: %s" % (status, detail))
+
+
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_uint32),
+        ("grid", ctypes.c_uint32),
+        ("mulmod", ctypes.c_uint32),
+        ("unroll", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class StreamDesc(ctypes.Structure):
+    """One stream of a batched call (see nn_stream_desc in include/nn.h)."""
+    _fields_ = [
+        ("state", ctypes.c_uint64),
+        ("length", ctypes.c_uint64),
+        ("out_offset", ctypes.c_uint64),
+    ]
+
+
+_u64 = ctypes.c_uint64
+_pu64 = ctypes.POINTER(ctypes.c_uint64)
+_vp = ctypes.c_void_p
+_int = ctypes.c_int
+
+# name -> (restype, argtypes); must match include/nn.h
+SIGNATURES = {
+    "nn_seed": (_int, [_u64, _pu64]),
+    "nn_skip": (_int, [_u64, _u64, _pu64]),
+    "nn_init": (_int, [_int]),
+    "nn_generate": (_int, [_pu64, _u64, _vp, _int, _vp]),
+    "nn_generate_ex": (_int, [_pu64, _u64, _vp, _int, _vp, ctypes.POINTER(LaunchCfg)]),
+    "nn_default_cfg": (_int, [_int, _u64, ctypes.POINTER(LaunchCfg)]),
+    "nn_fill": (_int, [_u64, _vp, _u64, _vp, ctypes.POINTER(LaunchCfg)]),
+    "nn_strerror": (ctypes.c_char_p, [_int]),
+    "nn_last_error": (ctypes.c_char_p, []),
+    "nn_version": (ctypes.c_char_p, []),
+    "nn_debug_mulmod": (_int, [_int, _pu64, _pu64, _u64, _pu64]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loaded on first use)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NativeLibraryMissing(
+                "%s is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+                "or `python paper_1206_1187_amd/build.py`" % LIB_PATH)
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            if hasattr(handle, name):
+                fn = getattr(handle, name)
+                fn.restype = res
+                fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(status):
+    if status != NN_OK:
+        detail = lib().nn_last_error().decode() or lib().nn_strerror(status).decode()
+        raise NNError(status, detail)
+    return status

@@ -1,0 +1,147 @@
+// nn_arith.hpp -- exact arithmetic modulo 3^33 shared by the gfx950 kernels
+// and their host build (the same source, compiled for both sides).
+//
+// The generator (Section 2, Eq. 3) multiplies a 53-bit state by a 53-bit
+// multiplier modulo m = 3^33 ~ 2^52.3, a 106-bit product.  CDNA has no
+// 64x64-bit integer multiplier, so the step loop offers four exact
+// reductions (chosen by measurement):
+//
+//  * mm_fp64   -- FP64 FMA: the product as an exact double-double
+//                 (two-product), a quotient estimate from a double-double
+//                 v/m, and an exactly computed remainder;
+//  * mm_barrett -- Barrett's reduction with k = 53, mu = floor(2^106/m)
+//                 (Section 3.1, Algorithm Barrett), two final corrections;
+//  * mm_shoup   -- Shoup's fixed-multiplier quotient floor(v 2^64 / m);
+//  * mm_montgomery -- Montgomery reduction with R = 2^64, the multiplier
+//                 pre-scaled by R so states stay in standard form.
+//
+// Every function takes a state z (a unit, 1 <= z < m) and a fixed
+// multiplier described by `Mult` and returns v*z mod m in [1, m).
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define NN_HD __host__ __device__ __forceinline__
+#else
+#define NN_HD inline
+#endif
+
+namespace nn {
+
+typedef unsigned __int128 u128;
+
+constexpr uint64_t kMod = 5559060566555523ULL;               // 3^33
+constexpr uint64_t kPeriod = 2ULL * (kMod / 3ULL);            // 2*3^32
+constexpr uint64_t kMult = (uint64_t)(((u128)1 << 53) % kMod); // 2^53 mod 3^33 (Eq. 3)
+constexpr uint64_t kHalf = kMod / 2ULL;                       // floor(3^33/2) (Eq. 2)
+constexpr double kModD = 5559060566555523.0;
+constexpr double kRecip = 1.0 / 5559060566555523.0;           // RN(1/3^33)
+constexpr uint64_t kBarrettMu = (uint64_t)(((u128)1 << 106) / kMod);
+
+// -m^{-1} mod 2^64 by Newton iteration (m odd).
+constexpr uint64_t mont_neg_inv() {
+    uint64_t x = kMod;  // correct to 3 bits for odd m
+    for (int i = 0; i < 6; ++i) x *= 2ULL - kMod * x;
+    return 0ULL - x;
+}
+constexpr uint64_t kMontNInv = mont_neg_inv();
+static_assert(kMod * (0ULL - kMontNInv) == 1ULL, "Montgomery inverse");
+static_assert(kMod < (1ULL << 53) && (1ULL << 53) < 2 * kMod, "m is a 53-bit number");
+
+// A fixed multiplier v (a unit mod m) with the data each reduction needs.
+struct Mult {
+    double v;        // v, exact as a double (v < 2^53)
+    double qh, ql;   // v/m as an unevaluated double-double sum qh + ql
+    uint64_t vi;     // v
+    uint64_t shoup;  // floor(v * 2^64 / m)
+    uint64_t mont;   // v * 2^64 mod m
+};
+
+// ---------------------------------------------------------------- FP64 --
+// r = v z - q m with q = rint(z (qh + ql)).  Exactness (all values are
+// integers below 2^106, m < 2^53 < 2m):
+//  * ph + pl == v z and sh + sl == q m exactly (FMA two-product);
+//  * |q - v z/m| <= 0.75 + 2^-52, because fl(z qh + fl(z ql)) is within
+//    one rounding of v z/m and rint adds at most 0.5 (0.5 in total when the
+//    estimate is >= 2^52, where its ulp is already 1); so |r| < m;
+//  * ph - sh is exact (either both are within a factor two of each other,
+//    Sterbenz, or the difference is an integer below 2^53), pl - sl is an
+//    integer below 2^53 in magnitude, and r itself is an integer below m.
+// The translation unit is built with FP contraction off so none of these
+// products is fused into a neighbouring add.
+NN_HD double mm_fp64(double z, double v, double qh, double ql) {
+    const double ph = v * z;
+    const double pl = __builtin_fma(v, z, -ph);
+    const double e = __builtin_fma(z, qh, z * ql);
+    const double q = __builtin_rint(e);
+    const double sh = q * kModD;
+    const double sl = __builtin_fma(q, kModD, -sh);
+    const double r = (ph - sh) + (pl - sl);
+    return r < 0.0 ? r + kModD : r;
+}
+
+// ------------------------------------------------------------- Barrett --
+// Algorithm Barrett (Section 3.1) with k = 53: q1 = x >> 52,
+// q3 = (q1 mu) >> 54 underestimates floor(x/m) by at most 2.
+NN_HD uint64_t mm_barrett(uint64_t a, uint64_t b) {
+    const u128 x = (u128)a * b;
+    const uint64_t q1 = (uint64_t)(x >> 52);
+    const uint64_t q3 = (uint64_t)(((u128)q1 * kBarrettMu) >> 54);
+    uint64_t r = (uint64_t)x - q3 * kMod;  // < 3m, exact modulo 2^64
+    if (r >= kMod) r -= kMod;
+    if (r >= kMod) r -= kMod;
+    return r;
+}
+
+// --------------------------------------------------------------- Shoup --
+// q = floor(z * floor(v 2^64/m) / 2^64) is floor(v z/m) or one less.
+NN_HD uint64_t mm_shoup(uint64_t z, uint64_t v, uint64_t vshoup) {
+    const uint64_t q = (uint64_t)(((u128)z * vshoup) >> 64);
+    const uint64_t r = v * z - q * kMod;  // in [0, 2m), exact modulo 2^64
+    return r >= kMod ? r - kMod : r;
+}
+
+// ---------------------------------------------------------- Montgomery --
+// REDC(z * vmont) = z * v * 2^64 * 2^-64 = v z (mod m).  T < m^2 and
+// U m < 2^117, so T + U m fits 128 bits and the result is below 2m.
+NN_HD uint64_t mm_montgomery(uint64_t z, uint64_t vmont) {
+    const u128 t = (u128)z * vmont;
+    const uint64_t u = (uint64_t)t * kMontNInv;
+    const u128 s = t + (u128)u * kMod;
+    const uint64_t r = (uint64_t)(s >> 64);
+    return r >= kMod ? r - kMod : r;
+}
+
+// ----------------------------------------------------- variant policies --
+// State type, conversion and one multiplication per reduction.
+struct VarFP64 {
+    typedef double S;
+    static NN_HD S load(uint64_t x) { return (double)x; }
+    static NN_HD S mul(S z, const Mult& f) { return mm_fp64(z, f.v, f.qh, f.ql); }
+    static NN_HD uint64_t to_u64(S z) { return (uint64_t)z; }
+    static NN_HD double to_f64(S z) { return z * kRecip; }
+};
+struct VarBarrett {
+    typedef uint64_t S;
+    static NN_HD S load(uint64_t x) { return x; }
+    static NN_HD S mul(S z, const Mult& f) { return mm_barrett(z, f.vi); }
+    static NN_HD uint64_t to_u64(S z) { return z; }
+    static NN_HD double to_f64(S z) { return (double)z * kRecip; }
+};
+struct VarShoup {
+    typedef uint64_t S;
+    static NN_HD S load(uint64_t x) { return x; }
+    static NN_HD S mul(S z, const Mult& f) { return mm_shoup(z, f.vi, f.shoup); }
+    static NN_HD uint64_t to_u64(S z) { return z; }
+    static NN_HD double to_f64(S z) { return (double)z * kRecip; }
+};
+struct VarMontgomery {
+    typedef uint64_t S;
+    static NN_HD S load(uint64_t x) { return x; }
+    static NN_HD S mul(S z, const Mult& f) { return mm_montgomery(z, f.mont); }
+    static NN_HD uint64_t to_u64(S z) { return z; }
+    static NN_HD double to_f64(S z) { return (double)z * kRecip; }
+};
+
+}  // namespace nn
