@@ -66,20 +66,37 @@ typedef enum nn_mulmod {
 #define NN_INDEX_MIN 5559060566555623ULL /* 3^33 + 100 (Algorithm BB step 1) */
 #define NN_INDEX_MAX 9007199254740992ULL /* 2^53       (Algorithm BB step 1) */
 
-/* Launch configuration.  Any field left 0 takes the library default for the
- * call's size.  block: threads per workgroup, a multiple of 64 in [64,1024].
- * grid: workgroups (the total thread count block*grid must not exceed 2^24).
- * unroll: 1, 2, 4 or 8 iterations of the step loop per trip.
- * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable (default is
- * non-temporal streaming stores). */
+/* Launch configuration.  Any field left 0 takes the library default.
+ *
+ * Two layouts write the same values (serial order in memory):
+ *  - rows (default): grid*block threads loop over rows of
+ *    width*grid*block outputs, stepping by a jump multiplier;
+ *  - flat (NN_CFG_FLAT): every 256-thread workgroup writes 512 consecutive
+ *    outputs, two per lane in one 16-byte store, and exits (needs a 16-byte
+ *    aligned output).
+ *
+ * block: threads per workgroup, a multiple of 64 in [64,1024] (rows).
+ * grid: workgroups, block*grid <= 2^24 (rows).
+ * mulmod: an nn_mulmod (both layouts).
+ * unroll: 1, 2, 4 or 8 iterations of the step loop per trip (rows).
+ * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable (default:
+ * non-temporal streaming stores); NN_CFG_ROWS / NN_CFG_FLAT force a layout.
+ * width: outputs per lane and store, 1 (8-byte stores) or 2 (16-byte
+ * stores, needs a 16-byte aligned output) (rows; flat is always 2).
+ * occupancy: 0, or a cap in [2,16] on resident workgroups per compute unit
+ * (flat), enforced through unused dynamic LDS. */
 typedef struct nn_launch_cfg {
     uint32_t block;
     uint32_t grid;
     uint32_t mulmod; /* nn_mulmod */
     uint32_t unroll;
     uint32_t flags;
+    uint32_t width;
+    uint32_t occupancy;
 } nn_launch_cfg;
 #define NN_CFG_TEMPORAL_STORES 1u
+#define NN_CFG_ROWS 2u
+#define NN_CFG_FLAT 4u
 
 /* ---------------------------------------------------------------- host -- */
 

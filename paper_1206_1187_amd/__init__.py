@@ -52,11 +52,21 @@ def init(device=0):
     _native.check(_native.lib().nn_init(int(device)))
 
 
-def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False):
+def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layout=None,
+             occupancy=0):
+    """Launch configuration (include/nn.h, nn_launch_cfg); ``layout`` is
+    None (library default), "flat" or "rows"."""
     if isinstance(mulmod, str):
         mulmod = MULMOD_NAMES[mulmod]
-    return LaunchCfg(int(block), int(grid), int(mulmod), int(unroll),
-                     _native.NN_CFG_TEMPORAL_STORES if temporal else 0)
+    flags = _native.NN_CFG_TEMPORAL_STORES if temporal else 0
+    if layout == "flat":
+        flags |= _native.NN_CFG_FLAT
+    elif layout == "rows":
+        flags |= _native.NN_CFG_ROWS
+    elif layout is not None:
+        raise NNError(_native.NN_EINVAL, "layout must be None, 'flat' or 'rows'")
+    return LaunchCfg(int(block), int(grid), int(mulmod), int(unroll), flags, int(width),
+                     int(occupancy))
 
 
 def default_cfg(kind, count):

@@ -13,6 +13,8 @@ NN_OK, NN_EINVAL, NN_ERANGE, NN_EHIP, NN_ENOMEM, NN_ENODEV = range(6)
 NN_OUT_U64, NN_OUT_F64 = 0, 1
 NN_MULMOD_DEFAULT, NN_MULMOD_FP64, NN_MULMOD_BARRETT, NN_MULMOD_SHOUP, NN_MULMOD_MONTGOMERY = range(5)
 NN_CFG_TEMPORAL_STORES = 1
+NN_CFG_ROWS = 2
+NN_CFG_FLAT = 4
 
 MULMOD_NAMES = {
     "default": NN_MULMOD_DEFAULT,
@@ -40,6 +42,8 @@ class LaunchCfg(ctypes.Structure):
         ("mulmod", ctypes.c_uint32),
         ("unroll", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
+        ("width", ctypes.c_uint32),
+        ("occupancy", ctypes.c_uint32),
     ]
 
     def as_dict(self):

@@ -42,9 +42,12 @@ constexpr int kMaxDevices = 64;
 
 struct DeviceTables {
     bool ready = false;
-    Mult* t_lo = nullptr;  // device, kLoSize entries
-    Mult* t_hi = nullptr;  // device, kHiSize entries
+    Mult* t_lo = nullptr;       // device, kLoSize entries
+    Mult* t_hi = nullptr;       // device, kHiSize entries
+    uint64_t* t_blk = nullptr;  // device, kFlatMaxBlocks entries (flat layout)
     int cus = 0;
+    uint32_t lds_per_cu = 0;
+    uint32_t lds_per_block = 0;
 };
 
 std::mutex g_dev_mutex;
@@ -70,6 +73,21 @@ const std::vector<Mult>& host_tables() {
     return tab;
 }
 
+// Host copy of the flat layout's workgroup multipliers (2^53)^(512 b).
+const std::vector<uint64_t>& host_block_table() {
+    static std::vector<uint64_t> tab = [] {
+        std::vector<uint64_t> t(kFlatMaxBlocks);
+        const uint64_t step = MultPowers::get().pow(kFlatPerBlock);
+        uint64_t p = 1;
+        for (uint64_t b = 0; b < kFlatMaxBlocks; ++b) {
+            t[b] = p;
+            p = h_mulmod(p, step);
+        }
+        return t;
+    }();
+    return tab;
+}
+
 // Set up tables on `dev`, which must be the current device.
 int ensure_device_current(int dev, DeviceTables** out) {
     if (dev < 0 || dev >= kMaxDevices) return fail(NN_ENODEV, "device %d out of range", dev);
@@ -84,17 +102,25 @@ int ensure_device_current(int dev, DeviceTables** out) {
             return fail(NN_ENODEV, "device %d is %s, this library is built for gfx950", dev,
                         prop.gcnArchName);
         const std::vector<Mult>& h = host_tables();
+        const std::vector<uint64_t>& hb = host_block_table();
+        const size_t mult_bytes = h.size() * sizeof(Mult);
+        const size_t blk_bytes = hb.size() * sizeof(uint64_t);
         void* mem = nullptr;
-        e = hipMalloc(&mem, h.size() * sizeof(Mult));
+        e = hipMalloc(&mem, mult_bytes + blk_bytes);
         if (e != hipSuccess) return fail(NN_ENOMEM, "hipMalloc tables: %s", hipGetErrorString(e));
-        e = hipMemcpy(mem, h.data(), h.size() * sizeof(Mult), hipMemcpyHostToDevice);
+        e = hipMemcpy(mem, h.data(), mult_bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((char*)mem + mult_bytes, hb.data(), blk_bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(mem);
             return fail(NN_EHIP, "table upload: %s", hipGetErrorString(e));
         }
         d.t_lo = (Mult*)mem;
         d.t_hi = d.t_lo + kLoSize;
+        d.t_blk = (uint64_t*)((char*)mem + mult_bytes);
         d.cus = prop.multiProcessorCount;
+        d.lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
+        d.lds_per_block = (uint32_t)prop.sharedMemPerBlock;
         d.ready = true;
     }
     *out = &d;
@@ -109,37 +135,79 @@ int current_device(DeviceTables** out) {
 }
 
 struct Resolved {
-    uint32_t block, grid, mulmod, unroll;
-    bool nontemporal;
+    uint32_t block, grid, mulmod, unroll, width, occupancy;
+    bool nontemporal, flat;
+    uint32_t lds;  // dynamic LDS bytes per workgroup that cap residency
 };
 
+// Defaults from the write-bandwidth measurements on MI355X: 16-byte stores
+// per lane from one 256-thread workgroup per compute unit.
 constexpr uint32_t kDefaultBlock = 256;
-constexpr uint32_t kDefaultBlocksPerCU = 8;
+constexpr uint32_t kDefaultBlocksPerCU = 1;
 constexpr uint32_t kDefaultUnroll = 4;
 
-int resolve_cfg(const nn_launch_cfg* cfg, uint64_t count, int cus, Resolved* r) {
-    nn_launch_cfg c = {0, 0, 0, 0, 0};
+// `out` may be NULL (query of the defaults): it is then taken as aligned.
+int resolve_cfg(const nn_launch_cfg* cfg, uint64_t count, const DeviceTables& d,
+                const void* out, Resolved* r) {
+    const int cus = d.cus;
+    nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
+    const bool aligned16 = ((uintptr_t)out % 16) == 0;
+    const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT;
+    if (c.flags & ~known) return fail(NN_EINVAL, "unknown flags 0x%x", c.flags);
+    if ((c.flags & NN_CFG_ROWS) && (c.flags & NN_CFG_FLAT))
+        return fail(NN_EINVAL, "NN_CFG_ROWS and NN_CFG_FLAT are exclusive");
+    r->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
+    r->mulmod = c.mulmod ? c.mulmod : NN_MULMOD_FP64;
+    if (r->mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", r->mulmod);
+    r->occupancy = c.occupancy;
+    r->lds = 0;
+    if (r->occupancy) {
+        if (r->occupancy < 2 || r->occupancy > 16)
+            return fail(NN_EINVAL, "occupancy %u: must be 0 or in [2, 16]", r->occupancy);
+        const uint32_t unit = 512;
+        r->lds = (d.lds_per_cu / (r->occupancy + 1) / unit + 1) * unit;
+        if (r->lds > d.lds_per_block || (uint64_t)r->lds * r->occupancy > d.lds_per_cu)
+            return fail(NN_EINVAL, "occupancy %u not expressible on this device", r->occupancy);
+    }
+    // The row layout is the default: its step loop hides the multiplication
+    // latency that bounds the flat layout (measured on MI355X).
+    r->flat = (c.flags & NN_CFG_FLAT) != 0;
+    if (r->flat) {
+        if (!aligned16)
+            return fail(NN_EINVAL, "the flat layout needs a 16-byte aligned output (got %p)", out);
+        if ((c.block && c.block != kFlatBlock) || c.grid || c.unroll || (c.width && c.width != 2))
+            return fail(NN_EINVAL, "the flat layout has a fixed shape (block 256, width 2)");
+        r->block = kFlatBlock;
+        r->width = 2;
+        r->unroll = 1;
+        const uint64_t chunk = count < kFlatMaxCount ? count : kFlatMaxCount;
+        r->grid = (uint32_t)((chunk + kFlatPerBlock - 1) / kFlatPerBlock);
+        if (!r->grid) r->grid = 1;
+        return NN_OK;
+    }
+    r->width = c.width ? c.width : (aligned16 ? 2u : 1u);
+    if (r->width != 1 && r->width != 2)
+        return fail(NN_EINVAL, "width %u: must be 1 or 2", r->width);
+    if (r->width == 2 && !aligned16)
+        return fail(NN_EINVAL, "width 2 needs a 16-byte aligned output (got %p)", out);
     r->block = c.block ? c.block : kDefaultBlock;
     if (r->block < 64 || r->block > 1024 || r->block % 64)
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", r->block);
     if (c.grid) {
         r->grid = c.grid;
     } else {
-        const uint64_t need = (count + r->block - 1) / r->block;
+        const uint64_t per_block = (uint64_t)r->block * r->width;
+        const uint64_t need = (count + per_block - 1) / per_block;
         const uint64_t cap = (uint64_t)(cus > 0 ? cus : 1) * kDefaultBlocksPerCU;
         r->grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
     }
     if ((uint64_t)r->grid * r->block > kMaxThreads)
         return fail(NN_EINVAL, "grid*block = %llu exceeds %llu threads",
                     (unsigned long long)r->grid * r->block, (unsigned long long)kMaxThreads);
-    r->mulmod = c.mulmod ? c.mulmod : NN_MULMOD_FP64;
-    if (r->mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", r->mulmod);
     r->unroll = c.unroll ? c.unroll : kDefaultUnroll;
     if (r->unroll != 1 && r->unroll != 2 && r->unroll != 4 && r->unroll != 8)
         return fail(NN_EINVAL, "unroll %u: must be 1, 2, 4 or 8", r->unroll);
-    if (c.flags & ~NN_CFG_TEMPORAL_STORES) return fail(NN_EINVAL, "unknown flags 0x%x", c.flags);
-    r->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
     return NN_OK;
 }
 
@@ -194,13 +262,16 @@ int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg* cfg_out) {
     int st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(nullptr, count, d->cus, &r);
+    st = resolve_cfg(nullptr, count, *d, nullptr, &r);
     if (st) return st;
+    cfg_out->width = r.width;
     cfg_out->block = r.block;
     cfg_out->grid = r.grid;
     cfg_out->mulmod = r.mulmod;
     cfg_out->unroll = r.unroll;
-    cfg_out->flags = r.nontemporal ? 0u : NN_CFG_TEMPORAL_STORES;
+    cfg_out->occupancy = r.occupancy;
+    cfg_out->flags = (r.nontemporal ? 0u : NN_CFG_TEMPORAL_STORES) |
+                     (r.flat ? NN_CFG_FLAT : NN_CFG_ROWS);
     return ok();
 }
 
@@ -218,20 +289,43 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
     st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(cfg, count, d->cus, &r);
+    st = resolve_cfg(cfg, count, *d, out_dev, &r);
     if (st) return st;
+
+    if (r.flat) {
+        FlatArgs f;
+        f.M1 = make_mult(kMult);
+        f.t_blk = d->t_blk;
+        f.t_lo = d->t_lo;
+        for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
+            const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
+            f.out = (uint64_t*)out_dev + off;
+            f.count = n;
+            f.base = h_skip(s, off + 1);  // the first output of this chunk
+            hipError_t e = launch_generate_flat((int)r.mulmod, kind, r.nontemporal, r.lds,
+                                                (hipStream_t)stream, f);
+            if (e != hipSuccess)
+                return fail(NN_EHIP, "generate launch: %s", hipGetErrorString(e));
+        }
+        *state = h_skip(s, count);
+        return ok();
+    }
+    if (r.lds)
+        return fail(NN_EINVAL, "occupancy applies to the flat layout only");
 
     GenArgs a;
     a.out = (uint64_t*)out_dev;
     a.T = (uint64_t)r.grid * r.block;
-    a.e_full = count / a.T;
-    a.rem = (uint32_t)(count % a.T);
+    const uint64_t row = a.T * r.width;
+    a.e_full = count / row;
+    a.rem = (uint32_t)(count % row);
     a.base = h_mulmod(s, kMult);
-    a.J = make_mult(MultPowers::get().pow(a.T));
+    a.J = make_mult(MultPowers::get().pow(row));
+    a.M1 = make_mult(kMult);
     a.t_lo = d->t_lo;
     a.t_hi = d->t_hi;
-    hipError_t e = launch_generate((int)r.mulmod, kind, (int)r.unroll, r.nontemporal, r.grid,
-                                   r.block, (hipStream_t)stream, a);
+    hipError_t e = launch_generate((int)r.mulmod, kind, (int)r.width, (int)r.unroll,
+                                   r.nontemporal, r.grid, r.block, (hipStream_t)stream, a);
     if (e != hipSuccess) return fail(NN_EHIP, "generate launch: %s", hipGetErrorString(e));
     *state = h_skip(s, count);
     return ok();
@@ -249,11 +343,23 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(cfg, count, d->cus, &r);
+    st = resolve_cfg(cfg, count, *d, out_dev, &r);
     if (st) return st;
+    if (r.flat) {
+        for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
+            const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
+            hipError_t e = launch_fill_flat(r.nontemporal, r.lds, (hipStream_t)stream,
+                                            (uint64_t*)out_dev + off, n, value);
+            if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
+        }
+        return ok();
+    }
+    if (r.lds) return fail(NN_EINVAL, "occupancy applies to the flat layout only");
     const uint64_t T = (uint64_t)r.grid * r.block;
-    hipError_t e = launch_fill((int)r.unroll, r.nontemporal, r.grid, r.block, (hipStream_t)stream,
-                               (uint64_t*)out_dev, T, count / T, (uint32_t)(count % T), value);
+    const uint64_t row = T * r.width;
+    hipError_t e = launch_fill((int)r.width, (int)r.unroll, r.nontemporal, r.grid, r.block,
+                               (hipStream_t)stream, (uint64_t*)out_dev, T, count / row,
+                               (uint32_t)(count % row), value);
     if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
     return ok();
 }

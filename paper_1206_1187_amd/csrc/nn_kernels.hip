@@ -1,25 +1,30 @@
 // nn_kernels.hip -- gfx950 kernels of the alpha_{2,3} generator.
 //
 // Layout (serial order in memory, coalesced stores): with T = grid*block
-// threads, thread t starts at element t by skip-ahead and then strides by
-// T using the jump multiplier J = (2^53)^T, so a wavefront's 64 lanes always
-// store 64 consecutive elements (512 contiguous bytes).  Eq. 3 applied T
-// times is one multiplication by J (Section 2: any iterate is reachable
-// directly), which keeps memory order equal to sequence order, unlike the
-// paper's strided layout of Section 3.2.
+// threads, each owning W consecutive elements per row, row i covers
+// elements [i*W*T, (i+1)*W*T) and thread t writes elements
+// i*W*T + W*t .. + W-1.  A thread starts at element W*t by skip-ahead and
+// then moves one row per step with the jump multiplier J = (2^53)^(W*T):
+// Eq. 3 applied W*T times is one multiplication by J (Section 2: any iterate
+// is reachable directly).  A wavefront's 64 lanes therefore store 64*W
+// consecutive elements (512 or 1024 contiguous bytes) per row, and memory
+// order equals sequence order, unlike the paper's strided layout of
+// Section 3.2.
 #include <hip/hip_runtime.h>
 
 #include "nn_kernels.hpp"
 
 namespace nn {
 
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
 template <class V>
-__device__ __forceinline__ typename V::S thread_start(uint64_t base, uint64_t t,
+__device__ __forceinline__ typename V::S thread_start(uint64_t base, uint64_t k,
                                                       const Mult* __restrict__ t_lo,
                                                       const Mult* __restrict__ t_hi) {
     typename V::S z = V::load(base);
-    z = V::mul(z, t_hi[t >> kLoBits]);
-    z = V::mul(z, t_lo[t & (kLoSize - 1)]);
+    z = V::mul(z, t_hi[k >> kLoBits]);
+    z = V::mul(z, t_lo[k & (kLoSize - 1)]);
     return z;
 }
 
@@ -31,19 +36,21 @@ __device__ __forceinline__ uint64_t out_bits(typename V::S z) {
         return (uint64_t)__double_as_longlong(V::to_f64(z));
 }
 
-template <bool NT>
-__device__ __forceinline__ void put(uint64_t* p, uint64_t x) {
+template <bool NT, class P, class X>
+__device__ __forceinline__ void put(P* p, X x) {
     if constexpr (NT)
         __builtin_nontemporal_store(x, p);
     else
         *p = x;
 }
 
+// W = 1: one element per thread and row.
 template <class V, int KIND, int UNROLL, bool NT>
-__global__ __launch_bounds__(1024) void k_generate(uint64_t* __restrict__ out, uint64_t T,
-                                                   uint64_t e_full, uint32_t rem, uint64_t base,
-                                                   Mult J, const Mult* __restrict__ t_lo,
-                                                   const Mult* __restrict__ t_hi) {
+__global__ __launch_bounds__(1024) void k_generate1(uint64_t* __restrict__ out, uint64_t T,
+                                                    uint64_t e_full, uint32_t rem, uint64_t base,
+                                                    Mult J, Mult M1,
+                                                    const Mult* __restrict__ t_lo,
+                                                    const Mult* __restrict__ t_hi) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const bool extra = t < rem;
     if (e_full == 0 && !extra) return;
@@ -58,75 +65,223 @@ __global__ __launch_bounds__(1024) void k_generate(uint64_t* __restrict__ out, u
     if (extra) put<NT>(row + t, out_bits<V, KIND>(z));
 }
 
+// W = 2: two consecutive elements per thread and row, one 16-byte store.
+// Requires a 16-byte aligned output.
+template <class V, int KIND, int UNROLL, bool NT>
+__global__ __launch_bounds__(1024) void k_generate2(uint64_t* __restrict__ out, uint64_t T,
+                                                    uint64_t e_full, uint32_t rem, uint64_t base,
+                                                    Mult J, Mult M1,
+                                                    const Mult* __restrict__ t_lo,
+                                                    const Mult* __restrict__ t_hi) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t rem_pairs = rem >> 1;
+    const bool extra_pair = t < rem_pairs;
+    const bool extra_one = (rem & 1u) && t == rem_pairs;
+    if (e_full == 0 && !extra_pair && !extra_one) return;
+    typename V::S za = thread_start<V>(base, 2ull * t, t_lo, t_hi);
+    typename V::S zb = V::mul(za, M1);
+    u64x2* row = reinterpret_cast<u64x2*>(out);
+#pragma unroll UNROLL
+    for (uint64_t i = 0; i < e_full; ++i) {
+        u64x2 v;
+        v.x = out_bits<V, KIND>(za);
+        v.y = out_bits<V, KIND>(zb);
+        put<NT>(row + t, v);
+        row += T;
+        za = V::mul(za, J);
+        zb = V::mul(zb, J);
+    }
+    if (extra_pair) {
+        u64x2 v;
+        v.x = out_bits<V, KIND>(za);
+        v.y = out_bits<V, KIND>(zb);
+        put<NT>(row + t, v);
+    } else if (extra_one) {
+        put<NT>(reinterpret_cast<uint64_t*>(row + t), out_bits<V, KIND>(za));
+    }
+}
+
 // The paper's "Constant" kernel (Section 4.2): the same stores, a fixed value.
-template <int UNROLL, bool NT>
+template <int W, int UNROLL, bool NT>
 __global__ __launch_bounds__(1024) void k_fill(uint64_t* __restrict__ out, uint64_t T,
                                                uint64_t e_full, uint32_t rem, uint64_t value) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t* row = out;
+    if constexpr (W == 1) {
+        uint64_t* row = out;
 #pragma unroll UNROLL
-    for (uint64_t i = 0; i < e_full; ++i) {
-        put<NT>(row + t, value);
-        row += T;
+        for (uint64_t i = 0; i < e_full; ++i) {
+            put<NT>(row + t, value);
+            row += T;
+        }
+        if (t < rem) put<NT>(row + t, value);
+    } else {
+        u64x2 v;
+        v.x = value;
+        v.y = value;
+        u64x2* row = reinterpret_cast<u64x2*>(out);
+#pragma unroll UNROLL
+        for (uint64_t i = 0; i < e_full; ++i) {
+            put<NT>(row + t, v);
+            row += T;
+        }
+        if (t < (rem >> 1))
+            put<NT>(row + t, v);
+        else if ((rem & 1u) && t == (rem >> 1))
+            put<NT>(reinterpret_cast<uint64_t*>(row + t), value);
     }
-    if (t < rem) put<NT>(row + t, value);
 }
 
-template <class V, int KIND, int U, bool NT>
-static hipError_t gen_one(uint32_t grid, uint32_t block, hipStream_t s, const GenArgs& a) {
-    hipLaunchKernelGGL((k_generate<V, KIND, U, NT>), dim3(grid), dim3(block), 0, s, a.out, a.T,
-                       a.e_full, a.rem, a.base, a.J, a.t_lo, a.t_hi);
-    return hipGetLastError();
+// Flat layout (see launch_generate_flat).  The workgroup's start state
+// depends only on uniform values, so its integer product runs on the scalar
+// unit; each lane then needs one multiplication per output.
+template <class V, int KIND, bool NT>
+__global__ __launch_bounds__(kFlatBlock) void k_generate_flat(uint64_t* __restrict__ out,
+                                                              uint64_t count, uint64_t base,
+                                                              Mult M1,
+                                                              const uint64_t* __restrict__ t_blk,
+                                                              const Mult* __restrict__ t_lo) {
+    extern __shared__ char occupancy_cap[];  // dynamic LDS only limits residency
+    (void)occupancy_cap;
+    const uint64_t b = blockIdx.x;
+    const uint64_t z_blk = mm_barrett(base, t_blk[b]);
+    const uint32_t l = threadIdx.x;
+    const uint64_t k = (uint64_t)kFlatPerBlock * b + 2u * l;
+    if (k >= count) return;
+    const typename V::S za = V::mul(V::load(z_blk), t_lo[2u * l]);
+    if (k + 1 < count) {
+        const typename V::S zb = V::mul(za, M1);
+        u64x2 v;
+        v.x = out_bits<V, KIND>(za);
+        v.y = out_bits<V, KIND>(zb);
+        put<NT>(reinterpret_cast<u64x2*>(out + k), v);
+    } else {
+        put<NT>(out + k, out_bits<V, KIND>(za));
+    }
+}
+
+template <bool NT>
+__global__ __launch_bounds__(kFlatBlock) void k_fill_flat(uint64_t* __restrict__ out,
+                                                          uint64_t count, uint64_t value) {
+    extern __shared__ char occupancy_cap[];
+    (void)occupancy_cap;
+    const uint64_t k = (uint64_t)kFlatPerBlock * blockIdx.x + 2u * threadIdx.x;
+    if (k >= count) return;
+    if (k + 1 < count) {
+        u64x2 v;
+        v.x = value;
+        v.y = value;
+        put<NT>(reinterpret_cast<u64x2*>(out + k), v);
+    } else {
+        put<NT>(out + k, value);
+    }
 }
 
 template <class V, int KIND, bool NT>
-static hipError_t gen_u(int unroll, uint32_t grid, uint32_t block, hipStream_t s,
-                        const GenArgs& a) {
-    switch (unroll) {
-        case 1: return gen_one<V, KIND, 1, NT>(grid, block, s, a);
-        case 2: return gen_one<V, KIND, 2, NT>(grid, block, s, a);
-        case 4: return gen_one<V, KIND, 4, NT>(grid, block, s, a);
-        case 8: return gen_one<V, KIND, 8, NT>(grid, block, s, a);
-        default: return hipErrorInvalidValue;
-    }
+static hipError_t flat_one(uint32_t lds, hipStream_t s, const FlatArgs& a) {
+    const uint32_t grid = (uint32_t)((a.count + kFlatPerBlock - 1) / kFlatPerBlock);
+    hipLaunchKernelGGL((k_generate_flat<V, KIND, NT>), dim3(grid), dim3(kFlatBlock), lds, s,
+                       a.out, a.count, a.base, a.M1, a.t_blk, a.t_lo);
+    return hipGetLastError();
 }
 
 template <class V>
-static hipError_t gen_v(int kind, int unroll, bool nt, uint32_t grid, uint32_t block,
-                        hipStream_t s, const GenArgs& a) {
-    if (kind == 0)
-        return nt ? gen_u<V, 0, true>(unroll, grid, block, s, a)
-                  : gen_u<V, 0, false>(unroll, grid, block, s, a);
-    return nt ? gen_u<V, 1, true>(unroll, grid, block, s, a)
-              : gen_u<V, 1, false>(unroll, grid, block, s, a);
+static hipError_t flat_v(int kind, bool nt, uint32_t lds, hipStream_t s, const FlatArgs& a) {
+    if (kind == 0) return nt ? flat_one<V, 0, true>(lds, s, a) : flat_one<V, 0, false>(lds, s, a);
+    return nt ? flat_one<V, 1, true>(lds, s, a) : flat_one<V, 1, false>(lds, s, a);
 }
 
-hipError_t launch_generate(int mulmod, int kind, int unroll, bool nt, uint32_t grid,
-                           uint32_t block, hipStream_t s, const GenArgs& a) {
+hipError_t launch_generate_flat(int mulmod, int kind, bool nt, uint32_t lds, hipStream_t s,
+                                const FlatArgs& a) {
     switch (mulmod) {
-        case 1: return gen_v<VarFP64>(kind, unroll, nt, grid, block, s, a);
-        case 2: return gen_v<VarBarrett>(kind, unroll, nt, grid, block, s, a);
-        case 3: return gen_v<VarShoup>(kind, unroll, nt, grid, block, s, a);
-        case 4: return gen_v<VarMontgomery>(kind, unroll, nt, grid, block, s, a);
+        case 1: return flat_v<VarFP64>(kind, nt, lds, s, a);
+        case 2: return flat_v<VarBarrett>(kind, nt, lds, s, a);
+        case 3: return flat_v<VarShoup>(kind, nt, lds, s, a);
+        case 4: return flat_v<VarMontgomery>(kind, nt, lds, s, a);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int U, bool NT>
+hipError_t launch_fill_flat(bool nt, uint32_t lds, hipStream_t s, uint64_t* out, uint64_t count,
+                            uint64_t value) {
+    const uint32_t grid = (uint32_t)((count + kFlatPerBlock - 1) / kFlatPerBlock);
+    if (nt)
+        hipLaunchKernelGGL((k_fill_flat<true>), dim3(grid), dim3(kFlatBlock), lds, s, out, count,
+                           value);
+    else
+        hipLaunchKernelGGL((k_fill_flat<false>), dim3(grid), dim3(kFlatBlock), lds, s, out,
+                           count, value);
+    return hipGetLastError();
+}
+
+template <class V, int KIND, int W, int U, bool NT>
+static hipError_t gen_one(uint32_t grid, uint32_t block, hipStream_t s, const GenArgs& a) {
+    if constexpr (W == 1)
+        hipLaunchKernelGGL((k_generate1<V, KIND, U, NT>), dim3(grid), dim3(block), 0, s, a.out,
+                           a.T, a.e_full, a.rem, a.base, a.J, a.M1, a.t_lo, a.t_hi);
+    else
+        hipLaunchKernelGGL((k_generate2<V, KIND, U, NT>), dim3(grid), dim3(block), 0, s, a.out,
+                           a.T, a.e_full, a.rem, a.base, a.J, a.M1, a.t_lo, a.t_hi);
+    return hipGetLastError();
+}
+
+template <class V, int KIND, int W, bool NT>
+static hipError_t gen_u(int unroll, uint32_t grid, uint32_t block, hipStream_t s,
+                        const GenArgs& a) {
+    switch (unroll) {
+        case 1: return gen_one<V, KIND, W, 1, NT>(grid, block, s, a);
+        case 2: return gen_one<V, KIND, W, 2, NT>(grid, block, s, a);
+        case 4: return gen_one<V, KIND, W, 4, NT>(grid, block, s, a);
+        case 8: return gen_one<V, KIND, W, 8, NT>(grid, block, s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class V, int KIND>
+static hipError_t gen_k(int width, int unroll, bool nt, uint32_t grid, uint32_t block,
+                        hipStream_t s, const GenArgs& a) {
+    if (width == 1)
+        return nt ? gen_u<V, KIND, 1, true>(unroll, grid, block, s, a)
+                  : gen_u<V, KIND, 1, false>(unroll, grid, block, s, a);
+    if (width == 2)
+        return nt ? gen_u<V, KIND, 2, true>(unroll, grid, block, s, a)
+                  : gen_u<V, KIND, 2, false>(unroll, grid, block, s, a);
+    return hipErrorInvalidValue;
+}
+
+template <class V>
+static hipError_t gen_v(int kind, int width, int unroll, bool nt, uint32_t grid, uint32_t block,
+                        hipStream_t s, const GenArgs& a) {
+    return kind == 0 ? gen_k<V, 0>(width, unroll, nt, grid, block, s, a)
+                     : gen_k<V, 1>(width, unroll, nt, grid, block, s, a);
+}
+
+hipError_t launch_generate(int mulmod, int kind, int width, int unroll, bool nt, uint32_t grid,
+                           uint32_t block, hipStream_t s, const GenArgs& a) {
+    switch (mulmod) {
+        case 1: return gen_v<VarFP64>(kind, width, unroll, nt, grid, block, s, a);
+        case 2: return gen_v<VarBarrett>(kind, width, unroll, nt, grid, block, s, a);
+        case 3: return gen_v<VarShoup>(kind, width, unroll, nt, grid, block, s, a);
+        case 4: return gen_v<VarMontgomery>(kind, width, unroll, nt, grid, block, s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int W, int U, bool NT>
 static hipError_t fill_one(uint32_t grid, uint32_t block, hipStream_t s, uint64_t* out,
                            uint64_t T, uint64_t e_full, uint32_t rem, uint64_t value) {
-    hipLaunchKernelGGL((k_fill<U, NT>), dim3(grid), dim3(block), 0, s, out, T, e_full, rem,
+    hipLaunchKernelGGL((k_fill<W, U, NT>), dim3(grid), dim3(block), 0, s, out, T, e_full, rem,
                        value);
     return hipGetLastError();
 }
 
-hipError_t launch_fill(int unroll, bool nt, uint32_t grid, uint32_t block, hipStream_t s,
-                       uint64_t* out, uint64_t T, uint64_t e_full, uint32_t rem,
-                       uint64_t value) {
-#define NN_FILL_CASE(U)                                                          \
-    case U:                                                                      \
-        return nt ? fill_one<U, true>(grid, block, s, out, T, e_full, rem, value) \
-                  : fill_one<U, false>(grid, block, s, out, T, e_full, rem, value);
+template <int W>
+static hipError_t fill_w(int unroll, bool nt, uint32_t grid, uint32_t block, hipStream_t s,
+                         uint64_t* out, uint64_t T, uint64_t e_full, uint32_t rem,
+                         uint64_t value) {
+#define NN_FILL_CASE(U)                                                              \
+    case U:                                                                          \
+        return nt ? fill_one<W, U, true>(grid, block, s, out, T, e_full, rem, value) \
+                  : fill_one<W, U, false>(grid, block, s, out, T, e_full, rem, value);
     switch (unroll) {
         NN_FILL_CASE(1)
         NN_FILL_CASE(2)
@@ -135,6 +290,14 @@ hipError_t launch_fill(int unroll, bool nt, uint32_t grid, uint32_t block, hipSt
         default: return hipErrorInvalidValue;
     }
 #undef NN_FILL_CASE
+}
+
+hipError_t launch_fill(int width, int unroll, bool nt, uint32_t grid, uint32_t block,
+                       hipStream_t s, uint64_t* out, uint64_t T, uint64_t e_full, uint32_t rem,
+                       uint64_t value) {
+    if (width == 1) return fill_w<1>(unroll, nt, grid, block, s, out, T, e_full, rem, value);
+    if (width == 2) return fill_w<2>(unroll, nt, grid, block, s, out, T, e_full, rem, value);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace nn

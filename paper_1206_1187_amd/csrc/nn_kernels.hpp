@@ -9,16 +9,20 @@
 namespace nn {
 
 // Skip-ahead tables on the device: t_lo[l] = 2^(53 l) for l < 1024 and
-// t_hi[j] = 2^(53 * 1024 j) for j < 16384 (mod 3^33), so the multiplier of
-// any offset t < 2^24 is t_hi[t >> 10] * t_lo[t & 1023].
+// t_hi[j] = 2^(53 * 1024 j) for j < 32768 (mod 3^33), so the multiplier of
+// any offset k < 2^25 is t_hi[k >> 10] * t_lo[k & 1023].
 constexpr uint32_t kLoBits = 10;
 constexpr uint32_t kLoSize = 1u << kLoBits;
-constexpr uint32_t kHiSize = 1u << 14;
-constexpr uint64_t kMaxThreads = (uint64_t)kLoSize * kHiSize;  // 2^24
+constexpr uint32_t kHiSize = 1u << 15;
+constexpr uint64_t kMaxOffset = (uint64_t)kLoSize * kHiSize;  // 2^25
+constexpr uint64_t kMaxThreads = kMaxOffset / 2;             // 2^24
 
-// Plain generation: thread t of T = grid*block emits elements t + i*T for
-// i < e_full, plus element t + e_full*T when t < rem (count = e_full*T+rem).
-// `base` is state * 2^53 (the first output of the call), J = (2^53)^T.
+// Plain generation.  Each of the T = grid*block threads owns W consecutive
+// elements per row (W = 1: 8-byte stores, W = 2: 16-byte stores); row i
+// covers elements [i*W*T, (i+1)*W*T).  count = e_full*W*T + rem with
+// rem < W*T: the last, partial row holds `rem` elements.  `base` is
+// state * 2^53 (the first output of the call), J = (2^53)^(W*T) and
+// M1 = 2^53 with its reduction data.
 struct GenArgs {
     uint64_t* out;
     uint64_t T;
@@ -26,14 +30,39 @@ struct GenArgs {
     uint32_t rem;
     uint64_t base;
     Mult J;
+    Mult M1;
     const Mult* t_lo;
     const Mult* t_hi;
 };
 
-hipError_t launch_generate(int mulmod, int kind, int unroll, bool nontemporal, uint32_t grid,
-                           uint32_t block, hipStream_t stream, const GenArgs& a);
+hipError_t launch_generate(int mulmod, int kind, int width, int unroll, bool nontemporal,
+                           uint32_t grid, uint32_t block, hipStream_t stream, const GenArgs& a);
 
-hipError_t launch_fill(int unroll, bool nontemporal, uint32_t grid, uint32_t block,
+// Flat layout: workgroup b of 256 threads writes elements
+// [512 b, 512 b + 512) of the launch, two consecutive ones per lane in one
+// 16-byte store, and exits; every workgroup starts from
+// base * t_blk[b] with t_blk[b] = (2^53)^(512 b), b < kFlatMaxBlocks.
+constexpr uint32_t kFlatBlock = 256;
+constexpr uint32_t kFlatPerBlock = 2 * kFlatBlock;
+constexpr uint64_t kFlatMaxBlocks = 1ull << 21;
+constexpr uint64_t kFlatMaxCount = kFlatMaxBlocks * kFlatPerBlock;  // 2^30 per launch
+
+struct FlatArgs {
+    uint64_t* out;   // 16-byte aligned
+    uint64_t count;  // <= kFlatMaxCount
+    uint64_t base;
+    Mult M1;
+    const uint64_t* t_blk;
+    const Mult* t_lo;
+};
+
+// lds_bytes > 0 caps the resident workgroups per compute unit.
+hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, uint32_t lds_bytes,
+                                hipStream_t stream, const FlatArgs& a);
+hipError_t launch_fill_flat(bool nontemporal, uint32_t lds_bytes, hipStream_t stream,
+                            uint64_t* out, uint64_t count, uint64_t value);
+
+hipError_t launch_fill(int width, int unroll, bool nontemporal, uint32_t grid, uint32_t block,
                        hipStream_t stream, uint64_t* out, uint64_t T, uint64_t e_full,
                        uint32_t rem, uint64_t value);
 

@@ -84,13 +84,15 @@ def test_plain_single_bit_exact(kind):
 def test_every_reduction_bit_exact(variant, kind):
     z0 = orc.seed(wl.plain_bulk().index)
     count = 3 * 65536 + 4099  # several rows of a 64K-thread grid plus a ragged tail
+    ref, zr = orc.gen(z0, count, kind, threads=0)
     for block, grid, unroll in [(256, 256, 4), (64, 7, 1), (1024, 3, 8), (128, 1001, 2)]:
-        cfg = nn.make_cfg(block=block, grid=grid, mulmod=variant, unroll=unroll)
-        _say("reduction", variant, kind, block, grid, unroll)
-        got, zn = _gen_guarded(z0, count, kind, cfg=cfg)
-        ref, zr = orc.gen(z0, count, kind, threads=0)
-        assert zn == zr
-        assert np.array_equal(got, ref.view(np.uint64)), (variant, kind, block, grid, unroll)
+        for width in (1, 2):
+            cfg = nn.make_cfg(block=block, grid=grid, mulmod=variant, unroll=unroll, width=width)
+            _say("reduction", variant, kind, block, grid, unroll, width)
+            got, zn = _gen_guarded(z0, count, kind, cfg=cfg)
+            assert zn == zr
+            assert np.array_equal(got, ref.view(np.uint64)), (variant, kind, block, grid,
+                                                              unroll, width)
 
 
 @pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
@@ -101,14 +103,68 @@ def test_thread_count_independence(block):
     ref_all = ref_all.view(np.uint64)
     for grid in (1, 3, 64, 257):
         T = grid * block
-        for count in sorted({1, 2, T - 1, T, T + 1, 3 * T + 17, 99991}):
-            if count < 1 or count > ref_all.size:
-                continue
-            for unroll in (1, 8):
-                cfg = nn.make_cfg(block=block, grid=grid, unroll=unroll)
-                got, zn = _gen_guarded(z0, count, "f64", cfg=cfg, guard=256)
-                assert np.array_equal(got, ref_all[:count]), (block, grid, count, unroll)
+        for width in (1, 2):
+            row = T * width
+            for count in sorted({1, 2, 3, row - 1, row, row + 1, 3 * row + 17, 99991}):
+                if count < 1 or count > ref_all.size:
+                    continue
+                for unroll in (1, 8):
+                    cfg = nn.make_cfg(block=block, grid=grid, unroll=unroll, width=width)
+                    got, zn = _gen_guarded(z0, count, "f64", cfg=cfg, guard=256)
+                    assert np.array_equal(got, ref_all[:count]), (block, grid, count, unroll,
+                                                                  width)
+                    assert zn == orc.skip(z0, count)
+
+
+def test_output_alignment():
+    """An output that is only 8-byte aligned takes 8-byte stores by default;
+    asking for 16-byte stores there is an error and writes nothing."""
+    z0 = orc.seed(wl.INDEX_MIN + 99)
+    ref, zr = orc.gen(z0, 50_001, "u64", threads=0)
+    got, zn = _gen_guarded(z0, 50_001, "u64", guard=4097)
+    assert np.array_equal(got, ref) and zn == zr
+    buf = _sentinel_buffer(50_001 + 2)
+    with pytest.raises(nn.NNError):
+        nn.generate_into(z0, buf[1:50_002].view(torch.uint64), cfg=nn.make_cfg(width=2))
+    torch.cuda.synchronize()
+    assert (_bits(buf) == SENTINEL).all()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_flat_layout_bit_exact(variant):
+    """The flat layout (one 512-output workgroup each) for every reduction,
+    both kinds, ragged tails and residency caps."""
+    z0 = orc.seed(wl.INDEX_MIN + 31337)
+    ref_u, _ = orc.gen(z0, 300_000, "u64", threads=0)
+    ref_f, _ = orc.gen(z0, 300_000, "f64", threads=0)
+    for count in (1, 2, 3, 511, 512, 513, 1023, 1024, 1025, 3 * 512 + 1, 99_991, 300_000):
+        for occ in (0, 3):
+            cfg = nn.make_cfg(mulmod=variant, layout="flat", occupancy=occ)
+            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=512)
+                assert np.array_equal(got, ref.view(np.uint64)[:count]), (variant, count, occ, kind)
                 assert zn == orc.skip(z0, count)
+    # temporal stores write the same values
+    got, _ = _gen_guarded(z0, 99_991, "f64", cfg=nn.make_cfg(mulmod=variant, layout="flat",
+                                                            temporal=True))
+    assert np.array_equal(got, ref_f.view(np.uint64)[:99_991])
+
+
+def test_config_validation():
+    z0 = orc.seed(wl.INDEX_MIN)
+    out = torch.empty(4096, dtype=torch.float64, device="cuda")
+    bad = [nn.make_cfg(layout="flat", block=512), nn.make_cfg(layout="flat", width=1),
+           nn.make_cfg(block=100), nn.make_cfg(block=2048), nn.make_cfg(unroll=3),
+           nn.make_cfg(width=3), nn.make_cfg(occupancy=1), nn.make_cfg(occupancy=17),
+           nn.make_cfg(layout="rows", occupancy=4), nn.make_cfg(mulmod=9),
+           nn.make_cfg(grid=1 << 20, block=1024)]
+    for cfg in bad:
+        with pytest.raises(nn.NNError):
+            nn.generate_into(z0, out, cfg=cfg)
+    with pytest.raises(nn.NNError):
+        nn.generate_into(z0, out[1:].view(torch.float64), cfg=nn.make_cfg(layout="flat"))
+    d = nn.default_cfg("f64", 1 << 30)
+    assert d.flags & 2 and d.width == 2 and d.block == 256
 
 
 def test_chained_calls_concatenate():
@@ -161,8 +217,9 @@ def test_skip_stress_sample():
 
 
 def test_fill_ceiling_kernel_pattern():
-    for block, grid, count in [(256, 2048, 1 << 20), (64, 5, 100_003)]:
-        cfg = nn.make_cfg(block=block, grid=grid)
+    for block, grid, count, width in [(256, 2048, 1 << 20, 1), (64, 5, 100_003, 1),
+                                      (256, 256, 1 << 20, 2), (64, 5, 100_003, 2)]:
+        cfg = nn.make_cfg(block=block, grid=grid, width=width)
         buf = _sentinel_buffer(count + 512)
         nn.fill(buf[256:256 + count], 0x3FF0000000000001, cfg=cfg)
         torch.cuda.synchronize()
@@ -193,3 +250,20 @@ def test_plain_bulk_full_size_bit_exact():
             assert bad.size == 0, (kind, c, bad[:4])
         del out, flat
         torch.cuda.empty_cache()
+
+
+def test_flat_chunk_boundary_beyond_one_launch():
+    """Counts above one flat launch (2^30 outputs) are split into several
+    launches; check the outputs on both sides of every split and the tail."""
+    z0 = orc.seed(wl.plain_bulk().index + 5)
+    count = (1 << 30) + 4099
+    out, zn = nn.generate(z0, count, "f64")
+    torch.cuda.synchronize()
+    assert zn == orc.skip(z0, count)
+    flat = out.view(torch.int64)
+    for start, n in ((0, 8192), ((1 << 30) - 8192, 8192 + 4099), (123_456_789, 4096)):
+        ref, _ = orc.gen(orc.skip(z0, start), n, "f64", threads=0)
+        got = flat[start:start + n].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref.view(np.uint64)), start
+    del out, flat
+    torch.cuda.empty_cache()
