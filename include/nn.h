@@ -84,7 +84,9 @@ typedef enum nn_mulmod {
  * width: outputs per lane and store, 1 (8-byte stores) or 2 (16-byte
  * stores, needs a 16-byte aligned output) (rows; flat is always 2).
  * occupancy: 0, or a cap in [2,16] on resident workgroups per compute unit
- * (flat), enforced through unused dynamic LDS. */
+ * (flat), enforced through unused dynamic LDS.
+ * ilp: rows each thread keeps in flight, 1, 2 or 4 (rows with width 2):
+ * 2*ilp independent multiplication chains per lane. */
 typedef struct nn_launch_cfg {
     uint32_t block;
     uint32_t grid;
@@ -93,6 +95,7 @@ typedef struct nn_launch_cfg {
     uint32_t flags;
     uint32_t width;
     uint32_t occupancy;
+    uint32_t ilp;
 } nn_launch_cfg;
 #define NN_CFG_TEMPORAL_STORES 1u
 #define NN_CFG_ROWS 2u
@@ -146,8 +149,9 @@ int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg *cfg_out);
 
 /* nn_fill -- the paper's "Constant" measurement kernel (Section 4.2,
  * Table 1): writes `value` to out_dev[0..count) with exactly the store
- * pattern nn_generate_ex uses for the same cfg, giving the write-bandwidth
- * ceiling of that pattern.  Same pointer rules and errors as nn_generate. */
+ * pattern nn_generate_ex uses for the same cfg and NN_OUT_F64 (fields left
+ * 0 resolve as for F64 output), giving the write-bandwidth ceiling of that
+ * pattern.  Same pointer rules and errors as nn_generate. */
 int nn_fill(uint64_t count, void *out_dev, uint64_t value, void *stream,
             const nn_launch_cfg *cfg);
 

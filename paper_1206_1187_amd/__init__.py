@@ -53,7 +53,7 @@ def init(device=0):
 
 
 def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layout=None,
-             occupancy=0):
+             occupancy=0, ilp=0):
     """Launch configuration (include/nn.h, nn_launch_cfg); ``layout`` is
     None (library default), "flat" or "rows"."""
     if isinstance(mulmod, str):
@@ -66,7 +66,7 @@ def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layou
     elif layout is not None:
         raise NNError(_native.NN_EINVAL, "layout must be None, 'flat' or 'rows'")
     return LaunchCfg(int(block), int(grid), int(mulmod), int(unroll), flags, int(width),
-                     int(occupancy))
+                     int(occupancy), int(ilp))
 
 
 def default_cfg(kind, count):

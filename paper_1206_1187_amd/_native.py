@@ -44,6 +44,7 @@ class LaunchCfg(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("width", ctypes.c_uint32),
         ("occupancy", ctypes.c_uint32),
+        ("ilp", ctypes.c_uint32),
     ]
 
     def as_dict(self):

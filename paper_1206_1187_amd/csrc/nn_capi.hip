@@ -135,22 +135,32 @@ int current_device(DeviceTables** out) {
 }
 
 struct Resolved {
-    uint32_t block, grid, mulmod, unroll, width, occupancy;
+    uint32_t block, grid, mulmod, unroll, width, occupancy, ilp;
     bool nontemporal, flat;
     uint32_t lds;  // dynamic LDS bytes per workgroup that cap residency
 };
 
-// Defaults from the write-bandwidth measurements on MI355X: 16-byte stores
-// per lane from one 256-thread workgroup per compute unit.
+// Defaults from launch-shape sweeps on MI355X (256 CUs, bulk outputs of
+// 2^28..2^30): 16-byte stores per lane from 256-thread workgroups on a
+// fraction of the CUs (fewer concurrent writers keep the HBM write stream
+// closer to sequential).  F64 output: the FP64 reduction with two rows in
+// flight on CUs/2 workgroups; U64 output: Shoup's reduction (integer state,
+// no conversion) with one row on 3*CUs/4 workgroups.
+struct KindDefaults {
+    uint32_t mulmod, grid_num, grid_den, unroll, ilp;
+};
 constexpr uint32_t kDefaultBlock = 256;
-constexpr uint32_t kDefaultBlocksPerCU = 1;
-constexpr uint32_t kDefaultUnroll = 4;
+constexpr KindDefaults kDefaults[2] = {
+    {NN_MULMOD_SHOUP, 3, 4, 2, 1},  // NN_OUT_U64
+    {NN_MULMOD_FP64, 1, 2, 4, 2},   // NN_OUT_F64
+};
 
 // `out` may be NULL (query of the defaults): it is then taken as aligned.
-int resolve_cfg(const nn_launch_cfg* cfg, uint64_t count, const DeviceTables& d,
+int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const DeviceTables& d,
                 const void* out, Resolved* r) {
     const int cus = d.cus;
-    nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0};
+    const KindDefaults& kd = kDefaults[kind == NN_OUT_F64 ? 1 : 0];
+    nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
     const bool aligned16 = ((uintptr_t)out % 16) == 0;
     const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT;
@@ -158,7 +168,7 @@ int resolve_cfg(const nn_launch_cfg* cfg, uint64_t count, const DeviceTables& d,
     if ((c.flags & NN_CFG_ROWS) && (c.flags & NN_CFG_FLAT))
         return fail(NN_EINVAL, "NN_CFG_ROWS and NN_CFG_FLAT are exclusive");
     r->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
-    r->mulmod = c.mulmod ? c.mulmod : NN_MULMOD_FP64;
+    r->mulmod = c.mulmod ? c.mulmod : kd.mulmod;
     if (r->mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", r->mulmod);
     r->occupancy = c.occupancy;
     r->lds = 0;
@@ -178,9 +188,11 @@ int resolve_cfg(const nn_launch_cfg* cfg, uint64_t count, const DeviceTables& d,
             return fail(NN_EINVAL, "the flat layout needs a 16-byte aligned output (got %p)", out);
         if ((c.block && c.block != kFlatBlock) || c.grid || c.unroll || (c.width && c.width != 2))
             return fail(NN_EINVAL, "the flat layout has a fixed shape (block 256, width 2)");
+        if (c.ilp > 1) return fail(NN_EINVAL, "ilp applies to the row layout only");
         r->block = kFlatBlock;
         r->width = 2;
         r->unroll = 1;
+        r->ilp = 1;
         const uint64_t chunk = count < kFlatMaxCount ? count : kFlatMaxCount;
         r->grid = (uint32_t)((chunk + kFlatPerBlock - 1) / kFlatPerBlock);
         if (!r->grid) r->grid = 1;
@@ -199,15 +211,20 @@ int resolve_cfg(const nn_launch_cfg* cfg, uint64_t count, const DeviceTables& d,
     } else {
         const uint64_t per_block = (uint64_t)r->block * r->width;
         const uint64_t need = (count + per_block - 1) / per_block;
-        const uint64_t cap = (uint64_t)(cus > 0 ? cus : 1) * kDefaultBlocksPerCU;
+        uint64_t cap = (uint64_t)(cus > 0 ? cus : 1) * kd.grid_num / kd.grid_den;
+        if (cap == 0) cap = 1;
         r->grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
     }
     if ((uint64_t)r->grid * r->block > kMaxThreads)
         return fail(NN_EINVAL, "grid*block = %llu exceeds %llu threads",
                     (unsigned long long)r->grid * r->block, (unsigned long long)kMaxThreads);
-    r->unroll = c.unroll ? c.unroll : kDefaultUnroll;
+    r->unroll = c.unroll ? c.unroll : kd.unroll;
     if (r->unroll != 1 && r->unroll != 2 && r->unroll != 4 && r->unroll != 8)
         return fail(NN_EINVAL, "unroll %u: must be 1, 2, 4 or 8", r->unroll);
+    r->ilp = c.ilp ? c.ilp : (r->width == 2 ? kd.ilp : 1u);
+    if (r->ilp != 1 && r->ilp != 2 && r->ilp != 4)
+        return fail(NN_EINVAL, "ilp %u: must be 1, 2 or 4", r->ilp);
+    if (r->ilp > 1 && r->width != 2) return fail(NN_EINVAL, "ilp > 1 needs width 2");
     return NN_OK;
 }
 
@@ -262,7 +279,7 @@ int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg* cfg_out) {
     int st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(nullptr, count, *d, nullptr, &r);
+    st = resolve_cfg(nullptr, kind, count, *d, nullptr, &r);
     if (st) return st;
     cfg_out->width = r.width;
     cfg_out->block = r.block;
@@ -270,6 +287,7 @@ int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg* cfg_out) {
     cfg_out->mulmod = r.mulmod;
     cfg_out->unroll = r.unroll;
     cfg_out->occupancy = r.occupancy;
+    cfg_out->ilp = r.ilp;
     cfg_out->flags = (r.nontemporal ? 0u : NN_CFG_TEMPORAL_STORES) |
                      (r.flat ? NN_CFG_FLAT : NN_CFG_ROWS);
     return ok();
@@ -289,7 +307,7 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
     st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(cfg, count, *d, out_dev, &r);
+    st = resolve_cfg(cfg, kind, count, *d, out_dev, &r);
     if (st) return st;
 
     if (r.flat) {
@@ -320,11 +338,13 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
     a.e_full = count / row;
     a.rem = (uint32_t)(count % row);
     a.base = h_mulmod(s, kMult);
-    a.J = make_mult(MultPowers::get().pow(row));
+    const uint64_t jump = MultPowers::get().pow(row);
+    a.J = make_mult(jump);
     a.M1 = make_mult(kMult);
+    a.JI = make_mult(MultPowers::get().pow(row * r.ilp));
     a.t_lo = d->t_lo;
     a.t_hi = d->t_hi;
-    hipError_t e = launch_generate((int)r.mulmod, kind, (int)r.width, (int)r.unroll,
+    hipError_t e = launch_generate((int)r.mulmod, kind, (int)r.width, (int)r.unroll, (int)r.ilp,
                                    r.nontemporal, r.grid, r.block, (hipStream_t)stream, a);
     if (e != hipSuccess) return fail(NN_EHIP, "generate launch: %s", hipGetErrorString(e));
     *state = h_skip(s, count);
@@ -343,7 +363,7 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(cfg, count, *d, out_dev, &r);
+    st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r);
     if (st) return st;
     if (r.flat) {
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {

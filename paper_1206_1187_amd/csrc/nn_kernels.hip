@@ -101,6 +101,73 @@ __global__ __launch_bounds__(1024) void k_generate2(uint64_t* __restrict__ out, 
     }
 }
 
+// W = 2 with IL rows in flight per thread: 2*IL independent multiplication
+// chains per lane, each advanced by JI = J^IL per trip.
+template <class V, int KIND, int UNROLL, bool NT, int IL>
+__global__ __launch_bounds__(1024) void k_generate2_ilp(uint64_t* __restrict__ out, uint64_t T,
+                                                        uint64_t e_full, uint32_t rem,
+                                                        uint64_t base, Mult J, Mult M1, Mult JI,
+                                                        const Mult* __restrict__ t_lo,
+                                                        const Mult* __restrict__ t_hi) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t rem_pairs = rem >> 1;
+    const bool extra_pair = t < rem_pairs;
+    const bool extra_one = (rem & 1u) && t == rem_pairs;
+    if (e_full == 0 && !extra_pair && !extra_one) return;
+    typename V::S za[IL], zb[IL];
+    za[0] = thread_start<V>(base, 2ull * t, t_lo, t_hi);
+    zb[0] = V::mul(za[0], M1);
+#pragma unroll
+    for (int r = 1; r < IL; ++r) {
+        za[r] = V::mul(za[r - 1], J);
+        zb[r] = V::mul(zb[r - 1], J);
+    }
+    u64x2* row = reinterpret_cast<u64x2*>(out);
+    uint64_t i = 0;
+#pragma unroll UNROLL
+    for (; i + IL <= e_full; i += IL) {
+#pragma unroll
+        for (int r = 0; r < IL; ++r) {
+            u64x2 v;
+            v.x = out_bits<V, KIND>(za[r]);
+            v.y = out_bits<V, KIND>(zb[r]);
+            put<NT>(row + r * T + t, v);
+        }
+        row += IL * T;
+#pragma unroll
+        for (int r = 0; r < IL; ++r) {
+            za[r] = V::mul(za[r], JI);
+            zb[r] = V::mul(zb[r], JI);
+        }
+    }
+    // Fewer than IL full rows remain, then the partial row; za[r], zb[r]
+    // hold rows i + r.
+    const uint32_t left = (uint32_t)(e_full - i);
+    typename V::S pa = za[0], pb = zb[0];
+#pragma unroll
+    for (int r = 0; r < IL; ++r) {
+        if ((uint32_t)r < left) {
+            u64x2 v;
+            v.x = out_bits<V, KIND>(za[r]);
+            v.y = out_bits<V, KIND>(zb[r]);
+            put<NT>(row + r * T + t, v);
+        }
+        if ((uint32_t)r == left) {
+            pa = za[r];
+            pb = zb[r];
+        }
+    }
+    row += left * T;
+    if (extra_pair) {
+        u64x2 v;
+        v.x = out_bits<V, KIND>(pa);
+        v.y = out_bits<V, KIND>(pb);
+        put<NT>(row + t, v);
+    } else if (extra_one) {
+        put<NT>(reinterpret_cast<uint64_t*>(row + t), out_bits<V, KIND>(pa));
+    }
+}
+
 // The paper's "Constant" kernel (Section 4.2): the same stores, a fixed value.
 template <int W, int UNROLL, bool NT>
 __global__ __launch_bounds__(1024) void k_fill(uint64_t* __restrict__ out, uint64_t T,
@@ -213,55 +280,65 @@ hipError_t launch_fill_flat(bool nt, uint32_t lds, hipStream_t s, uint64_t* out,
     return hipGetLastError();
 }
 
-template <class V, int KIND, int W, int U, bool NT>
+// Kernel selector: W = 1, W = 2, or W = 2 with IL = 2 or 4 rows in flight.
+template <class V, int KIND, int W, int IL, int U, bool NT>
 static hipError_t gen_one(uint32_t grid, uint32_t block, hipStream_t s, const GenArgs& a) {
     if constexpr (W == 1)
         hipLaunchKernelGGL((k_generate1<V, KIND, U, NT>), dim3(grid), dim3(block), 0, s, a.out,
                            a.T, a.e_full, a.rem, a.base, a.J, a.M1, a.t_lo, a.t_hi);
-    else
+    else if constexpr (IL == 1)
         hipLaunchKernelGGL((k_generate2<V, KIND, U, NT>), dim3(grid), dim3(block), 0, s, a.out,
                            a.T, a.e_full, a.rem, a.base, a.J, a.M1, a.t_lo, a.t_hi);
+    else
+        hipLaunchKernelGGL((k_generate2_ilp<V, KIND, U, NT, IL>), dim3(grid), dim3(block), 0, s,
+                           a.out, a.T, a.e_full, a.rem, a.base, a.J, a.M1, a.JI, a.t_lo,
+                           a.t_hi);
     return hipGetLastError();
 }
 
-template <class V, int KIND, int W, bool NT>
+template <class V, int KIND, int W, int IL, bool NT>
 static hipError_t gen_u(int unroll, uint32_t grid, uint32_t block, hipStream_t s,
                         const GenArgs& a) {
     switch (unroll) {
-        case 1: return gen_one<V, KIND, W, 1, NT>(grid, block, s, a);
-        case 2: return gen_one<V, KIND, W, 2, NT>(grid, block, s, a);
-        case 4: return gen_one<V, KIND, W, 4, NT>(grid, block, s, a);
-        case 8: return gen_one<V, KIND, W, 8, NT>(grid, block, s, a);
+        case 1: return gen_one<V, KIND, W, IL, 1, NT>(grid, block, s, a);
+        case 2: return gen_one<V, KIND, W, IL, 2, NT>(grid, block, s, a);
+        case 4: return gen_one<V, KIND, W, IL, 4, NT>(grid, block, s, a);
+        case 8: return gen_one<V, KIND, W, IL, 8, NT>(grid, block, s, a);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <class V, int KIND, int W, int IL>
+static hipError_t gen_n(int unroll, bool nt, uint32_t grid, uint32_t block, hipStream_t s,
+                        const GenArgs& a) {
+    return nt ? gen_u<V, KIND, W, IL, true>(unroll, grid, block, s, a)
+              : gen_u<V, KIND, W, IL, false>(unroll, grid, block, s, a);
+}
+
 template <class V, int KIND>
-static hipError_t gen_k(int width, int unroll, bool nt, uint32_t grid, uint32_t block,
+static hipError_t gen_k(int width, int unroll, int ilp, bool nt, uint32_t grid, uint32_t block,
                         hipStream_t s, const GenArgs& a) {
-    if (width == 1)
-        return nt ? gen_u<V, KIND, 1, true>(unroll, grid, block, s, a)
-                  : gen_u<V, KIND, 1, false>(unroll, grid, block, s, a);
-    if (width == 2)
-        return nt ? gen_u<V, KIND, 2, true>(unroll, grid, block, s, a)
-                  : gen_u<V, KIND, 2, false>(unroll, grid, block, s, a);
+    if (width == 1 && ilp == 1) return gen_n<V, KIND, 1, 1>(unroll, nt, grid, block, s, a);
+    if (width == 2 && ilp == 1) return gen_n<V, KIND, 2, 1>(unroll, nt, grid, block, s, a);
+    if (width == 2 && ilp == 2) return gen_n<V, KIND, 2, 2>(unroll, nt, grid, block, s, a);
+    if (width == 2 && ilp == 4) return gen_n<V, KIND, 2, 4>(unroll, nt, grid, block, s, a);
     return hipErrorInvalidValue;
 }
 
 template <class V>
-static hipError_t gen_v(int kind, int width, int unroll, bool nt, uint32_t grid, uint32_t block,
-                        hipStream_t s, const GenArgs& a) {
-    return kind == 0 ? gen_k<V, 0>(width, unroll, nt, grid, block, s, a)
-                     : gen_k<V, 1>(width, unroll, nt, grid, block, s, a);
+static hipError_t gen_v(int kind, int width, int unroll, int ilp, bool nt, uint32_t grid,
+                        uint32_t block, hipStream_t s, const GenArgs& a) {
+    return kind == 0 ? gen_k<V, 0>(width, unroll, ilp, nt, grid, block, s, a)
+                     : gen_k<V, 1>(width, unroll, ilp, nt, grid, block, s, a);
 }
 
-hipError_t launch_generate(int mulmod, int kind, int width, int unroll, bool nt, uint32_t grid,
-                           uint32_t block, hipStream_t s, const GenArgs& a) {
+hipError_t launch_generate(int mulmod, int kind, int width, int unroll, int ilp, bool nt,
+                           uint32_t grid, uint32_t block, hipStream_t s, const GenArgs& a) {
     switch (mulmod) {
-        case 1: return gen_v<VarFP64>(kind, width, unroll, nt, grid, block, s, a);
-        case 2: return gen_v<VarBarrett>(kind, width, unroll, nt, grid, block, s, a);
-        case 3: return gen_v<VarShoup>(kind, width, unroll, nt, grid, block, s, a);
-        case 4: return gen_v<VarMontgomery>(kind, width, unroll, nt, grid, block, s, a);
+        case 1: return gen_v<VarFP64>(kind, width, unroll, ilp, nt, grid, block, s, a);
+        case 2: return gen_v<VarBarrett>(kind, width, unroll, ilp, nt, grid, block, s, a);
+        case 3: return gen_v<VarShoup>(kind, width, unroll, ilp, nt, grid, block, s, a);
+        case 4: return gen_v<VarMontgomery>(kind, width, unroll, ilp, nt, grid, block, s, a);
         default: return hipErrorInvalidValue;
     }
 }

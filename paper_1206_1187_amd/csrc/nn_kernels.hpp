@@ -31,12 +31,15 @@ struct GenArgs {
     uint64_t base;
     Mult J;
     Mult M1;
+    Mult JI;  // J^ilp: the step of a thread that advances ilp rows at once
     const Mult* t_lo;
     const Mult* t_hi;
 };
 
-hipError_t launch_generate(int mulmod, int kind, int width, int unroll, bool nontemporal,
-                           uint32_t grid, uint32_t block, hipStream_t stream, const GenArgs& a);
+// ilp (width 2 only): rows a thread keeps in flight, 1, 2 or 4.
+hipError_t launch_generate(int mulmod, int kind, int width, int unroll, int ilp,
+                           bool nontemporal, uint32_t grid, uint32_t block, hipStream_t stream,
+                           const GenArgs& a);
 
 // Flat layout: workgroup b of 256 threads writes elements
 // [512 b, 512 b + 512) of the launch, two consecutive ones per lane in one

@@ -86,13 +86,14 @@ def test_every_reduction_bit_exact(variant, kind):
     count = 3 * 65536 + 4099  # several rows of a 64K-thread grid plus a ragged tail
     ref, zr = orc.gen(z0, count, kind, threads=0)
     for block, grid, unroll in [(256, 256, 4), (64, 7, 1), (1024, 3, 8), (128, 1001, 2)]:
-        for width in (1, 2):
-            cfg = nn.make_cfg(block=block, grid=grid, mulmod=variant, unroll=unroll, width=width)
-            _say("reduction", variant, kind, block, grid, unroll, width)
+        for width, ilp in ((1, 1), (2, 1), (2, 2), (2, 4)):
+            cfg = nn.make_cfg(block=block, grid=grid, mulmod=variant, unroll=unroll, width=width,
+                              ilp=ilp)
+            _say("reduction", variant, kind, block, grid, unroll, width, ilp)
             got, zn = _gen_guarded(z0, count, kind, cfg=cfg)
             assert zn == zr
             assert np.array_equal(got, ref.view(np.uint64)), (variant, kind, block, grid,
-                                                              unroll, width)
+                                                              unroll, width, ilp)
 
 
 @pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
@@ -103,16 +104,18 @@ def test_thread_count_independence(block):
     ref_all = ref_all.view(np.uint64)
     for grid in (1, 3, 64, 257):
         T = grid * block
-        for width in (1, 2):
+        for width, ilp in ((1, 1), (2, 1), (2, 2), (2, 4)):
             row = T * width
-            for count in sorted({1, 2, 3, row - 1, row, row + 1, 3 * row + 17, 99991}):
+            counts = {1, 2, 3, row - 1, row, row + 1, 3 * row + 17, 5 * row - 1, 99991}
+            for count in sorted(counts):
                 if count < 1 or count > ref_all.size:
                     continue
                 for unroll in (1, 8):
-                    cfg = nn.make_cfg(block=block, grid=grid, unroll=unroll, width=width)
+                    cfg = nn.make_cfg(block=block, grid=grid, unroll=unroll, width=width,
+                                      ilp=ilp)
                     got, zn = _gen_guarded(z0, count, "f64", cfg=cfg, guard=256)
                     assert np.array_equal(got, ref_all[:count]), (block, grid, count, unroll,
-                                                                  width)
+                                                                  width, ilp)
                     assert zn == orc.skip(z0, count)
 
 
@@ -157,6 +160,7 @@ def test_config_validation():
            nn.make_cfg(block=100), nn.make_cfg(block=2048), nn.make_cfg(unroll=3),
            nn.make_cfg(width=3), nn.make_cfg(occupancy=1), nn.make_cfg(occupancy=17),
            nn.make_cfg(layout="rows", occupancy=4), nn.make_cfg(mulmod=9),
+           nn.make_cfg(ilp=3), nn.make_cfg(width=1, ilp=2), nn.make_cfg(layout="flat", ilp=2),
            nn.make_cfg(grid=1 << 20, block=1024)]
     for cfg in bad:
         with pytest.raises(nn.NNError):
