@@ -155,6 +155,65 @@ int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg *cfg_out);
 int nn_fill(uint64_t count, void *out_dev, uint64_t value, void *stream,
             const nn_launch_cfg *cfg);
 
+/* -------------------------------------------------------------- batch -- */
+
+/* One stream of a batch: a window of the sequence.  The call writes the
+ * `length` outputs that follow `state` (z_1..z_length after it) to
+ * out[out_offset .. out_offset + length).  Windows of one batch must not
+ * overlap in the output (overlapping windows leave the overlap undefined). */
+typedef struct nn_stream_desc {
+    uint64_t state;
+    uint64_t length;
+    uint64_t out_offset;
+} nn_stream_desc;
+
+/* Batch configuration (0 = default).  block: threads per workgroup (a
+ * multiple of 64 in [64,1024]); grid: persistent workgroups; rows: rows of
+ * 2*block outputs per tile (a tile is one workgroup's unit of work, with
+ * its own skip-ahead); mulmod: an nn_mulmod; flags: NN_CFG_TEMPORAL_STORES,
+ * NN_BATCH_NO_GRAPH (enqueue a copy and a kernel launch instead of
+ * replaying the plan's graph). */
+typedef struct nn_batch_cfg {
+    uint32_t block;
+    uint32_t grid;
+    uint32_t rows;
+    uint32_t mulmod;
+    uint32_t flags;
+} nn_batch_cfg;
+#define NN_BATCH_NO_GRAPH 8u
+
+/* Opaque batch plan: device workspace, pinned staging and a hipGraph of
+ * (staging -> workspace copy, persistent kernel) whose arguments never
+ * change, owned by the library until nn_batch_plan_destroy. */
+typedef struct nn_batch_plan nn_batch_plan;
+
+/* nn_batch_plan_create -- a plan on the current device for batches of at
+ * most `max_streams` streams and `max_outputs` outputs in total, writing
+ * `kind` outputs.  Allocates the workspace (about 8 bytes per 2*block*rows
+ * outputs plus 24 bytes per stream) in device and pinned host memory.
+ * Errors: NN_EINVAL (kind, cfg), NN_ERANGE (capacity), NN_ENOMEM, NN_EHIP. */
+int nn_batch_plan_create(int kind, uint32_t max_streams, uint64_t max_outputs,
+                         const nn_batch_cfg *cfg, nn_batch_plan **plan_out);
+/* Waits for the plan's last batch, then frees it (NULL is a no-op). */
+int nn_batch_plan_destroy(nn_batch_plan *plan);
+/* The plan's resolved configuration. */
+int nn_batch_plan_cfg(const nn_batch_plan *plan, nn_batch_cfg *cfg_out);
+
+/* nn_generate_batch -- the batched form of Algorithm BB step 3: every
+ * stream of `descs` (host array of n) is generated by one persistent kernel
+ * launch on `stream` (a hipStream_t), replayed from the plan's hipGraph.
+ * out_dev: device memory of the plan's device, 16-byte aligned, holding
+ * every window.  Streams longer than 2^24 outputs are split internally.
+ * Outputs are identical to nn_generate on each stream alone.  final_states
+ * (host array of n, or NULL) receives each stream's state after its window.
+ * Asynchronous; the call blocks only while the plan's previous batch is
+ * still copying its descriptors.  A plan serves one call at a time (calls
+ * on one plan are serialised).  Errors: NN_EINVAL (states, pointers, wrong
+ * device), NN_ERANGE (more streams or tiles than the plan holds; nothing is
+ * enqueued), NN_EHIP. */
+int nn_generate_batch(nn_batch_plan *plan, const nn_stream_desc *descs, uint32_t n,
+                      void *out_dev, void *stream, uint64_t *final_states);
+
 /* ------------------------------------------------------------- status -- */
 
 /* Static description of a status code (never NULL). */

@@ -22,7 +22,7 @@ INDEX_MIN = MODULUS + 100
 INDEX_MAX = 2 ** 53
 
 __all__ = [
-    "seed", "skip", "generate", "generate_into", "fill", "default_cfg", "make_cfg",
+    "seed", "skip", "generate", "generate_into", "fill", "default_cfg", "make_cfg", "BatchPlan",
     "init", "version", "NNError", "NativeLibraryMissing", "MODULUS", "PERIOD",
     "INDEX_MIN", "INDEX_MAX",
 ]
@@ -145,3 +145,83 @@ def debug_mulmod(variant, a, b):
     _native.check(_native.lib().nn_debug_mulmod(
         int(variant), a.ctypes.data_as(p), b.ctypes.data_as(p), a.size, out.ctypes.data_as(p)))
     return out
+
+
+_DESC_DTYPE = [("state", "<u8"), ("length", "<u8"), ("out_offset", "<u8")]
+
+
+class BatchPlan:
+    """A batch plan (include/nn.h, nn_batch_plan): many streams generated by
+    one persistent kernel replayed from a hipGraph.
+
+        plan = BatchPlan("f64", max_streams=10000, max_outputs=1 << 32)
+        final = plan.generate(states, lengths, offsets, out)   # out: cuda tensor
+    """
+
+    def __init__(self, kind, max_streams, max_outputs, block=0, grid=0, rows=0, mulmod=0,
+                 temporal=False, graph=True, device=None):
+        import torch
+        if isinstance(mulmod, str):
+            mulmod = MULMOD_NAMES[mulmod]
+        flags = (_native.NN_CFG_TEMPORAL_STORES if temporal else 0) | \
+                (0 if graph else _native.NN_BATCH_NO_GRAPH)
+        cfg = _native.BatchCfg(int(block), int(grid), int(rows), int(mulmod), flags)
+        self.kind = _kind(kind)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else int(device))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _native.check(_native.lib().nn_batch_plan_create(
+                self.kind, int(max_streams), int(max_outputs), ctypes.byref(cfg),
+                ctypes.byref(handle)))
+        self._h = handle
+
+    def cfg(self):
+        c = _native.BatchCfg()
+        _native.check(_native.lib().nn_batch_plan_cfg(self._h, ctypes.byref(c)))
+        return c
+
+    def generate(self, states, lengths, out_offsets, out, stream=None, final_states=False):
+        """Write every stream's window into the cuda tensor ``out`` (uint64 or
+        float64, matching the plan's kind).  Returns the streams' final
+        states as a numpy uint64 array when ``final_states`` is true."""
+        import numpy as np
+        import torch
+        if self._h is None:
+            raise NNError(_native.NN_EINVAL, "plan is closed")
+        want = torch.uint64 if self.kind == NN_OUT_U64 else torch.float64
+        if not out.is_cuda or not out.is_contiguous() or out.dtype != want:
+            raise NNError(_native.NN_EINVAL, "out must be a contiguous cuda %s tensor" % want)
+        n = len(states)
+        descs = np.empty(n, dtype=_DESC_DTYPE)
+        descs["state"] = np.asarray(states, dtype=np.uint64)
+        descs["length"] = np.asarray(lengths, dtype=np.uint64)
+        descs["out_offset"] = np.asarray(out_offsets, dtype=np.uint64)
+        ends = descs["out_offset"] + descs["length"]
+        if n and int(ends.max()) > out.numel():
+            raise NNError(_native.NN_ERANGE, "a window ends past the output tensor")
+        fin = np.empty(n, dtype=np.uint64) if final_states else None
+        p64 = ctypes.POINTER(ctypes.c_uint64)
+        with torch.cuda.device(out.device):
+            rc = _native.lib().nn_generate_batch(
+                self._h, ctypes.c_void_p(descs.ctypes.data), n, ctypes.c_void_p(out.data_ptr()),
+                _stream_handle(stream), fin.ctypes.data_as(p64) if fin is not None else None)
+        _native.check(rc)
+        return fin
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _native.lib().nn_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -60,6 +60,22 @@ class StreamDesc(ctypes.Structure):
     ]
 
 
+class BatchCfg(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_uint32),
+        ("grid", ctypes.c_uint32),
+        ("rows", ctypes.c_uint32),
+        ("mulmod", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+NN_BATCH_NO_GRAPH = 8
+
+
 _u64 = ctypes.c_uint64
 _pu64 = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
@@ -78,6 +94,11 @@ SIGNATURES = {
     "nn_last_error": (ctypes.c_char_p, []),
     "nn_version": (ctypes.c_char_p, []),
     "nn_debug_mulmod": (_int, [_int, _pu64, _pu64, _u64, _pu64]),
+    "nn_batch_plan_create": (_int, [_int, ctypes.c_uint32, _u64, ctypes.POINTER(BatchCfg),
+                                    ctypes.POINTER(_vp)]),
+    "nn_batch_plan_destroy": (_int, [_vp]),
+    "nn_batch_plan_cfg": (_int, [_vp, ctypes.POINTER(BatchCfg)]),
+    "nn_generate_batch": (_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _pu64]),
 }
 
 _lib = None

@@ -1,0 +1,224 @@
+"""GPU parity of the batched form (nn_generate_batch) against the oracle,
+and against the plain path stream by stream.  Bit-exact throughout."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1206_1187_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1206_1187_amd as nn  # noqa: E402
+
+M = 3 ** 33
+P = 2 * 3 ** 32
+SENTINEL = 0xDEADBEEFCAFEF00D
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _bits(t):
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)
+
+
+def _sentinel(n):
+    host = np.full(n, SENTINEL, dtype=np.uint64)
+    return torch.from_numpy(host.view(np.int64)).cuda()
+
+
+def _mixed_batch(seed, lengths):
+    """Random states, the given lengths, windows packed back to back with a
+    gap of 0..2 elements (so offsets take both parities)."""
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(wl.INDEX_MIN, wl.INDEX_MAX, len(lengths), endpoint=True, dtype=np.int64)
+    states = np.array([orc.seed(int(a)) for a in idx], dtype=np.uint64)
+    lengths = np.asarray(lengths, dtype=np.uint64)
+    gaps = rng.integers(0, 3, len(lengths)).astype(np.uint64)
+    offsets = np.zeros(len(lengths), dtype=np.uint64)
+    pos = 1  # the first window starts at an odd offset
+    for i in range(len(lengths)):
+        pos += int(gaps[i])
+        offsets[i] = pos
+        pos += int(lengths[i])
+    return states, lengths, offsets, pos + 3
+
+
+def _check_batch(got, states, lengths, offsets, kind):
+    written = np.zeros(got.size, dtype=bool)
+    for s, n, o in zip(states.tolist(), lengths.tolist(), offsets.tolist()):
+        ref, _ = orc.gen(s, n, kind)
+        assert np.array_equal(got[o:o + n], ref.view(np.uint64)), (s, n, o)
+        written[o:o + n] = True
+    assert (got[~written] == SENTINEL).all(), "write outside every window"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available()
+    nn.init(0)
+    yield
+    torch.cuda.synchronize()
+
+
+LENGTHS = [0, 1, 2, 3, 4, 63, 64, 65, 511, 512, 513, 1023, 1024, 1025, 8191, 8192, 8193,
+           16383, 16384, 16385, 70_001, 100_003, 262_145]
+
+
+@pytest.mark.parametrize("kind", ["u64", "f64"])
+@pytest.mark.parametrize("mulmod", ["fp64", "shoup", "barrett", "montgomery"])
+def test_batch_bit_exact_mixed_lengths(kind, mulmod):
+    states, lengths, offsets, total = _mixed_batch(11, LENGTHS)
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    for block, rows, grid, graph in [(256, 16, 0, True), (64, 1, 3, False), (1024, 3, 7, True),
+                                     (128, 64, 1, True)]:
+        _say("batch", kind, mulmod, block, rows, grid, graph)
+        buf = _sentinel(total)
+        with nn.BatchPlan(kind, 64, total, block=block, rows=rows, grid=grid, mulmod=mulmod,
+                          graph=graph) as plan:
+            fin = plan.generate(states, lengths, offsets, buf.view(dt), final_states=True)
+            torch.cuda.synchronize()
+        _check_batch(_bits(buf), states, lengths, offsets, kind)
+        for s, n, f in zip(states.tolist(), lengths.tolist(), fin.tolist()):
+            assert f == orc.skip(s, n)
+
+
+def test_graph_replays_with_eager_work_between():
+    """Replay one plan's graph many times with other work and syncs in
+    between; every replay must equal the oracle."""
+    kind = "f64"
+    with nn.BatchPlan(kind, 64, 1 << 22, rows=8) as plan:
+        for rep in range(6):
+            states, lengths, offsets, total = _mixed_batch(100 + rep, LENGTHS[rep:])
+            buf = _sentinel(total)
+            plan.generate(states, lengths, offsets, buf.view(torch.float64))
+            # eager work on the same stream between replays
+            junk = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+            nn.generate_into(orc.seed(wl.INDEX_MIN + rep), junk)
+            junk.mul_(2.0)
+            torch.cuda.synchronize()
+            _check_batch(_bits(buf), states, lengths, offsets, kind)
+
+
+def test_back_to_back_batches_without_sync():
+    """Several batches of one plan enqueued before any host synchronisation."""
+    bufs, cases = [], []
+    with nn.BatchPlan("u64", 64, 1 << 21, rows=4) as plan:
+        for rep in range(5):
+            states, lengths, offsets, total = _mixed_batch(200 + rep, LENGTHS)
+            buf = _sentinel(total)
+            plan.generate(states, lengths, offsets, buf.view(torch.uint64))
+            bufs.append(buf)
+            cases.append((states, lengths, offsets))
+        torch.cuda.synchronize()
+    for buf, (states, lengths, offsets) in zip(bufs, cases):
+        _check_batch(_bits(buf), states, lengths, offsets, "u64")
+
+
+def test_batch_equals_plain_per_stream():
+    states, lengths, offsets, total = _mixed_batch(7, LENGTHS)
+    buf = _sentinel(total)
+    with nn.BatchPlan("f64", 64, total) as plan:
+        plan.generate(states, lengths, offsets, buf.view(torch.float64))
+    torch.cuda.synchronize()
+    got = _bits(buf)
+    for s, n, o in zip(states.tolist(), lengths.tolist(), offsets.tolist()):
+        if n == 0:
+            continue
+        t, _ = nn.generate(s, n, "f64")
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(t), got[o:o + n])
+
+
+def test_long_stream_split_boundary():
+    """A stream longer than one internal piece (2^24 outputs)."""
+    s = orc.seed(wl.INDEX_MIN + 4242)
+    n = (1 << 24) * 2 + 777
+    buf = _sentinel(n + 3)
+    with nn.BatchPlan("u64", 4, n) as plan:
+        fin = plan.generate([s], [n], [1], buf.view(torch.uint64), final_states=True)
+    torch.cuda.synchronize()
+    got = _bits(buf)
+    assert got[0] == SENTINEL and (got[n + 1:] == SENTINEL).all()
+    assert int(fin[0]) == orc.skip(s, n)
+    for start in (0, (1 << 24) - 4096, (2 << 24) - 4096, n - 5000):
+        k = min(8192, n - start)
+        ref, _ = orc.gen(orc.skip(s, start), k, "u64")
+        assert np.array_equal(got[1 + start:1 + start + k], ref), start
+
+
+def test_batch_errors_enqueue_nothing():
+    with nn.BatchPlan("f64", 2, 10_000) as plan:
+        out = _sentinel(20_000)
+        good = orc.seed(wl.INDEX_MIN)
+        with pytest.raises(nn.NNError):  # too many streams
+            plan.generate([good] * 3, [10] * 3, [0, 10, 20], out.view(torch.float64))
+        with pytest.raises(nn.NNError):  # too many outputs / tiles
+            plan.generate([good], [19_999], [0], out.view(torch.float64))
+        with pytest.raises(nn.NNError):  # invalid state
+            plan.generate([3], [10], [0], out.view(torch.float64))
+        with pytest.raises(nn.NNError):  # misaligned output base
+            plan.generate([good], [10], [0], out[1:].view(torch.float64))
+        torch.cuda.synchronize()
+        assert (_bits(out) == SENTINEL).all()
+        fin = plan.generate([good], [0], [0], out.view(torch.float64), final_states=True)
+        assert int(fin[0]) == good
+
+
+def test_skip_stress_full_as_one_batch():
+    """Config 3 in full: 65,536 offsets over the whole period (forced ones
+    next to the wrap), 4,096 variates each, one batched launch."""
+    base = orc.seed(wl.INDEX_MIN)
+    offs = wl.skip_offsets()
+    states = np.array([nn.skip(base, int(o)) for o in offs], dtype=np.uint64)
+    lengths = np.full(offs.size, 4096, dtype=np.uint64)
+    offsets = np.arange(offs.size, dtype=np.uint64) * 4096
+    out = torch.empty(offs.size * 4096, dtype=torch.float64, device="cuda")
+    with nn.BatchPlan("f64", offs.size, out.numel()) as plan:
+        plan.generate(states, lengths, offsets, out)
+    torch.cuda.synchronize()
+    got = _bits(out).reshape(offs.size, 4096)
+    for i, o in enumerate(offs.tolist()):
+        z = orc.skip(base, o)
+        assert int(states[i]) == z
+        ref, _ = orc.gen(z, 4096, "f64")
+        assert np.array_equal(got[i], ref.view(np.uint64)), (i, o)
+
+
+def test_batched_workload_full_size_sampled():
+    """Config 4 at full size (10,000 streams, 2.7e9 outputs) in the bench's
+    plan configuration: every stream's first and last 64 outputs, and 400
+    whole streams, against the oracle."""
+    case = wl.batched()
+    states = np.array([orc.seed(int(a)) for a in case.indices], dtype=np.uint64)
+    lengths = case.lengths
+    offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
+    total = int(lengths.sum())
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    with nn.BatchPlan("f64", len(states), total) as plan:
+        _say("batched full", plan.cfg().as_dict(), total)
+        fin = plan.generate(states, lengths, offsets, out, final_states=True)
+    torch.cuda.synchronize()
+    flat = out.view(torch.int64)
+    rng = np.random.default_rng(99)
+    whole = set(rng.choice(len(states), 400, replace=False).tolist())
+    for i, (s, n, o) in enumerate(zip(states.tolist(), lengths.tolist(), offsets.tolist())):
+        assert int(fin[i]) == orc.skip(s, n)
+        if i in whole:
+            ref, _ = orc.gen(s, n, "f64", threads=0 if n > 1 << 16 else 1)
+            got = flat[o:o + n].cpu().numpy().view(np.uint64)
+            assert np.array_equal(got, ref.view(np.uint64)), i
+        else:
+            k = min(64, n)
+            head, _ = orc.gen(s, k, "f64")
+            tail, _ = orc.gen(orc.skip(s, n - k), k, "f64")
+            assert np.array_equal(flat[o:o + k].cpu().numpy().view(np.uint64),
+                                  head.view(np.uint64)), i
+            assert np.array_equal(flat[o + n - k:o + n].cpu().numpy().view(np.uint64),
+                                  tail.view(np.uint64)), i
+    del out, flat
+    torch.cuda.empty_cache()
