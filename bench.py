@@ -75,6 +75,90 @@ def traffic_from_profile():
         return None
 
 
+def batched_leg(nn, torch):
+    """Config 4: 10,000 streams (lengths log-uniform in [1, 2^22]) as one
+    batched launch replayed from the plan's hipGraph, against the same
+    streams with one nn_generate launch each on the same stream."""
+    import numpy as np
+
+    from paper_1206_1187_amd import tune
+
+    states, lengths, offsets = tune.batch_workload()
+    total = int(lengths.sum())
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    kw = tune.best_batch_cfg("f64", total)
+    res = {"workload": "batched: 10,000 seed indices (numpy default_rng(3)), lengths "
+                       "log-uniform in [1, 2^22], f64, windows packed back to back",
+           "streams": len(states), "variates": total}
+    with nn.BatchPlan("f64", len(states), total, **kw) as plan:
+        res["cfg"] = plan.cfg().as_dict()
+        graph_s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 10, torch)
+    with nn.BatchPlan("f64", len(states), total, graph=False, **kw) as plan:
+        direct_s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 10, torch)
+    res["graph_ms"] = graph_s * 1e3
+    res["no_graph_ms"] = direct_s * 1e3
+    res["variates_per_s"] = total / graph_s
+    res["GBps"] = 8.0 * total / graph_s / 1e9
+    res["frac_of_hbm_peak"] = res["GBps"] / (HBM_PEAK_GBPS)
+    batched_bits = out.view(torch.int64)[:4096].cpu().numpy().copy()
+    # one launch per stream, same output, same stream
+    views = [(int(s), out[int(o):int(o) + int(n)]) for s, n, o in zip(states, lengths, offsets)]
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for s, v in views:
+        nn.generate_into(s, v)
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res["per_stream_ms"] = a.elapsed_time(b)
+    res["per_stream_wall_ms"] = wall * 1e3
+    res["speedup_vs_per_stream"] = res["per_stream_ms"] / res["graph_ms"]
+    same = np.array_equal(out.view(torch.int64)[:4096].cpu().numpy(), batched_bits)
+    res["outputs_equal_sample"] = bool(same)
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def served_leg(nn, torch):
+    """Config 5: Poisson arrivals at 20k req/s for 10 s, sizes log-uniform in
+    [256, 2^24], 1,024 client streams, 64 GB output pool; the served form
+    against one nn_generate launch per request on the same trace, then a
+    load sweep (the trace's first 20,000 requests replayed 4x, 16x and 32x
+    faster)."""
+    import numpy as np
+
+    from paper_1206_1187_amd import serve
+    from paper_1206_1187_amd import workloads as wl
+
+    tr = wl.served()
+    states = np.array([nn.seed(int(a)) for a in tr.stream_indices], dtype=np.uint64)
+    pool = 64 << 30
+    res = {"workload": "served: numpy default_rng(4), 1,024 streams, Poisson 20k req/s for "
+                       "10 s, sizes log-uniform in [256, 2^24] f64, 64 GB pool",
+           "requests": int(tr.count.size), "variates": int(tr.count.sum())}
+    with serve.Server(states, pool, lanes=2) as srv:
+        res["served"] = serve.replay_served(srv, tr, timeout_s=120)
+    res["plain_per_request"] = serve.replay_plain(tr, states, pool // 8, timeout_s=120)
+    n = 20000
+    sl = wl.ServedTrace(tr.stream_indices, tr.t_arrive[:n], tr.stream_id[:n], tr.count[:n])
+    sweep = []
+    for scale in (4, 16, 32):
+        with serve.Server(states, pool, lanes=2) as srv:
+            a = serve.replay_served(srv, sl, time_scale=scale, timeout_s=120)
+        b = serve.replay_plain(sl, states, pool // 8, time_scale=scale, timeout_s=120)
+        sweep.append({"load_x": scale,
+                      "served": {k: a[k] for k in ("variates_per_s", "p50_ms", "p99_ms")},
+                      "plain": {k: b[k] for k in ("variates_per_s", "p50_ms", "p99_ms")}})
+    res["load_sweep_first_20000"] = sweep
+    res["served"].pop("stats", None)
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(case):
     """The oracle on all host threads over one whole step of the workload,
     streamed through one 2^25-element host buffer; plus one thread on a
@@ -117,6 +201,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fill ceiling and reduction comparison")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (torch) five times, "
                          "to scale hardware byte counters")
@@ -247,6 +332,12 @@ def main():
 
     del out_f, out_u
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        result["batched"] = batched_leg(nn, torch)
+        log("batched", json.dumps(result["batched"]))
+        if not args.no_served:
+            result["served"] = served_leg(nn, torch)
+            log("served", json.dumps(result["served"]))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(case)
         log("cpu_baseline", json.dumps(cb))

@@ -42,7 +42,8 @@ typedef enum nn_status {
     NN_ERANGE = 2, /* count too large for the address space or a descriptor */
     NN_EHIP = 3,   /* a HIP runtime call or kernel launch failed */
     NN_ENOMEM = 4, /* device or host allocation failed */
-    NN_ENODEV = 5  /* no usable gfx950 device */
+    NN_ENODEV = 5, /* no usable gfx950 device */
+    NN_ECANCELED = 6 /* a served request was cancelled before admission */
 } nn_status;
 
 typedef enum nn_out_kind {
@@ -213,6 +214,80 @@ int nn_batch_plan_cfg(const nn_batch_plan *plan, nn_batch_cfg *cfg_out);
  * enqueued), NN_EHIP. */
 int nn_generate_batch(nn_batch_plan *plan, const nn_stream_desc *descs, uint32_t n,
                       void *out_dev, void *stream, uint64_t *final_states);
+
+/* ------------------------------------------------------------- server -- */
+
+/* The served form: continuous batching of variate requests.  Each client
+ * stream has a state at position 0, held in a device table.  A request
+ * (stream, count) receives the next `count` outputs of its stream in
+ * submission order (its window is fixed at submission), so its bytes are
+ * the same whether it runs alone or with any other traffic.  Requests are
+ * admitted from the head of the arrival queue while the output pool has
+ * room and slots are free, and launched as batches on `lanes` concurrent
+ * HIP streams, each replaying a batch plan's graph. */
+typedef struct nn_server nn_server;
+
+typedef struct nn_server_cfg {
+    void *pool;                  /* caller-owned output pool (device memory of the
+                                    current device, 256-byte aligned), or NULL for
+                                    one owned by the server */
+    uint64_t pool_bytes;         /* output pool size in bytes, > 0 */
+    uint64_t max_batch_outputs;  /* outputs per batch and per request; 0 = 2^26 */
+    uint32_t max_batch_requests; /* requests per batch; 0 = 4096 */
+    uint32_t max_slots;          /* admitted, unreleased requests; 0 = 65536 */
+    uint32_t lanes;              /* concurrent batches; 0 = 2, at most 64 */
+    uint32_t kind;               /* nn_out_kind */
+    uint32_t flags;              /* NN_SERVER_FAKE_DEVICE */
+    nn_batch_cfg batch;          /* kernel shape of every lane's plan */
+    double fake_latency_s;       /* fake device: seconds per batch */
+    double fake_bytes_per_s;     /* fake device: write rate (0 = instant) */
+} nn_server_cfg;
+/* Fake device: host memory pool, outputs computed on the host by the
+ * library's exact host arithmetic, completions on a clock set by the caller
+ * (nn_server_set_clock), launch failures injectable.  For testing the
+ * scheduler without a GPU. */
+#define NN_SERVER_FAKE_DEVICE 1u
+
+typedef struct nn_completion {
+    uint64_t ticket;
+    uint64_t count;
+    uint64_t position; /* window start within the stream (modulo the period) */
+    void *data;        /* the outputs: device pointer into the pool (host
+                          pointer on the fake device); valid until release */
+    double t_submit, t_admit, t_launch, t_done; /* seconds on the server clock */
+    uint32_t stream_id;
+    int32_t status;    /* NN_OK, NN_EHIP (launch failed) or NN_ECANCELED */
+} nn_completion;
+
+typedef struct nn_server_stats {
+    uint64_t submitted, completed, failed, released;
+    uint64_t in_flight, batches, queued, pending;
+    uint64_t pool_used, pool_peak, slots_used;
+    double now;
+} nn_server_stats;
+
+/* nn_server_create -- a server on the current device for n_streams client
+ * streams whose states at position 0 are stream_states (host array of
+ * units).  Allocates the pool, the state table and `lanes` batch plans.
+ * Errors: NN_EINVAL, NN_ENOMEM, NN_EHIP. */
+int nn_server_create(const nn_server_cfg *cfg, const uint64_t *stream_states, uint32_t n_streams,
+                     nn_server **out);
+/* Waits for in-flight batches and frees everything (NULL is a no-op). */
+int nn_server_destroy(nn_server *srv);
+/* Queues a request; *ticket_out identifies it.  NN_ERANGE if it can never
+ * be admitted (larger than the pool or than max_batch_outputs). */
+int nn_server_submit(nn_server *srv, uint32_t stream_id, uint64_t count, uint64_t *ticket_out);
+/* Makes progress (harvest finished batches, admit, launch) and reports up
+ * to max_out finished requests, oldest first, into out (host array). */
+int nn_server_poll(nn_server *srv, nn_completion *out, uint32_t max_out, uint32_t *n_out);
+/* Returns a reported request's pool region and slot to the server. */
+int nn_server_release(nn_server *srv, uint64_t ticket);
+/* Cancels a request still in the queue (it finishes with NN_ECANCELED). */
+int nn_server_cancel(nn_server *srv, uint64_t ticket);
+int nn_server_stats_get(nn_server *srv, nn_server_stats *out);
+/* Fake device only: advance the server clock; inject n launch failures. */
+int nn_server_set_clock(nn_server *srv, double now);
+int nn_server_inject_failures(nn_server *srv, uint32_t n);
 
 /* ------------------------------------------------------------- status -- */
 

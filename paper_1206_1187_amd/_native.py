@@ -81,6 +81,51 @@ _pu64 = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
 _int = ctypes.c_int
 
+NN_SERVER_FAKE_DEVICE = 1
+NN_ECANCELED = 6
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [
+        ("pool", ctypes.c_void_p),
+        ("pool_bytes", ctypes.c_uint64),
+        ("max_batch_outputs", ctypes.c_uint64),
+        ("max_batch_requests", ctypes.c_uint32),
+        ("max_slots", ctypes.c_uint32),
+        ("lanes", ctypes.c_uint32),
+        ("kind", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("batch", BatchCfg),
+        ("fake_latency_s", ctypes.c_double),
+        ("fake_bytes_per_s", ctypes.c_double),
+    ]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("count", ctypes.c_uint64),
+        ("position", ctypes.c_uint64),
+        ("data", ctypes.c_void_p),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_launch", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("stream_id", ctypes.c_uint32),
+        ("status", ctypes.c_int32),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "failed", "released", "in_flight", "batches", "queued",
+        "pending", "pool_used", "pool_peak", "slots_used")] + [("now", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+
 # name -> (restype, argtypes); must match include/nn.h
 SIGNATURES = {
     "nn_seed": (_int, [_u64, _pu64]),
@@ -100,6 +145,24 @@ SIGNATURES = {
     "nn_batch_plan_cfg": (_int, [_vp, ctypes.POINTER(BatchCfg)]),
     "nn_generate_batch": (_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _pu64]),
 }
+
+_SERVER_SIGNATURES = {
+    "nn_server_create": (ctypes.c_int, [ctypes.POINTER(ServerCfg), ctypes.c_void_p,
+                                        ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "nn_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "nn_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "nn_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Completion),
+                                      ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
+    "nn_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "nn_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "nn_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "nn_server_set_clock": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "nn_server_inject_failures": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+}
+
+
+SIGNATURES.update(_SERVER_SIGNATURES)
 
 _lib = None
 

@@ -7,7 +7,7 @@
 // steps both states by (2^53)^(2*block) per row.  Pairs are aligned to the
 // global output index, so the 16-byte stores stay aligned for any stream
 // offset: a stream at an odd offset starts and may end with a half pair.
-// Element x of a stream is its output z_(x+1) = base * (2^53)^x.
+// Element x of a window is src * (2^53)^(pos + x + 1).
 #include <hip/hip_runtime.h>
 
 #include "nn_batch.hpp"
@@ -15,7 +15,18 @@
 
 namespace nn {
 
-template <class V, int KIND, bool NT>
+// src * (2^53)^k for any k < 2^52 through the four 13-bit skip tables.
+template <class V>
+__device__ __forceinline__ typename V::S skip_any(uint64_t src, uint64_t k,
+                                                  const Mult* __restrict__ t_sk) {
+    typename V::S z = V::load(src);
+#pragma unroll
+    for (uint32_t lvl = 0; lvl < kSkipLevels; ++lvl)
+        z = V::mul(z, t_sk[lvl * kSkipSize + ((k >> (kSkipBits * lvl)) & (kSkipSize - 1))]);
+    return z;
+}
+
+template <class V, int KIND, bool NT, bool INDEXED>
 __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
     const BatchHeader* hdr = a.ws;
     const uint32_t n_desc = hdr->n_desc;
@@ -40,7 +51,11 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
         // Row r, lane l: x_b = P0 + 2(rB + l) + 1 - s, x_a = x_b - 1.
         const uint64_t xb0 = P0 + 2ull * l + 1 - s;
         uint64_t* const pair0 = out + (D.out_off - s) + P0 + 2ull * l;  // global index of x_a, even
-        typename V::S zb = thread_start<V>(D.base, xb0, a.t_lo, a.t_hi);
+        typename V::S zb;
+        if constexpr (INDEXED)
+            zb = skip_any<V>(hdr->states[D.src], D.pos + xb0 + 1, a.t_sk);
+        else
+            zb = thread_start<V>(D.src, xb0 + 1, a.t_lo, a.t_hi);
         typename V::S za = V::mul(zb, a.Minv);
         for (uint32_t r = 0; r < rows; ++r) {
             const uint64_t xb = xb0 + 2ull * r * B;
@@ -63,30 +78,35 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
     }
 }
 
+template <class V, int KIND, bool NT>
+static const void* kernel_kvn(bool indexed) {
+    return indexed ? reinterpret_cast<const void*>(&k_batch<V, KIND, NT, true>)
+                   : reinterpret_cast<const void*>(&k_batch<V, KIND, NT, false>);
+}
+
 template <class V, int KIND>
-static const void* kernel_kv(bool nt) {
-    return nt ? reinterpret_cast<const void*>(&k_batch<V, KIND, true>)
-              : reinterpret_cast<const void*>(&k_batch<V, KIND, false>);
+static const void* kernel_kv(bool nt, bool indexed) {
+    return nt ? kernel_kvn<V, KIND, true>(indexed) : kernel_kvn<V, KIND, false>(indexed);
 }
 
 template <class V>
-static const void* kernel_v(int kind, bool nt) {
-    return kind == 0 ? kernel_kv<V, 0>(nt) : kernel_kv<V, 1>(nt);
+static const void* kernel_v(int kind, bool nt, bool indexed) {
+    return kind == 0 ? kernel_kv<V, 0>(nt, indexed) : kernel_kv<V, 1>(nt, indexed);
 }
 
-const void* batch_kernel(int mulmod, int kind, bool nt) {
+const void* batch_kernel(int mulmod, int kind, bool nt, bool indexed) {
     switch (mulmod) {
-        case 1: return kernel_v<VarFP64>(kind, nt);
-        case 2: return kernel_v<VarBarrett>(kind, nt);
-        case 3: return kernel_v<VarShoup>(kind, nt);
-        case 4: return kernel_v<VarMontgomery>(kind, nt);
+        case 1: return kernel_v<VarFP64>(kind, nt, indexed);
+        case 2: return kernel_v<VarBarrett>(kind, nt, indexed);
+        case 3: return kernel_v<VarShoup>(kind, nt, indexed);
+        case 4: return kernel_v<VarMontgomery>(kind, nt, indexed);
         default: return nullptr;
     }
 }
 
-hipError_t launch_batch(int mulmod, int kind, bool nt, uint32_t grid, uint32_t block,
-                        hipStream_t s, const BatchArgs& a) {
-    const void* k = batch_kernel(mulmod, kind, nt);
+hipError_t launch_batch(int mulmod, int kind, bool nt, bool indexed, uint32_t grid,
+                        uint32_t block, hipStream_t s, const BatchArgs& a) {
+    const void* k = batch_kernel(mulmod, kind, nt, indexed);
     if (!k) return hipErrorInvalidValue;
     BatchArgs copy = a;
     void* params[] = {&copy};

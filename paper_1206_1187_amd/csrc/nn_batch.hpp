@@ -10,11 +10,16 @@
 
 namespace nn {
 
-// One stream after host preparation: `base` = state * 2^53 (its first
-// output), `len` outputs written from element `out_off` of the output.
-// Streams longer than kBatchMaxLen are split by the host.
+// One stream window after host preparation: `len` outputs written from
+// element `out_off` of the output; output x is src * (2^53)^(pos + x + 1).
+//  * direct batches: src = the state, pos = 0 (streams longer than
+//    kBatchMaxLen are split by the host, each piece with its own state);
+//  * indexed batches (the served form): src = a row of the device-resident
+//    stream-state table, pos = the window's position in that stream
+//    (reduced modulo the period).
 struct BatchDesc {
-    uint64_t base;
+    uint64_t src;
+    uint64_t pos;
     uint64_t len;
     uint64_t out_off;
 };
@@ -28,9 +33,16 @@ struct BatchHeader {
     uint64_t* out;
     uint32_t n_desc;
     uint32_t n_tiles;
-    uint64_t pad[6];
+    const uint64_t* states;  // indexed batches: the stream-state table
+    uint64_t pad[5];
 };
 static_assert(sizeof(BatchHeader) == 64, "header is one 64-byte line");
+
+// Skip tables of the indexed form: t_sk[lvl][j] = (2^53)^(j * 2^(13 lvl)),
+// lvl < 4, j < 8192, so any exponent below 2^52 costs four multiplications.
+constexpr uint32_t kSkipBits = 13;
+constexpr uint32_t kSkipSize = 1u << kSkipBits;
+constexpr uint32_t kSkipLevels = 4;
 
 // Kernel arguments (fixed for the life of a plan).
 struct BatchArgs {
@@ -40,13 +52,14 @@ struct BatchArgs {
     Mult Minv;              // (2^53)^-1
     const Mult* t_lo;
     const Mult* t_hi;
+    const Mult* t_sk;       // kSkipLevels * kSkipSize entries (indexed batches)
 };
 
-// The kernel entry for (mulmod, kind, nontemporal); its single parameter is
-// a BatchArgs passed by value.
-const void* batch_kernel(int mulmod, int kind, bool nontemporal);
+// The kernel entry for (mulmod, kind, nontemporal, indexed); its single
+// parameter is a BatchArgs passed by value.
+const void* batch_kernel(int mulmod, int kind, bool nontemporal, bool indexed);
 
-hipError_t launch_batch(int mulmod, int kind, bool nontemporal, uint32_t grid, uint32_t block,
-                        hipStream_t stream, const BatchArgs& a);
+hipError_t launch_batch(int mulmod, int kind, bool nontemporal, bool indexed, uint32_t grid,
+                        uint32_t block, hipStream_t stream, const BatchArgs& a);
 
 }  // namespace nn

@@ -1,142 +1,28 @@
-// nn_capi.hip -- the extern "C" boundary declared in include/nn.h.
+// nn_capi.hip -- the extern "C" entry points of include/nn.h for the plain
+// and batched forms (the served form is in nn_server.hip).
 //
-// Host work per generating call: validate, pick the launch shape, compute
-// base = state*2^53 and the jump J = (2^53)^T with its reduction data,
-// enqueue one kernel, and advance the caller's state by skip-ahead.  No
-// allocation and no synchronisation happen on this path after the one-time
-// per-device table upload.
+// Host work per plain call: validate, pick the launch shape, compute
+// base = state*2^53 and the jump multiplier with its reduction data, enqueue
+// one kernel, and advance the caller's state by skip-ahead.  No allocation
+// and no synchronisation happen on this path after the one-time per-device
+// table upload.
 #include <hip/hip_runtime.h>
-#include <stdarg.h>
-#include <stdio.h>
-#include <string.h>
-
-#include <new>
+#include <stdint.h>
 
 #include <mutex>
-#include <string>
-#include <vector>
 
 #include "nn.h"
-#include "nn_batch.hpp"
 #include "nn_host.hpp"
+#include "nn_internal.hpp"
 #include "nn_kernels.hpp"
 
 using namespace nn;
 
+namespace nn {
+const char* last_error();
+}
+
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int status, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return status;
-}
-
-int ok() {
-    g_last_error.clear();
-    return NN_OK;
-}
-
-constexpr int kMaxDevices = 64;
-
-struct DeviceTables {
-    bool ready = false;
-    Mult* t_lo = nullptr;       // device, kLoSize entries
-    Mult* t_hi = nullptr;       // device, kHiSize entries
-    uint64_t* t_blk = nullptr;  // device, kFlatMaxBlocks entries (flat layout)
-    int cus = 0;
-    uint32_t lds_per_cu = 0;
-    uint32_t lds_per_block = 0;
-};
-
-std::mutex g_dev_mutex;
-DeviceTables g_dev[kMaxDevices];
-
-// Host copies of the skip-ahead tables (built once, shared by all devices).
-const std::vector<Mult>& host_tables() {
-    static std::vector<Mult> tab = [] {
-        std::vector<Mult> t(kLoSize + kHiSize);
-        uint64_t p = 1;
-        for (uint32_t l = 0; l < kLoSize; ++l) {  // (2^53)^l
-            t[l] = make_mult(p);
-            p = h_mulmod(p, kMult);
-        }
-        const uint64_t step = p;  // (2^53)^1024
-        uint64_t q = 1;
-        for (uint32_t j = 0; j < kHiSize; ++j) {  // (2^53)^(1024 j)
-            t[kLoSize + j] = make_mult(q);
-            q = h_mulmod(q, step);
-        }
-        return t;
-    }();
-    return tab;
-}
-
-// Host copy of the flat layout's workgroup multipliers (2^53)^(512 b).
-const std::vector<uint64_t>& host_block_table() {
-    static std::vector<uint64_t> tab = [] {
-        std::vector<uint64_t> t(kFlatMaxBlocks);
-        const uint64_t step = MultPowers::get().pow(kFlatPerBlock);
-        uint64_t p = 1;
-        for (uint64_t b = 0; b < kFlatMaxBlocks; ++b) {
-            t[b] = p;
-            p = h_mulmod(p, step);
-        }
-        return t;
-    }();
-    return tab;
-}
-
-// Set up tables on `dev`, which must be the current device.
-int ensure_device_current(int dev, DeviceTables** out) {
-    if (dev < 0 || dev >= kMaxDevices) return fail(NN_ENODEV, "device %d out of range", dev);
-    std::lock_guard<std::mutex> lock(g_dev_mutex);
-    DeviceTables& d = g_dev[dev];
-    if (!d.ready) {
-        hipDeviceProp_t prop;
-        hipError_t e = hipGetDeviceProperties(&prop, dev);
-        if (e != hipSuccess)
-            return fail(NN_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
-        if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
-            return fail(NN_ENODEV, "device %d is %s, this library is built for gfx950", dev,
-                        prop.gcnArchName);
-        const std::vector<Mult>& h = host_tables();
-        const std::vector<uint64_t>& hb = host_block_table();
-        const size_t mult_bytes = h.size() * sizeof(Mult);
-        const size_t blk_bytes = hb.size() * sizeof(uint64_t);
-        void* mem = nullptr;
-        e = hipMalloc(&mem, mult_bytes + blk_bytes);
-        if (e != hipSuccess) return fail(NN_ENOMEM, "hipMalloc tables: %s", hipGetErrorString(e));
-        e = hipMemcpy(mem, h.data(), mult_bytes, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy((char*)mem + mult_bytes, hb.data(), blk_bytes, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(mem);
-            return fail(NN_EHIP, "table upload: %s", hipGetErrorString(e));
-        }
-        d.t_lo = (Mult*)mem;
-        d.t_hi = d.t_lo + kLoSize;
-        d.t_blk = (uint64_t*)((char*)mem + mult_bytes);
-        d.cus = prop.multiProcessorCount;
-        d.lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
-        d.lds_per_block = (uint32_t)prop.sharedMemPerBlock;
-        d.ready = true;
-    }
-    *out = &d;
-    return NN_OK;
-}
-
-int current_device(DeviceTables** out) {
-    int dev = -1;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return fail(NN_ENODEV, "hipGetDevice: %s", hipGetErrorString(e));
-    return ensure_device_current(dev, out);
-}
 
 struct Resolved {
     uint32_t block, grid, mulmod, unroll, width, occupancy, ilp;
@@ -144,26 +30,13 @@ struct Resolved {
     uint32_t lds;  // dynamic LDS bytes per workgroup that cap residency
 };
 
-// Defaults from launch-shape sweeps on MI355X (256 CUs, bulk outputs of
-// 2^28..2^30): 16-byte stores per lane from 256-thread workgroups on a
-// fraction of the CUs (fewer concurrent writers keep the HBM write stream
-// closer to sequential).  F64 output: the FP64 reduction with two rows in
-// flight on CUs/2 workgroups; U64 output: Shoup's reduction (integer state,
-// no conversion) with one row on 3*CUs/4 workgroups.
-struct KindDefaults {
-    uint32_t mulmod, grid_num, grid_den, unroll, ilp;
-};
-constexpr uint32_t kDefaultBlock = 256;
-constexpr KindDefaults kDefaults[2] = {
-    {NN_MULMOD_SHOUP, 3, 4, 2, 1},  // NN_OUT_U64
-    {NN_MULMOD_FP64, 1, 2, 4, 2},   // NN_OUT_F64
-};
+
 
 // `out` may be NULL (query of the defaults): it is then taken as aligned.
 int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const DeviceTables& d,
                 const void* out, Resolved* r) {
     const int cus = d.cus;
-    const KindDefaults& kd = kDefaults[kind == NN_OUT_F64 ? 1 : 0];
+    const KindDefaults& kd = kind_defaults(kind);
     nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
     const bool aligned16 = ((uintptr_t)out % 16) == 0;
@@ -244,46 +117,6 @@ int check_out(uint64_t count, void* out) {
 
 }  // namespace
 
-// ------------------------------------------------------------- batch plan --
-struct nn_batch_plan {
-    std::mutex mu;  // one batch call at a time per plan
-    int device = 0;
-    int kind = 0;
-    uint32_t mulmod = 0, block = 0, grid = 0, rows = 0;
-    bool nontemporal = true, use_graph = true;
-    uint32_t max_streams = 0;
-    uint64_t max_outputs = 0;
-    uint32_t cap_desc = 0;
-    uint64_t cap_tiles = 0;
-    size_t ws_bytes = 0;
-    void* ws_dev = nullptr;
-    void* ws_host = nullptr;  // pinned staging, same layout as ws_dev
-    hipEvent_t done = nullptr;
-    bool pending = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy_node = nullptr, kernel_node = nullptr;
-    BatchArgs args;
-};
-
-namespace {
-
-void plan_release(nn_batch_plan* p) {
-    if (p->done) {
-        (void)hipEventSynchronize(p->done);
-        (void)hipEventDestroy(p->done);
-    }
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->ws_dev) (void)hipFree(p->ws_dev);
-    if (p->ws_host) (void)hipHostFree(p->ws_host);
-    delete p;
-}
-
-constexpr uint32_t kBatchDefaultRows = 16;
-
-}  // namespace
-
 extern "C" {
 
 int nn_seed(uint64_t index, uint64_t* state_out) {
@@ -311,7 +144,7 @@ int nn_init(int device) {
         if (e != hipSuccess) return fail(NN_ENODEV, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
     }
     DeviceTables* d = nullptr;
-    int st = ensure_device_current(device, &d);
+    int st = current_device(&d);
     if (device != prev) (void)hipSetDevice(prev);
     return st == NN_OK ? ok() : st;
 }
@@ -430,102 +263,12 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
 
 int nn_batch_plan_create(int kind, uint32_t max_streams, uint64_t max_outputs,
                          const nn_batch_cfg* cfg, nn_batch_plan** plan_out) {
-    if (!plan_out) return fail(NN_EINVAL, "plan_out is NULL");
-    if (kind != NN_OUT_U64 && kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %d unknown", kind);
-    if (max_streams == 0) return fail(NN_EINVAL, "max_streams must be positive");
-    nn_batch_cfg c = {0, 0, 0, 0, 0};
-    if (cfg) c = *cfg;
-    if (c.flags & ~(NN_CFG_TEMPORAL_STORES | NN_BATCH_NO_GRAPH))
-        return fail(NN_EINVAL, "unknown batch flags 0x%x", c.flags);
-    DeviceTables* d = nullptr;
-    int st = current_device(&d);
-    if (st) return st;
-    const KindDefaults& kd = kDefaults[kind == NN_OUT_F64 ? 1 : 0];
-    const uint32_t block = c.block ? c.block : kDefaultBlock;
-    if (block < 64 || block > 1024 || block % 64)
-        return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
-    const uint32_t rows = c.rows ? c.rows : kBatchDefaultRows;
-    if (rows < 1 || rows > 4096) return fail(NN_EINVAL, "rows %u: must be in [1, 4096]", rows);
-    const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
-    if (mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", mulmod);
-    uint32_t grid = c.grid;
-    if (!grid) {
-        grid = (uint32_t)((uint64_t)d->cus * kd.grid_num / kd.grid_den);
-        if (!grid) grid = 1;
-    }
-    if (grid > (1u << 20)) return fail(NN_EINVAL, "grid %u too large", grid);
-    const uint64_t tile = 2ull * block * rows;
-    const uint64_t cap_desc = (uint64_t)max_streams + max_outputs / kBatchMaxLen + 1;
-    const uint64_t cap_tiles = max_outputs / tile + 2 * cap_desc;
-    if (cap_desc > 0xffffffffull || cap_tiles > 0xffffffffull)
-        return fail(NN_ERANGE, "batch capacity too large");
-
-    nn_batch_plan* p = new (std::nothrow) nn_batch_plan();
-    if (!p) return fail(NN_ENOMEM, "plan allocation");
-    (void)hipGetDevice(&p->device);
-    p->kind = kind;
-    p->mulmod = mulmod;
-    p->block = block;
-    p->grid = grid;
-    p->rows = rows;
-    p->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
-    p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
-    p->max_streams = max_streams;
-    p->max_outputs = max_outputs;
-    p->cap_desc = (uint32_t)cap_desc;
-    p->cap_tiles = cap_tiles;
-    p->ws_bytes = sizeof(BatchHeader) + cap_desc * sizeof(BatchDesc) + cap_tiles * sizeof(uint64_t);
-    hipError_t e = hipMalloc(&p->ws_dev, p->ws_bytes);
-    if (e != hipSuccess) {
-        plan_release(p);
-        return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", p->ws_bytes, hipGetErrorString(e));
-    }
-    e = hipHostMalloc(&p->ws_host, p->ws_bytes, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        plan_release(p);
-        return fail(NN_ENOMEM, "pinned staging (%zu bytes): %s", p->ws_bytes, hipGetErrorString(e));
-    }
-    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        plan_release(p);
-        return fail(NN_EHIP, "event: %s", hipGetErrorString(e));
-    }
-    p->args.ws = (const BatchHeader*)p->ws_dev;
-    p->args.rows = rows;
-    p->args.JB = make_mult(MultPowers::get().pow(2ull * block));
-    p->args.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
-    p->args.t_lo = d->t_lo;
-    p->args.t_hi = d->t_hi;
-    if (p->use_graph) {
-        e = hipGraphCreate(&p->graph, 0);
-        if (e == hipSuccess)
-            e = hipGraphAddMemcpyNode1D(&p->copy_node, p->graph, nullptr, 0, p->ws_dev, p->ws_host,
-                                        sizeof(BatchHeader), hipMemcpyHostToDevice);
-        if (e == hipSuccess) {
-            hipKernelNodeParams kp;
-            memset(&kp, 0, sizeof kp);
-            void* params[] = {&p->args};
-            kp.func = const_cast<void*>(batch_kernel((int)mulmod, kind, p->nontemporal));
-            kp.gridDim = dim3(grid);
-            kp.blockDim = dim3(block);
-            kp.sharedMemBytes = 0;
-            kp.kernelParams = params;
-            kp.extra = nullptr;
-            e = hipGraphAddKernelNode(&p->kernel_node, p->graph, &p->copy_node, 1, &kp);
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            plan_release(p);
-            return fail(NN_EHIP, "batch graph: %s", hipGetErrorString(e));
-        }
-    }
-    *plan_out = p;
-    return ok();
+    int st = plan_create(kind, max_streams, max_outputs, cfg, false, nullptr, plan_out);
+    return st == NN_OK ? ok() : st;
 }
 
 int nn_batch_plan_destroy(nn_batch_plan* plan) {
-    if (!plan) return ok();
-    plan_release(plan);
+    if (plan) plan_release(plan);
     return ok();
 }
 
@@ -543,8 +286,10 @@ int nn_batch_plan_cfg(const nn_batch_plan* plan, nn_batch_cfg* cfg_out) {
 int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t n, void* out_dev,
                       void* stream, uint64_t* final_states) {
     if (!plan) return fail(NN_EINVAL, "plan is NULL");
+    if (plan->indexed) return fail(NN_EINVAL, "plan belongs to a server");
     if (n && !descs) return fail(NN_EINVAL, "descs is NULL");
-    uint64_t total = 0, pieces = 0;
+    uint64_t total = 0, pieces = 0, tiles = 0;
+    const uint64_t tile = 2ull * plan->block * plan->rows;
     for (uint32_t i = 0; i < n; ++i) {
         const nn_stream_desc& q = descs[i];
         if (!valid_state(q.state))
@@ -554,7 +299,11 @@ int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t
             return fail(NN_ERANGE, "stream %u: output range overflows", i);
         total += q.length;
         if (total < q.length) return fail(NN_ERANGE, "total outputs overflow");
-        pieces += (q.length + kBatchMaxLen - 1) / kBatchMaxLen;
+        for (uint64_t off = 0; off < q.length; off += kBatchMaxLen) {
+            const uint64_t len = q.length - off < kBatchMaxLen ? q.length - off : kBatchMaxLen;
+            tiles += (len + ((q.out_offset + off) & 1u) + tile - 1) / tile;
+            ++pieces;
+        }
     }
     if (total) {
         if (!out_dev) return fail(NN_EINVAL, "output pointer is NULL");
@@ -566,77 +315,36 @@ int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t
     if (total > plan->max_outputs)
         return fail(NN_ERANGE, "batch of %llu outputs, plan holds %llu", (unsigned long long)total,
                     (unsigned long long)plan->max_outputs);
+    if (pieces > plan->cap_desc || tiles > plan->cap_tiles)
+        return fail(NN_ERANGE, "batch needs %llu pieces and %llu tiles, plan holds %u and %llu",
+                    (unsigned long long)pieces, (unsigned long long)tiles, plan->cap_desc,
+                    (unsigned long long)plan->cap_tiles);
     std::lock_guard<std::mutex> lock(plan->mu);
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
         return fail(NN_EINVAL, "plan belongs to device %d, current device is %d", plan->device, dev);
-    if (pieces > plan->cap_desc)
-        return fail(NN_ERANGE, "batch needs %llu stream pieces, plan holds %u",
-                    (unsigned long long)pieces, plan->cap_desc);
-    const uint64_t tile = 2ull * plan->block * plan->rows;
-    // Count tiles first so nothing is written to the staging on error.
-    uint64_t n_tiles = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        const nn_stream_desc& q = descs[i];
-        for (uint64_t off = 0; off < q.length; off += kBatchMaxLen) {
-            const uint64_t len = q.length - off < kBatchMaxLen ? q.length - off : kBatchMaxLen;
-            n_tiles += (len + ((q.out_offset + off) & 1u) + tile - 1) / tile;
-        }
-    }
-    if (n_tiles > plan->cap_tiles)
-        return fail(NN_ERANGE, "batch needs %llu tiles, plan holds %llu",
-                    (unsigned long long)n_tiles, (unsigned long long)plan->cap_tiles);
     if (total == 0) {
         if (final_states)
             for (uint32_t i = 0; i < n; ++i) final_states[i] = descs[i].state;
         return ok();
     }
-    // The previous batch of this plan must have consumed the staging.
-    if (plan->pending) {
-        hipError_t e = hipEventSynchronize(plan->done);
-        if (e != hipSuccess) return fail(NN_EHIP, "waiting for the previous batch: %s",
-                                         hipGetErrorString(e));
-        plan->pending = false;
-    }
-    BatchHeader* hdr = (BatchHeader*)plan->ws_host;
-    BatchDesc* dd = (BatchDesc*)(hdr + 1);
+    int st = plan_wait(plan);
+    if (st) return st;
+    BatchDesc* dd = plan_staged_descs(plan);
     uint32_t nd = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const nn_stream_desc& q = descs[i];
         for (uint64_t off = 0; off < q.length; off += kBatchMaxLen) {
             const uint64_t len = q.length - off < kBatchMaxLen ? q.length - off : kBatchMaxLen;
-            dd[nd].base = h_skip(q.state, off + 1);
+            dd[nd].src = h_skip(q.state, off);  // the state before the piece's first output
+            dd[nd].pos = 0;
             dd[nd].len = len;
             dd[nd].out_off = q.out_offset + off;
             ++nd;
         }
     }
-    uint64_t* tw = (uint64_t*)(dd + nd);
-    uint64_t nt = 0;
-    for (uint32_t k = 0; k < nd; ++k) {
-        const uint64_t m = (dd[k].len + (dd[k].out_off & 1u) + tile - 1) / tile;
-        for (uint64_t j = 0; j < m; ++j) tw[nt++] = ((uint64_t)k << 32) | j;
-    }
-    hdr->out = (uint64_t*)out_dev;
-    hdr->n_desc = nd;
-    hdr->n_tiles = (uint32_t)nt;
-    const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc) + nt * sizeof(uint64_t);
-    hipError_t e;
-    if (plan->use_graph) {
-        e = hipGraphExecMemcpyNodeSetParams1D(plan->exec, plan->copy_node, plan->ws_dev,
-                                              plan->ws_host, bytes, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
-    } else {
-        e = hipMemcpyAsync(plan->ws_dev, plan->ws_host, bytes, hipMemcpyHostToDevice,
-                           (hipStream_t)stream);
-        if (e == hipSuccess)
-            e = launch_batch((int)plan->mulmod, plan->kind, plan->nontemporal, plan->grid,
-                             plan->block, (hipStream_t)stream, plan->args);
-    }
-    if (e != hipSuccess) return fail(NN_EHIP, "batch launch: %s", hipGetErrorString(e));
-    e = hipEventRecord(plan->done, (hipStream_t)stream);
-    if (e != hipSuccess) return fail(NN_EHIP, "batch event: %s", hipGetErrorString(e));
-    plan->pending = true;
+    st = plan_launch_staged(plan, nd, out_dev, (hipStream_t)stream);
+    if (st) return st;
     if (final_states)
         for (uint32_t i = 0; i < n; ++i) final_states[i] = h_skip(descs[i].state, descs[i].length);
     return ok();
@@ -650,11 +358,12 @@ const char* nn_strerror(int status) {
         case NN_EHIP: return "HIP runtime error";
         case NN_ENOMEM: return "out of memory";
         case NN_ENODEV: return "no usable gfx950 device";
+        case NN_ECANCELED: return "request cancelled";
         default: return "unknown status";
     }
 }
 
-const char* nn_last_error(void) { return g_last_error.c_str(); }
+const char* nn_last_error(void) { return last_error(); }
 
 const char* nn_version(void) { return "nn-alpha23 0.1.0 (gfx950)"; }
 

@@ -1,0 +1,90 @@
+// nn_internal.hpp -- state shared by the C-ABI translation units: status
+// reporting, per-device tables and batch plans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "nn.h"
+#include "nn_arith.hpp"
+#include "nn_batch.hpp"
+
+namespace nn {
+
+// Records a detail string for nn_last_error() and returns `status`.
+int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int ok();
+
+struct DeviceTables {
+    bool ready = false;
+    Mult* t_lo = nullptr;       // kLoSize entries
+    Mult* t_hi = nullptr;       // kHiSize entries
+    Mult* t_sk = nullptr;       // kSkipLevels * kSkipSize entries
+    uint64_t* t_blk = nullptr;  // kFlatMaxBlocks entries (flat layout)
+    int cus = 0;
+    uint32_t lds_per_cu = 0;
+    uint32_t lds_per_block = 0;
+};
+
+// Tables of the current device (set up on first use).
+int current_device(DeviceTables** out);
+
+// Per-kind launch defaults.
+struct KindDefaults {
+    uint32_t mulmod, grid_num, grid_den, unroll, ilp;
+};
+const KindDefaults& kind_defaults(int kind);
+constexpr uint32_t kDefaultBlock = 256;
+
+}  // namespace nn
+
+// A batch plan: workspace, pinned staging, and a graph of (copy, kernel).
+struct nn_batch_plan {
+    std::mutex mu;  // one batch call at a time per plan
+    int device = 0;
+    int kind = 0;
+    bool indexed = false;
+    uint32_t mulmod = 0, block = 0, grid = 0, rows = 0;
+    bool nontemporal = true, use_graph = true;
+    uint32_t max_streams = 0;
+    uint64_t max_outputs = 0;
+    uint32_t cap_desc = 0;
+    uint64_t cap_tiles = 0;
+    size_t ws_bytes = 0;
+    void* ws_dev = nullptr;
+    void* ws_host = nullptr;  // pinned staging, same layout as ws_dev
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy_node = nullptr, kernel_node = nullptr;
+    nn::BatchArgs args;
+};
+
+namespace nn {
+
+// Creates a plan on the current device.  Indexed plans read window states
+// from `states` (a device table) and take descriptors with src = row.
+int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_batch_cfg* cfg,
+                bool indexed, const uint64_t* states, nn_batch_plan** out);
+void plan_release(nn_batch_plan* p);
+
+// Waits until the plan's previous batch has consumed its staging.
+int plan_wait(nn_batch_plan* p);
+// True when the plan's last batch (if any) has finished on the device.
+bool plan_idle(nn_batch_plan* p);
+// Staged descriptors of the next batch (capacity p->cap_desc); valid after
+// plan_wait().
+inline BatchDesc* plan_staged_descs(nn_batch_plan* p) {
+    return reinterpret_cast<BatchDesc*>(reinterpret_cast<BatchHeader*>(p->ws_host) + 1);
+}
+// Number of tiles `nd` staged descriptors need.
+uint64_t plan_count_tiles(const nn_batch_plan* p, const BatchDesc* d, uint32_t nd);
+// Builds the tile table for the `nd` staged descriptors, uploads and
+// launches on `stream`, and records the plan's completion event.  The
+// caller checked capacities (plan_count_tiles) and holds p->mu.
+int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t stream);
+
+}  // namespace nn

@@ -1,0 +1,328 @@
+// nn_runtime.hip -- status reporting, per-device skip tables and batch plans
+// (shared by the C-ABI entry points of the plain, batched and served forms).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nn_host.hpp"
+#include "nn_internal.hpp"
+#include "nn_kernels.hpp"
+
+namespace nn {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int ok() {
+    g_last_error.clear();
+    return NN_OK;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
+// Defaults from launch-shape sweeps on MI355X (256 CUs, bulk outputs of
+// 2^28..2^30): 16-byte stores per lane from 256-thread workgroups on a
+// fraction of the CUs (fewer concurrent writers keep the HBM write stream
+// closer to sequential).  F64 output: the FP64 reduction with two rows in
+// flight on CUs/2 workgroups; U64 output: Shoup's reduction (integer state,
+// no conversion) with one row on 3*CUs/4 workgroups.
+const KindDefaults& kind_defaults(int kind) {
+    static const KindDefaults d[2] = {
+        {NN_MULMOD_SHOUP, 3, 4, 2, 1},  // NN_OUT_U64
+        {NN_MULMOD_FP64, 1, 2, 4, 2},   // NN_OUT_F64
+    };
+    return d[kind == NN_OUT_F64 ? 1 : 0];
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mutex;
+DeviceTables g_dev[kMaxDevices];
+
+// Host copies of the device tables (built once, shared by all devices):
+// t_lo, t_hi, then the four 13-bit skip levels.
+const std::vector<Mult>& host_mult_tables() {
+    static std::vector<Mult> tab = [] {
+        std::vector<Mult> t(kLoSize + kHiSize + kSkipLevels * kSkipSize);
+        uint64_t p = 1;
+        for (uint32_t l = 0; l < kLoSize; ++l) {  // (2^53)^l
+            t[l] = make_mult(p);
+            p = h_mulmod(p, kMult);
+        }
+        const uint64_t step = p;  // (2^53)^1024
+        uint64_t q = 1;
+        for (uint32_t j = 0; j < kHiSize; ++j) {  // (2^53)^(1024 j)
+            t[kLoSize + j] = make_mult(q);
+            q = h_mulmod(q, step);
+        }
+        Mult* sk = t.data() + kLoSize + kHiSize;
+        for (uint32_t lvl = 0; lvl < kSkipLevels; ++lvl) {  // (2^53)^(j 2^(13 lvl))
+            const uint64_t unit = MultPowers::get().pow(1ull << (kSkipBits * lvl));
+            uint64_t r = 1;
+            for (uint32_t j = 0; j < kSkipSize; ++j) {
+                sk[lvl * kSkipSize + j] = make_mult(r);
+                r = h_mulmod(r, unit);
+            }
+        }
+        return t;
+    }();
+    return tab;
+}
+
+// Host copy of the flat layout's workgroup multipliers (2^53)^(512 b).
+const std::vector<uint64_t>& host_block_table() {
+    static std::vector<uint64_t> tab = [] {
+        std::vector<uint64_t> t(kFlatMaxBlocks);
+        const uint64_t step = MultPowers::get().pow(kFlatPerBlock);
+        uint64_t p = 1;
+        for (uint64_t b = 0; b < kFlatMaxBlocks; ++b) {
+            t[b] = p;
+            p = h_mulmod(p, step);
+        }
+        return t;
+    }();
+    return tab;
+}
+
+// Set up tables on `dev`, which must be the current device.
+int ensure_device_current(int dev, DeviceTables** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(NN_ENODEV, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    DeviceTables& d = g_dev[dev];
+    if (!d.ready) {
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess)
+            return fail(NN_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+        if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+            return fail(NN_ENODEV, "device %d is %s, this library is built for gfx950", dev,
+                        prop.gcnArchName);
+        const std::vector<Mult>& h = host_mult_tables();
+        const std::vector<uint64_t>& hb = host_block_table();
+        const size_t mult_bytes = h.size() * sizeof(Mult);
+        const size_t blk_bytes = hb.size() * sizeof(uint64_t);
+        void* mem = nullptr;
+        e = hipMalloc(&mem, mult_bytes + blk_bytes);
+        if (e != hipSuccess) return fail(NN_ENOMEM, "hipMalloc tables: %s", hipGetErrorString(e));
+        e = hipMemcpy(mem, h.data(), mult_bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((char*)mem + mult_bytes, hb.data(), blk_bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(mem);
+            return fail(NN_EHIP, "table upload: %s", hipGetErrorString(e));
+        }
+        d.t_lo = (Mult*)mem;
+        d.t_hi = d.t_lo + kLoSize;
+        d.t_sk = d.t_hi + kHiSize;
+        d.t_blk = (uint64_t*)((char*)mem + mult_bytes);
+        d.cus = prop.multiProcessorCount;
+        d.lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
+        d.lds_per_block = (uint32_t)prop.sharedMemPerBlock;
+        d.ready = true;
+    }
+    *out = &d;
+    return NN_OK;
+}
+
+constexpr uint32_t kBatchDefaultRows = 16;
+
+}  // namespace
+
+int current_device(DeviceTables** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(NN_ENODEV, "hipGetDevice: %s", hipGetErrorString(e));
+    return ensure_device_current(dev, out);
+}
+
+// ---------------------------------------------------------------- plans --
+
+void plan_release(nn_batch_plan* p) {
+    if (p->done) {
+        (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+    }
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ws_dev) (void)hipFree(p->ws_dev);
+    if (p->ws_host) (void)hipHostFree(p->ws_host);
+    delete p;
+}
+
+int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_batch_cfg* cfg,
+                bool indexed, const uint64_t* states, nn_batch_plan** plan_out) {
+    if (!plan_out) return fail(NN_EINVAL, "plan_out is NULL");
+    if (kind != NN_OUT_U64 && kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %d unknown", kind);
+    if (max_streams == 0) return fail(NN_EINVAL, "max_streams must be positive");
+    nn_batch_cfg c = {0, 0, 0, 0, 0};
+    if (cfg) c = *cfg;
+    if (c.flags & ~(NN_CFG_TEMPORAL_STORES | NN_BATCH_NO_GRAPH))
+        return fail(NN_EINVAL, "unknown batch flags 0x%x", c.flags);
+    DeviceTables* d = nullptr;
+    int st = current_device(&d);
+    if (st) return st;
+    const KindDefaults& kd = kind_defaults(kind);
+    const uint32_t block = c.block ? c.block : kDefaultBlock;
+    if (block < 64 || block > 1024 || block % 64)
+        return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
+    const uint32_t rows = c.rows ? c.rows : kBatchDefaultRows;
+    if (rows < 1 || rows > 4096) return fail(NN_EINVAL, "rows %u: must be in [1, 4096]", rows);
+    const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
+    if (mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", mulmod);
+    uint32_t grid = c.grid;
+    if (!grid) {
+        grid = (uint32_t)((uint64_t)d->cus * kd.grid_num / kd.grid_den);
+        if (!grid) grid = 1;
+    }
+    if (grid > (1u << 20)) return fail(NN_EINVAL, "grid %u too large", grid);
+    const uint64_t tile = 2ull * block * rows;
+    // Direct batches split streams into pieces of at most kBatchMaxLen.
+    const uint64_t cap_desc = (uint64_t)max_streams + (indexed ? 0 : max_outputs / kBatchMaxLen + 1);
+    const uint64_t cap_tiles = max_outputs / tile + 2 * cap_desc;
+    if (cap_desc > 0xffffffffull || cap_tiles > 0xffffffffull)
+        return fail(NN_ERANGE, "batch capacity too large");
+
+    nn_batch_plan* p = new (std::nothrow) nn_batch_plan();
+    if (!p) return fail(NN_ENOMEM, "plan allocation");
+    (void)hipGetDevice(&p->device);
+    p->kind = kind;
+    p->indexed = indexed;
+    p->mulmod = mulmod;
+    p->block = block;
+    p->grid = grid;
+    p->rows = rows;
+    p->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
+    p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
+    p->max_streams = max_streams;
+    p->max_outputs = max_outputs;
+    p->cap_desc = (uint32_t)cap_desc;
+    p->cap_tiles = cap_tiles;
+    p->ws_bytes = sizeof(BatchHeader) + cap_desc * sizeof(BatchDesc) + cap_tiles * sizeof(uint64_t);
+    hipError_t e = hipMalloc(&p->ws_dev, p->ws_bytes);
+    if (e != hipSuccess) {
+        plan_release(p);
+        return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", p->ws_bytes, hipGetErrorString(e));
+    }
+    e = hipHostMalloc(&p->ws_host, p->ws_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        plan_release(p);
+        return fail(NN_ENOMEM, "pinned staging (%zu bytes): %s", p->ws_bytes, hipGetErrorString(e));
+    }
+    BatchHeader* hdr = (BatchHeader*)p->ws_host;
+    memset(hdr, 0, sizeof *hdr);
+    hdr->states = states;
+    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        plan_release(p);
+        return fail(NN_EHIP, "event: %s", hipGetErrorString(e));
+    }
+    p->args.ws = (const BatchHeader*)p->ws_dev;
+    p->args.rows = rows;
+    p->args.JB = make_mult(MultPowers::get().pow(2ull * block));
+    p->args.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
+    p->args.t_lo = d->t_lo;
+    p->args.t_hi = d->t_hi;
+    p->args.t_sk = d->t_sk;
+    if (p->use_graph) {
+        e = hipGraphCreate(&p->graph, 0);
+        if (e == hipSuccess)
+            e = hipGraphAddMemcpyNode1D(&p->copy_node, p->graph, nullptr, 0, p->ws_dev, p->ws_host,
+                                        sizeof(BatchHeader), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            hipKernelNodeParams kp;
+            memset(&kp, 0, sizeof kp);
+            void* params[] = {&p->args};
+            kp.func = const_cast<void*>(batch_kernel((int)mulmod, kind, p->nontemporal, indexed));
+            kp.gridDim = dim3(grid);
+            kp.blockDim = dim3(block);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = params;
+            kp.extra = nullptr;
+            e = hipGraphAddKernelNode(&p->kernel_node, p->graph, &p->copy_node, 1, &kp);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            plan_release(p);
+            return fail(NN_EHIP, "batch graph: %s", hipGetErrorString(e));
+        }
+    }
+    *plan_out = p;
+    return NN_OK;
+}
+
+int plan_wait(nn_batch_plan* p) {
+    if (!p->pending) return NN_OK;
+    hipError_t e = hipEventSynchronize(p->done);
+    if (e != hipSuccess)
+        return fail(NN_EHIP, "waiting for the previous batch: %s", hipGetErrorString(e));
+    p->pending = false;
+    return NN_OK;
+}
+
+bool plan_idle(nn_batch_plan* p) {
+    if (!p->pending) return true;
+    if (hipEventQuery(p->done) == hipSuccess) {
+        p->pending = false;
+        return true;
+    }
+    return false;
+}
+
+uint64_t plan_count_tiles(const nn_batch_plan* p, const BatchDesc* d, uint32_t nd) {
+    const uint64_t tile = 2ull * p->block * p->rows;
+    uint64_t n = 0;
+    for (uint32_t k = 0; k < nd; ++k) n += (d[k].len + (d[k].out_off & 1u) + tile - 1) / tile;
+    return n;
+}
+
+int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t stream) {
+    const uint64_t tile = 2ull * p->block * p->rows;
+    BatchHeader* hdr = (BatchHeader*)p->ws_host;
+    BatchDesc* dd = plan_staged_descs(p);
+    uint64_t* tw = (uint64_t*)(dd + nd);
+    uint64_t nt = 0;
+    for (uint32_t k = 0; k < nd; ++k) {
+        const uint64_t m = (dd[k].len + (dd[k].out_off & 1u) + tile - 1) / tile;
+        for (uint64_t j = 0; j < m; ++j) tw[nt++] = ((uint64_t)k << 32) | j;
+    }
+    hdr->out = (uint64_t*)out;
+    hdr->n_desc = nd;
+    hdr->n_tiles = (uint32_t)nt;
+    const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc) + nt * sizeof(uint64_t);
+    hipError_t e;
+    if (p->use_graph) {
+        e = hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->ws_dev, p->ws_host, bytes,
+                                              hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipGraphLaunch(p->exec, stream);
+    } else {
+        e = hipMemcpyAsync(p->ws_dev, p->ws_host, bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = launch_batch((int)p->mulmod, p->kind, p->nontemporal, p->indexed, p->grid,
+                             p->block, stream, p->args);
+    }
+    if (e != hipSuccess) return fail(NN_EHIP, "batch launch: %s", hipGetErrorString(e));
+    e = hipEventRecord(p->done, stream);
+    if (e != hipSuccess) return fail(NN_EHIP, "batch event: %s", hipGetErrorString(e));
+    p->pending = true;
+    return NN_OK;
+}
+
+}  // namespace nn

@@ -1,0 +1,191 @@
+"""Autotuner for the launch shapes of the plain and batched forms.
+
+Times candidate configurations on a workload with HIP events (median of
+repeated launches) and records the fastest in a JSON cache keyed by device
+architecture, compute-unit count, form, output kind and a size bucket.  The
+binding reads the cache through ``best_plain_cfg`` / ``best_batch_cfg``.
+
+    python -m paper_1206_1187_amd.tune --form batch --kind f64
+    python -m paper_1206_1187_amd.tune --form plain --kind u64
+"""
+import argparse
+import itertools
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+
+
+def _device_key():
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
+    return "%s/%dcu" % (arch, p.multi_processor_count)
+
+
+def _bucket(n):
+    return "2^%d" % max(0, int(math.floor(math.log2(max(1, int(n))))))
+
+
+def _key(form, kind, size):
+    return "%s/%s/%s/%s" % (_device_key(), form, kind, _bucket(size))
+
+
+def load_cache(path=CACHE):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _lookup(form, kind, size, path=CACHE):
+    cache = load_cache(path)
+    entry = cache.get(_key(form, kind, size))
+    if entry is None:
+        # nearest tuned bucket of the same device, form and kind
+        prefix = "%s/%s/%s/" % (_device_key(), form, kind)
+        best = None
+        for k, v in cache.items():
+            if k.startswith(prefix):
+                d = abs(int(k.rsplit("^", 1)[1]) - int(_bucket(size)[2:]))
+                if best is None or d < best[0]:
+                    best = (d, v)
+        entry = best[1] if best else None
+    return dict(entry["cfg"]) if entry else {}
+
+
+def best_plain_cfg(kind, count, path=CACHE):
+    """make_cfg keyword arguments tuned for ``count`` outputs, or {}."""
+    return _lookup("plain", kind, count, path)
+
+
+def best_batch_cfg(kind, total, path=CACHE):
+    """BatchPlan keyword arguments tuned for ``total`` outputs, or {}."""
+    return _lookup("batch", kind, total, path)
+
+
+def _median_ms(fn, reps, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in evs)
+    return ms[len(ms) // 2]
+
+
+def tune_plain(kind, count, reps=9, log=print):
+    import torch
+
+    import paper_1206_1187_amd as nn
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    out = torch.empty(count, dtype=dt, device="cuda")
+    s0 = nn.seed(nn.INDEX_MIN)
+    results = []
+    grids = sorted({max(1, cus * k // 8) for k in (2, 3, 4, 5, 6, 8)})
+    for mulmod, grid, ilp, unroll in itertools.product(("fp64", "shoup"), grids, (1, 2, 4),
+                                                       (2, 4, 8)):
+        kw = dict(block=256, grid=grid, mulmod=mulmod, ilp=ilp, unroll=unroll, width=2,
+                  layout="rows")
+        cfg = nn.make_cfg(**kw)
+        ms = _median_ms(lambda: nn.generate_into(s0, out, cfg=cfg), reps)
+        results.append((ms, kw))
+        log(json.dumps(dict(kw, ms=ms, GBps=8 * count / ms / 1e6)))
+    results.sort(key=lambda r: r[0])
+    return results
+
+
+def batch_workload():
+    """The batched workload: 10,000 streams, lengths log-uniform in [1, 2^22]."""
+    import numpy as np
+
+    import paper_1206_1187_amd as nn
+    from paper_1206_1187_amd import workloads as wl
+    case = wl.batched()
+    states = np.array([nn.seed(int(a)) for a in case.indices], dtype=np.uint64)
+    lengths = case.lengths
+    offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
+    return states, lengths, offsets
+
+
+def tune_batch(kind, reps=5, log=print, workload=None):
+    import torch
+
+    import paper_1206_1187_amd as nn
+    states, lengths, offsets = workload if workload is not None else batch_workload()
+    total = int(lengths.sum())
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    out = torch.empty(total, dtype=dt, device="cuda")
+    results = []
+    grids = sorted({max(1, cus * k // 8) for k in (2, 4, 6, 8, 16)})
+    for mulmod, block, rows, grid in itertools.product(("fp64", "shoup"), (256, 512),
+                                                       (4, 8, 16, 32, 64), grids):
+        kw = dict(block=block, rows=rows, grid=grid, mulmod=mulmod)
+        with nn.BatchPlan(kind, len(states), total, **kw) as plan:
+            ms = _median_ms(lambda: plan.generate(states, lengths, offsets, out), reps)
+        results.append((ms, kw))
+        log(json.dumps(dict(kw, ms=ms, GBps=8 * total / ms / 1e6)))
+    results.sort(key=lambda r: r[0])
+    return results
+
+
+def record(form, kind, size, results, path=CACHE):
+    cache = load_cache(path)
+    ms, kw = results[0]
+    cache[_key(form, kind, size)] = {
+        "cfg": kw,
+        "ms": ms,
+        "GBps": 8 * size / ms / 1e6,
+        "candidates": len(results),
+        "tuned_at": time.strftime("%Y-%m-%d"),
+    }
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return cache
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--form", choices=["plain", "batch"], required=True)
+    ap.add_argument("--kind", choices=["f64", "u64"], default="f64")
+    ap.add_argument("--count", type=int, default=1 << 30, help="plain form: outputs per launch")
+    ap.add_argument("--cache", default=CACHE)
+    args = ap.parse_args(argv)
+    import torch
+
+    import paper_1206_1187_amd as nn
+    torch.cuda.set_device(0)
+    nn.init(0)
+
+    def log(line):
+        print(line, file=sys.stderr, flush=True)
+
+    if args.form == "plain":
+        res = tune_plain(args.kind, args.count, log=log)
+        size = args.count
+    else:
+        wk = batch_workload()
+        res = tune_batch(args.kind, log=log, workload=wk)
+        size = int(wk[1].sum())
+    record(args.form, args.kind, size, res, args.cache)
+    print(json.dumps({"form": args.form, "kind": args.kind, "best": res[0][1],
+                      "ms": res[0][0], "GBps": 8 * size / res[0][0] / 1e6}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

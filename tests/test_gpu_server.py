@@ -1,0 +1,92 @@
+"""GPU tests of the served form: every served request equals the oracle on
+its window and equals the plain path run alone on the same window."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1206_1187_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1206_1187_amd as nn  # noqa: E402
+from paper_1206_1187_amd import serve  # noqa: E402
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _states(n, seed):
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(wl.INDEX_MIN, wl.INDEX_MAX, n, endpoint=True, dtype=np.int64)
+    return np.array([orc.seed(int(a)) for a in idx], dtype=np.uint64)
+
+
+def _bits(t):
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available()
+    nn.init(0)
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind", ["f64", "u64"])
+def test_served_requests_equal_oracle_and_plain_alone(kind):
+    states = _states(8, 21)
+    rng = np.random.default_rng(22)
+    reqs = [(int(rng.integers(0, 8)), int(np.floor(np.exp(rng.uniform(0, np.log(1 << 18))))))
+            for _ in range(300)] + [(3, 0), (5, 1), (5, (1 << 20) + 3)]
+    with serve.Server(states, 1 << 28, kind=kind, lanes=3, max_batch_requests=32) as srv:
+        tickets = [srv.submit(s, n) for s, n in reqs]
+        done = {}
+        while len(done) < len(reqs):
+            for c in srv.poll():
+                done[c.ticket] = c
+        pos = [0] * 8
+        for t, (s, n) in zip(tickets, reqs):
+            c = done[t]
+            assert c.status == 0 and c.position == pos[s]
+            pos[s] += n
+            got = _bits(srv.data(c)) if n else np.empty(0, dtype=np.uint64)
+            ref, _ = orc.gen(orc.skip(int(states[s]), c.position), n, kind)
+            assert np.array_equal(got, ref.view(np.uint64)), (t, s, n)
+            if 0 < n <= 1 << 16:  # alone: the plain path on the same window
+                alone, _ = nn.generate(nn.skip(int(states[s]), c.position), n, kind)
+                torch.cuda.synchronize()
+                assert np.array_equal(_bits(alone), got)
+            srv.release(t)
+        st = srv.stats()
+        assert st["pool_used"] == 0 and st["released"] == len(reqs) and st["batches"] >= 10
+
+
+def test_served_trace_slice_checked_per_request():
+    """A slice of the served workload (Poisson arrivals, sizes log-uniform in
+    [256, 2^24]) replayed in real time; each request's first and last 32
+    outputs are checked against the oracle before release."""
+    tr = wl.served()
+    n = 600
+    sl = wl.ServedTrace(tr.stream_indices, tr.t_arrive[:n], tr.stream_id[:n], tr.count[:n])
+    states = np.array([orc.seed(int(a)) for a in tr.stream_indices], dtype=np.uint64)
+    bad = []
+
+    def consumer(server, c):
+        d = server.data(c)
+        k = min(32, c.count)
+        s0 = int(states[c.stream_id])
+        head, _ = orc.gen(orc.skip(s0, c.position), k, "f64")
+        tail, _ = orc.gen(orc.skip(s0, c.position + c.count - k), k, "f64")
+        if not (np.array_equal(_bits(d[:k]), head.view(np.uint64)) and
+                np.array_equal(_bits(d[c.count - k:]), tail.view(np.uint64))):
+            bad.append(c.ticket)
+
+    with serve.Server(states, 16 << 30, lanes=2) as srv:
+        res = serve.replay_served(srv, sl, consumer=consumer, timeout_s=60)
+    _say("served slice", res)
+    assert not bad and res["failed"] == 0 and res["requests"] == n
