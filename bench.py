@@ -126,9 +126,9 @@ def batched_leg(nn, torch):
 def served_leg(nn, torch):
     """Config 5: Poisson arrivals at 20k req/s for 10 s, sizes log-uniform in
     [256, 2^24], 1,024 client streams, 64 GB output pool; the served form
-    against one nn_generate launch per request on the same trace, then a
-    load sweep (the trace's first 20,000 requests replayed 4x, 16x and 32x
-    faster)."""
+    against one nn_generate launch per request on the same trace (both
+    arrival loops native), then a load sweep (the trace's first 20,000
+    requests replayed 4x to 64x faster)."""
     import numpy as np
 
     from paper_1206_1187_amd import serve
@@ -141,20 +141,20 @@ def served_leg(nn, torch):
                        "10 s, sizes log-uniform in [256, 2^24] f64, 64 GB pool",
            "requests": int(tr.count.size), "variates": int(tr.count.sum())}
     with serve.Server(states, pool, lanes=2) as srv:
-        res["served"] = serve.replay_served(srv, tr, timeout_s=120)
-    res["plain_per_request"] = serve.replay_plain(tr, states, pool // 8, timeout_s=120)
+        res["served"] = serve.replay_served_native(srv, tr, timeout_s=120)
+    res["plain_per_request"] = serve.replay_per_request_native(tr, states, pool // 8,
+                                                               timeout_s=120)
     n = 20000
-    sl = wl.ServedTrace(tr.stream_indices, tr.t_arrive[:n], tr.stream_id[:n], tr.count[:n])
     sweep = []
-    for scale in (4, 16, 32):
+    for scale in (4, 16, 32, 64):
         with serve.Server(states, pool, lanes=2) as srv:
-            a = serve.replay_served(srv, sl, time_scale=scale, timeout_s=120)
-        b = serve.replay_plain(sl, states, pool // 8, time_scale=scale, timeout_s=120)
+            a = serve.replay_served_native(srv, tr, time_scale=scale, timeout_s=120, n=n)
+        b = serve.replay_per_request_native(tr, states, pool // 8, time_scale=scale,
+                                            timeout_s=120, n=n)
         sweep.append({"load_x": scale,
                       "served": {k: a[k] for k in ("variates_per_s", "p50_ms", "p99_ms")},
                       "plain": {k: b[k] for k in ("variates_per_s", "p50_ms", "p99_ms")}})
     res["load_sweep_first_20000"] = sweep
-    res["served"].pop("stats", None)
     torch.cuda.empty_cache()
     return res
 
@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fill ceiling and reduction comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form replay")
+    ap.add_argument("--only", choices=["batched", "served"],
+                    help="run only this leg and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (torch) five times, "
                          "to scale hardware byte counters")
@@ -230,6 +232,10 @@ def main():
         log("copied 5 x %d bytes" % (src.numel() * 8))
         return
     nn.init(0)
+    if args.only:
+        leg = batched_leg(nn, torch) if args.only == "batched" else served_leg(nn, torch)
+        print(json.dumps({args.only: leg}), flush=True)
+        return
     case = wl.plain_bulk()
     out_f = torch.empty(case.count_f64, dtype=torch.float64, device="cuda")
     out_u = torch.empty(case.count_u64, dtype=torch.uint64, device="cuda")

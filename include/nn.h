@@ -168,16 +168,18 @@ typedef struct nn_stream_desc {
     uint64_t out_offset;
 } nn_stream_desc;
 
-/* Batch configuration (0 = default).  block: threads per workgroup (a
- * multiple of 64 in [64,1024]); grid: persistent workgroups; rows: rows of
- * 2*block outputs per tile (a tile is one workgroup's unit of work, with
- * its own skip-ahead); mulmod: an nn_mulmod; flags: NN_CFG_TEMPORAL_STORES,
- * NN_BATCH_NO_GRAPH (enqueue a copy and a kernel launch instead of
- * replaying the plan's graph). */
+/* Batch configuration (0 = default).  The batch is cut into rows of
+ * 2*block outputs; each of the `grid` persistent workgroups takes a
+ * contiguous range of rows, steps its states from row to row inside a
+ * stream and skips ahead afresh where a new stream starts.
+ * block: threads per workgroup (a multiple of 64 in [64,1024]); grid:
+ * workgroups; ilp: 0 or 1 (reserved); mulmod: an nn_mulmod; flags:
+ * NN_CFG_TEMPORAL_STORES, NN_BATCH_NO_GRAPH (enqueue a copy and a kernel
+ * launch instead of replaying the plan's graph). */
 typedef struct nn_batch_cfg {
     uint32_t block;
     uint32_t grid;
-    uint32_t rows;
+    uint32_t ilp;
     uint32_t mulmod;
     uint32_t flags;
 } nn_batch_cfg;
@@ -190,8 +192,8 @@ typedef struct nn_batch_plan nn_batch_plan;
 
 /* nn_batch_plan_create -- a plan on the current device for batches of at
  * most `max_streams` streams and `max_outputs` outputs in total, writing
- * `kind` outputs.  Allocates the workspace (about 8 bytes per 2*block*rows
- * outputs plus 24 bytes per stream) in device and pinned host memory.
+ * `kind` outputs.  Allocates the workspace (40 bytes per stream, plus one
+ * per 2^24 outputs) in device and pinned host memory.
  * Errors: NN_EINVAL (kind, cfg), NN_ERANGE (capacity), NN_ENOMEM, NN_EHIP. */
 int nn_batch_plan_create(int kind, uint32_t max_streams, uint64_t max_outputs,
                          const nn_batch_cfg *cfg, nn_batch_plan **plan_out);
@@ -210,8 +212,8 @@ int nn_batch_plan_cfg(const nn_batch_plan *plan, nn_batch_cfg *cfg_out);
  * Asynchronous; the call blocks only while the plan's previous batch is
  * still copying its descriptors.  A plan serves one call at a time (calls
  * on one plan are serialised).  Errors: NN_EINVAL (states, pointers, wrong
- * device), NN_ERANGE (more streams or tiles than the plan holds; nothing is
- * enqueued), NN_EHIP. */
+ * device), NN_ERANGE (more streams or outputs than the plan holds; nothing
+ * is enqueued), NN_EHIP. */
 int nn_generate_batch(nn_batch_plan *plan, const nn_stream_desc *descs, uint32_t n,
                       void *out_dev, void *stream, uint64_t *final_states);
 
@@ -288,6 +290,35 @@ int nn_server_stats_get(nn_server *srv, nn_server_stats *out);
 /* Fake device only: advance the server clock; inject n launch failures. */
 int nn_server_set_clock(nn_server *srv, double now);
 int nn_server_inject_failures(nn_server *srv, uint32_t n);
+
+/* ------------------------------------------------------------- replay -- */
+
+/* Native load generators for measuring the served form against one launch
+ * per request on the same arrival trace (host arrays of n requests, arrival
+ * times in seconds, non-decreasing, divided by time_scale).  Both run in
+ * real time on the calling thread, release every output as soon as it is
+ * finished, and write each request's latency (seconds from its arrival to
+ * the moment its completion was observed) to latency_out[i].  timeout_s > 0
+ * bounds the run (NN_ERANGE when exceeded). */
+typedef struct nn_replay_stats {
+    double wall_s;
+    uint64_t requests, variates, failed;
+} nn_replay_stats;
+
+/* The trace through `srv` (nn_server_submit / _poll / _release). */
+int nn_server_replay(nn_server *srv, const double *t_arrive, const uint32_t *stream_id,
+                     const uint64_t *count, uint64_t n, double time_scale, double timeout_s,
+                     double *latency_out, nn_replay_stats *stats_out);
+
+/* The trace with one nn_generate launch per request on `stream`: window
+ * positions per stream in arrival order as in the server, outputs in a ring
+ * over pool_dev (pool_elems outputs of `kind`, caller-owned device memory);
+ * a request waits while the ring is full. */
+int nn_replay_per_request(const uint64_t *stream_states, uint32_t n_streams,
+                          const double *t_arrive, const uint32_t *stream_id,
+                          const uint64_t *count, uint64_t n, double time_scale, double timeout_s,
+                          void *pool_dev, uint64_t pool_elems, int kind, void *stream,
+                          double *latency_out, nn_replay_stats *stats_out);
 
 /* ------------------------------------------------------------- status -- */
 

@@ -64,7 +64,7 @@ class BatchCfg(ctypes.Structure):
     _fields_ = [
         ("block", ctypes.c_uint32),
         ("grid", ctypes.c_uint32),
-        ("rows", ctypes.c_uint32),
+        ("ilp", ctypes.c_uint32),
         ("mulmod", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
     ]
@@ -162,6 +162,26 @@ _SERVER_SIGNATURES = {
 }
 
 
+
+
+class ReplayStats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("requests", ctypes.c_uint64),
+                ("variates", ctypes.c_uint64), ("failed", ctypes.c_uint64)]
+
+
+_pd = ctypes.POINTER(ctypes.c_double)
+_SERVER_SIGNATURES.update({
+    "nn_server_replay": (ctypes.c_int, [ctypes.c_void_p, _pd, ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
+                                        ctypes.c_double, ctypes.c_double, _pd,
+                                        ctypes.POINTER(ReplayStats)]),
+    "nn_replay_per_request": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32, _pd,
+                                             ctypes.POINTER(ctypes.c_uint32),
+                                             ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                             ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, _pd,
+                                             ctypes.POINTER(ReplayStats)]),
+})
 SIGNATURES.update(_SERVER_SIGNATURES)
 
 _lib = None

@@ -1,13 +1,15 @@
 // nn_batch.hip -- persistent kernel of the batched form.
 //
-// Each stream is cut into tiles of rows*2*block outputs.  Workgroup w
-// processes tiles w, w + grid, w + 2*grid, ... of the batch (so the tiles
-// written at any moment are neighbours, as in the plain row layout).  Inside
-// a tile, lane l owns the aligned output pair (x_a, x_b) of each row and
-// steps both states by (2^53)^(2*block) per row.  Pairs are aligned to the
-// global output index, so the 16-byte stores stay aligned for any stream
-// offset: a stream at an odd offset starts and may end with a half pair.
-// Element x of a window is src * (2^53)^(pos + x + 1).
+// The batch is a sequence of rows of 2*block outputs (each window cut into
+// ceil((len + s)/(2*block)) rows, s = 1 for windows at odd output offsets).
+// Workgroup w processes the contiguous row range
+// [n_rows*w/grid, n_rows*(w+1)/grid): inside a window it keeps stepping its
+// lanes' states by (2^53)^(2*block) per row, exactly as the plain row
+// kernel, and it skips ahead afresh only when it enters a new window.  Lane
+// l owns the aligned output pair (x_a, x_b) of each row; pairs are aligned
+// to the global output index, so the 16-byte stores stay aligned for any
+// window offset (a window at an odd offset starts, and may end, with a half
+// pair).  Element x of a window is src * (2^53)^(pos + x + 1).
 #include <hip/hip_runtime.h>
 
 #include "nn_batch.hpp"
@@ -26,54 +28,86 @@ __device__ __forceinline__ typename V::S skip_any(uint64_t src, uint64_t k,
     return z;
 }
 
+// Stores row r's pair of lane l: x_b = 2(jr*B + l) + 1 - s, x_a = x_b - 1.
+template <class V, int KIND, bool NT>
+__device__ __forceinline__ void store_pair(uint64_t* out, const BatchDesc& D, uint64_t xb,
+                                           typename V::S za, typename V::S zb) {
+    const bool vb = xb < D.len;
+    const bool va = xb >= 1 && xb - 1 < D.len;
+    uint64_t* const p = out + (D.out_off + xb - 1);  // global index of x_a, even
+    if (va && vb) {
+        u64x2 v;
+        v.x = out_bits<V, KIND>(za);
+        v.y = out_bits<V, KIND>(zb);
+        put<NT>(reinterpret_cast<u64x2*>(p), v);
+    } else if (vb) {
+        put<NT>(p + 1, out_bits<V, KIND>(zb));
+    } else if (va) {
+        put<NT>(p, out_bits<V, KIND>(za));
+    }
+}
+
+// Two rows in flight: (za, zb) hold row r and (zc, zd) row r + 1 of the
+// current window; all four advance by JB^2 per pair of rows.
 template <class V, int KIND, bool NT, bool INDEXED>
 __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
     const BatchHeader* hdr = a.ws;
     const uint32_t n_desc = hdr->n_desc;
-    const uint32_t n_tiles = hdr->n_tiles;
+    const uint64_t n_rows = hdr->n_rows;
     uint64_t* const out = hdr->out;
     const BatchDesc* __restrict__ desc = reinterpret_cast<const BatchDesc*>(hdr + 1);
-    const uint64_t* __restrict__ tiles = reinterpret_cast<const uint64_t*>(desc + n_desc);
     const uint32_t B = blockDim.x;
     const uint32_t l = threadIdx.x;
-    const uint64_t S = 2ull * B * a.rows;  // tile size in the padded index
-
-    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const uint64_t w = tiles[t];
-        const BatchDesc D = desc[w >> 32];
-        const uint64_t j = (uint32_t)w;
-        // Padded index p = x + s, s = 1 for streams at odd output offsets.
-        const uint32_t s = (uint32_t)(D.out_off & 1u);
-        const uint64_t P0 = j * S;
-        const uint64_t Lp = D.len + s;
-        const uint64_t P1 = P0 + S < Lp ? P0 + S : Lp;
-        const uint32_t rows = (uint32_t)((P1 - P0 + 2ull * B - 1) / (2ull * B));
-        // Row r, lane l: x_b = P0 + 2(rB + l) + 1 - s, x_a = x_b - 1.
-        const uint64_t xb0 = P0 + 2ull * l + 1 - s;
-        uint64_t* const pair0 = out + (D.out_off - s) + P0 + 2ull * l;  // global index of x_a, even
-        typename V::S zb;
-        if constexpr (INDEXED)
-            zb = skip_any<V>(hdr->states[D.src], D.pos + xb0 + 1, a.t_sk);
+    const uint64_t r0 = n_rows * blockIdx.x / gridDim.x;
+    const uint64_t r1 = n_rows * (blockIdx.x + 1) / gridDim.x;
+    if (r0 >= r1 || n_desc == 0) return;
+    // The last window whose first row is at or before r0 (binary search).
+    uint32_t lo = 0, hi = n_desc - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (desc[mid].row_start <= r0)
+            lo = mid;
         else
-            zb = thread_start<V>(D.src, xb0 + 1, a.t_lo, a.t_hi);
-        typename V::S za = V::mul(zb, a.Minv);
-        for (uint32_t r = 0; r < rows; ++r) {
-            const uint64_t xb = xb0 + 2ull * r * B;
-            const bool vb = xb < D.len;
-            const bool va = xb >= 1 && xb - 1 < D.len;
-            uint64_t* const p = pair0 + 2ull * r * B;
-            if (va && vb) {
-                u64x2 v;
-                v.x = out_bits<V, KIND>(za);
-                v.y = out_bits<V, KIND>(zb);
-                put<NT>(reinterpret_cast<u64x2*>(p), v);
-            } else if (vb) {
-                put<NT>(p + 1, out_bits<V, KIND>(zb));
-            } else if (va) {
-                put<NT>(p, out_bits<V, KIND>(za));
-            }
-            za = V::mul(za, a.JB);
-            zb = V::mul(zb, a.JB);
+            hi = mid - 1;
+    }
+    uint32_t d = lo;
+    BatchDesc D = desc[d];
+    uint64_t next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
+    bool fresh = true;
+    typename V::S za = V::load(1), zb = V::load(1), zc = V::load(1), zd = V::load(1);
+    for (uint64_t r = r0; r < r1;) {
+        if (r >= next_start) {  // enter the next window (empty ones have no rows)
+            do {
+                ++d;
+                next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
+            } while (r >= next_start);
+            D = desc[d];
+            fresh = true;
+        }
+        const uint32_t s = (uint32_t)(D.out_off & 1u);
+        const uint64_t xb = 2ull * ((r - D.row_start) * B + l) + 1 - s;
+        if (fresh) {
+            // src * (2^53)^(pos + x_b + 1): the window's element x_b.
+            if constexpr (INDEXED)
+                zb = skip_any<V>(hdr->states[D.src], D.pos + xb + 1, a.t_sk);
+            else
+                zb = skip_any<V>(D.src, D.pos + xb + 1, a.t_sk);
+            za = V::mul(zb, a.Minv);
+            zc = V::mul(za, a.JB);
+            zd = V::mul(zb, a.JB);
+            fresh = false;
+        }
+        const uint64_t seg_end = next_start < r1 ? next_start : r1;
+        store_pair<V, KIND, NT>(out, D, xb, za, zb);
+        if (r + 1 < seg_end) {
+            store_pair<V, KIND, NT>(out, D, xb + 2ull * B, zc, zd);
+            za = V::mul(za, a.JB2);
+            zb = V::mul(zb, a.JB2);
+            zc = V::mul(zc, a.JB2);
+            zd = V::mul(zd, a.JB2);
+            r += 2;
+        } else {
+            r += 1;  // the window or the range ends here
         }
     }
 }

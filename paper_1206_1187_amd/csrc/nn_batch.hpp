@@ -12,29 +12,33 @@ namespace nn {
 
 // One stream window after host preparation: `len` outputs written from
 // element `out_off` of the output; output x is src * (2^53)^(pos + x + 1).
-//  * direct batches: src = the state, pos = 0 (streams longer than
-//    kBatchMaxLen are split by the host, each piece with its own state);
+//  * direct batches: src = the state, pos = the piece's offset in the
+//    stream (streams longer than kBatchMaxLen are split by the host);
 //  * indexed batches (the served form): src = a row of the device-resident
 //    stream-state table, pos = the window's position in that stream
 //    (reduced modulo the period).
+// The batch is cut into rows of 2*block outputs aligned to global output
+// pairs; row_start is the index of the window's first row in the batch
+// (a prefix sum of ceil((len + (out_off & 1)) / (2*block))).
 struct BatchDesc {
     uint64_t src;
     uint64_t pos;
     uint64_t len;
     uint64_t out_off;
+    uint64_t row_start;
 };
 
 constexpr uint64_t kBatchMaxLen = 1ull << 24;
 
 // Device workspace image, uploaded per batch as one contiguous block:
-// header, then n_desc descriptors, then n_tiles tile words
-// (desc index << 32 | tile index within the descriptor).
+// the header, then n_desc descriptors.
 struct BatchHeader {
     uint64_t* out;
     uint32_t n_desc;
-    uint32_t n_tiles;
+    uint32_t pad0;
+    uint64_t n_rows;
     const uint64_t* states;  // indexed batches: the stream-state table
-    uint64_t pad[5];
+    uint64_t pad[4];
 };
 static_assert(sizeof(BatchHeader) == 64, "header is one 64-byte line");
 
@@ -47,8 +51,8 @@ constexpr uint32_t kSkipLevels = 4;
 // Kernel arguments (fixed for the life of a plan).
 struct BatchArgs {
     const BatchHeader* ws;  // device workspace
-    uint32_t rows;          // rows of 2*block outputs per tile
     Mult JB;                // (2^53)^(2*block): one row
+    Mult JB2;               // (2^53)^(4*block): two rows
     Mult Minv;              // (2^53)^-1
     const Mult* t_lo;
     const Mult* t_hi;

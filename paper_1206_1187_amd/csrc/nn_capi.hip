@@ -276,7 +276,7 @@ int nn_batch_plan_cfg(const nn_batch_plan* plan, nn_batch_cfg* cfg_out) {
     if (!plan || !cfg_out) return fail(NN_EINVAL, "NULL argument");
     cfg_out->block = plan->block;
     cfg_out->grid = plan->grid;
-    cfg_out->rows = plan->rows;
+    cfg_out->ilp = 1;
     cfg_out->mulmod = plan->mulmod;
     cfg_out->flags = (plan->nontemporal ? 0u : NN_CFG_TEMPORAL_STORES) |
                      (plan->use_graph ? 0u : NN_BATCH_NO_GRAPH);
@@ -288,8 +288,7 @@ int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t
     if (!plan) return fail(NN_EINVAL, "plan is NULL");
     if (plan->indexed) return fail(NN_EINVAL, "plan belongs to a server");
     if (n && !descs) return fail(NN_EINVAL, "descs is NULL");
-    uint64_t total = 0, pieces = 0, tiles = 0;
-    const uint64_t tile = 2ull * plan->block * plan->rows;
+    uint64_t total = 0, pieces = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const nn_stream_desc& q = descs[i];
         if (!valid_state(q.state))
@@ -299,11 +298,7 @@ int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t
             return fail(NN_ERANGE, "stream %u: output range overflows", i);
         total += q.length;
         if (total < q.length) return fail(NN_ERANGE, "total outputs overflow");
-        for (uint64_t off = 0; off < q.length; off += kBatchMaxLen) {
-            const uint64_t len = q.length - off < kBatchMaxLen ? q.length - off : kBatchMaxLen;
-            tiles += (len + ((q.out_offset + off) & 1u) + tile - 1) / tile;
-            ++pieces;
-        }
+        pieces += (q.length + kBatchMaxLen - 1) / kBatchMaxLen;
     }
     if (total) {
         if (!out_dev) return fail(NN_EINVAL, "output pointer is NULL");
@@ -315,10 +310,9 @@ int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t
     if (total > plan->max_outputs)
         return fail(NN_ERANGE, "batch of %llu outputs, plan holds %llu", (unsigned long long)total,
                     (unsigned long long)plan->max_outputs);
-    if (pieces > plan->cap_desc || tiles > plan->cap_tiles)
-        return fail(NN_ERANGE, "batch needs %llu pieces and %llu tiles, plan holds %u and %llu",
-                    (unsigned long long)pieces, (unsigned long long)tiles, plan->cap_desc,
-                    (unsigned long long)plan->cap_tiles);
+    if (pieces > plan->cap_desc)
+        return fail(NN_ERANGE, "batch needs %llu stream pieces, plan holds %u",
+                    (unsigned long long)pieces, plan->cap_desc);
     std::lock_guard<std::mutex> lock(plan->mu);
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
@@ -336,8 +330,8 @@ int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t
         const nn_stream_desc& q = descs[i];
         for (uint64_t off = 0; off < q.length; off += kBatchMaxLen) {
             const uint64_t len = q.length - off < kBatchMaxLen ? q.length - off : kBatchMaxLen;
-            dd[nd].src = h_skip(q.state, off);  // the state before the piece's first output
-            dd[nd].pos = 0;
+            dd[nd].src = q.state;  // the device skips ahead by pos
+            dd[nd].pos = off % kPeriod;
             dd[nd].len = len;
             dd[nd].out_off = q.out_offset + off;
             ++nd;

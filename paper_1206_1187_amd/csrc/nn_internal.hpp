@@ -46,12 +46,11 @@ struct nn_batch_plan {
     int device = 0;
     int kind = 0;
     bool indexed = false;
-    uint32_t mulmod = 0, block = 0, grid = 0, rows = 0;
+    uint32_t mulmod = 0, block = 0, grid = 0;
     bool nontemporal = true, use_graph = true;
     uint32_t max_streams = 0;
     uint64_t max_outputs = 0;
     uint32_t cap_desc = 0;
-    uint64_t cap_tiles = 0;
     size_t ws_bytes = 0;
     void* ws_dev = nullptr;
     void* ws_host = nullptr;  // pinned staging, same layout as ws_dev
@@ -80,11 +79,10 @@ bool plan_idle(nn_batch_plan* p);
 inline BatchDesc* plan_staged_descs(nn_batch_plan* p) {
     return reinterpret_cast<BatchDesc*>(reinterpret_cast<BatchHeader*>(p->ws_host) + 1);
 }
-// Number of tiles `nd` staged descriptors need.
-uint64_t plan_count_tiles(const nn_batch_plan* p, const BatchDesc* d, uint32_t nd);
-// Builds the tile table for the `nd` staged descriptors, uploads and
-// launches on `stream`, and records the plan's completion event.  The
-// caller checked capacities (plan_count_tiles) and holds p->mu.
+// Fills in the row prefix of the `nd` staged descriptors (their src, pos,
+// len and out_off set by the caller), uploads them and launches on
+// `stream`, and records the plan's completion event.  The caller checked
+// nd <= p->cap_desc and holds p->mu.
 int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t stream);
 
 }  // namespace nn

@@ -142,8 +142,6 @@ int ensure_device_current(int dev, DeviceTables** out) {
     return NN_OK;
 }
 
-constexpr uint32_t kBatchDefaultRows = 16;
-
 }  // namespace
 
 int current_device(DeviceTables** out) {
@@ -183,8 +181,7 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     const uint32_t block = c.block ? c.block : kDefaultBlock;
     if (block < 64 || block > 1024 || block % 64)
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
-    const uint32_t rows = c.rows ? c.rows : kBatchDefaultRows;
-    if (rows < 1 || rows > 4096) return fail(NN_EINVAL, "rows %u: must be in [1, 4096]", rows);
+    if (c.ilp > 1) return fail(NN_EINVAL, "batch ilp %u: only 1 is supported", c.ilp);
     const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
     if (mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", mulmod);
     uint32_t grid = c.grid;
@@ -193,12 +190,9 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
         if (!grid) grid = 1;
     }
     if (grid > (1u << 20)) return fail(NN_EINVAL, "grid %u too large", grid);
-    const uint64_t tile = 2ull * block * rows;
     // Direct batches split streams into pieces of at most kBatchMaxLen.
     const uint64_t cap_desc = (uint64_t)max_streams + (indexed ? 0 : max_outputs / kBatchMaxLen + 1);
-    const uint64_t cap_tiles = max_outputs / tile + 2 * cap_desc;
-    if (cap_desc > 0xffffffffull || cap_tiles > 0xffffffffull)
-        return fail(NN_ERANGE, "batch capacity too large");
+    if (cap_desc > 0xffffffffull) return fail(NN_ERANGE, "batch capacity too large");
 
     nn_batch_plan* p = new (std::nothrow) nn_batch_plan();
     if (!p) return fail(NN_ENOMEM, "plan allocation");
@@ -208,14 +202,12 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->mulmod = mulmod;
     p->block = block;
     p->grid = grid;
-    p->rows = rows;
     p->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
     p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
     p->max_streams = max_streams;
     p->max_outputs = max_outputs;
     p->cap_desc = (uint32_t)cap_desc;
-    p->cap_tiles = cap_tiles;
-    p->ws_bytes = sizeof(BatchHeader) + cap_desc * sizeof(BatchDesc) + cap_tiles * sizeof(uint64_t);
+    p->ws_bytes = sizeof(BatchHeader) + cap_desc * sizeof(BatchDesc);
     hipError_t e = hipMalloc(&p->ws_dev, p->ws_bytes);
     if (e != hipSuccess) {
         plan_release(p);
@@ -235,8 +227,8 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
         return fail(NN_EHIP, "event: %s", hipGetErrorString(e));
     }
     p->args.ws = (const BatchHeader*)p->ws_dev;
-    p->args.rows = rows;
     p->args.JB = make_mult(MultPowers::get().pow(2ull * block));
+    p->args.JB2 = make_mult(MultPowers::get().pow(4ull * block));
     p->args.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
     p->args.t_lo = d->t_lo;
     p->args.t_hi = d->t_hi;
@@ -286,27 +278,19 @@ bool plan_idle(nn_batch_plan* p) {
     return false;
 }
 
-uint64_t plan_count_tiles(const nn_batch_plan* p, const BatchDesc* d, uint32_t nd) {
-    const uint64_t tile = 2ull * p->block * p->rows;
-    uint64_t n = 0;
-    for (uint32_t k = 0; k < nd; ++k) n += (d[k].len + (d[k].out_off & 1u) + tile - 1) / tile;
-    return n;
-}
-
 int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t stream) {
-    const uint64_t tile = 2ull * p->block * p->rows;
+    const uint64_t row = 2ull * p->block;
     BatchHeader* hdr = (BatchHeader*)p->ws_host;
     BatchDesc* dd = plan_staged_descs(p);
-    uint64_t* tw = (uint64_t*)(dd + nd);
-    uint64_t nt = 0;
+    uint64_t rows = 0;
     for (uint32_t k = 0; k < nd; ++k) {
-        const uint64_t m = (dd[k].len + (dd[k].out_off & 1u) + tile - 1) / tile;
-        for (uint64_t j = 0; j < m; ++j) tw[nt++] = ((uint64_t)k << 32) | j;
+        dd[k].row_start = rows;
+        rows += (dd[k].len + (dd[k].out_off & 1u) + row - 1) / row;
     }
     hdr->out = (uint64_t*)out;
     hdr->n_desc = nd;
-    hdr->n_tiles = (uint32_t)nt;
-    const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc) + nt * sizeof(uint64_t);
+    hdr->n_rows = rows;
+    const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc);
     hipError_t e;
     if (p->use_graph) {
         e = hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->ws_dev, p->ws_host, bytes,

@@ -284,6 +284,7 @@ bool launch(nn_server* s) {
                 dd[nd].pos = r.pos;
                 dd[nd].len = r.count;
                 dd[nd].out_off = r.pool_off / 8;
+                dd[nd].row_start = 0;
                 ++nd;
             }
             status = plan_launch_staged(lane->plan, nd, s->pool, lane->stream);
@@ -535,6 +536,154 @@ int nn_server_inject_failures(nn_server* s, uint32_t n) {
     std::lock_guard<std::mutex> lock(s->mu);
     if (!s->fake) return fail(NN_EINVAL, "failures are injectable on the fake device only");
     s->inject_failures = n;
+    return ok();
+}
+
+// --------------------------------------------------------------- replay --
+
+static int replay_check(const double* t_arrive, const uint32_t* stream_id, const uint64_t* count,
+                        uint64_t n, double time_scale, double* latency_out) {
+    if (n && (!t_arrive || !stream_id || !count || !latency_out))
+        return fail(NN_EINVAL, "NULL trace array");
+    if (!(time_scale > 0)) return fail(NN_EINVAL, "time_scale must be positive");
+    for (uint64_t i = 1; i < n; ++i)
+        if (t_arrive[i] < t_arrive[i - 1]) return fail(NN_EINVAL, "arrival times must not decrease");
+    return NN_OK;
+}
+
+int nn_server_replay(nn_server* s, const double* t_arrive, const uint32_t* stream_id,
+                     const uint64_t* count, uint64_t n, double time_scale, double timeout_s,
+                     double* latency_out, nn_replay_stats* stats_out) {
+    if (!s) return fail(NN_EINVAL, "NULL server");
+    int st = replay_check(t_arrive, stream_id, count, n, time_scale, latency_out);
+    if (st) return st;
+    if (s->fake) return fail(NN_EINVAL, "replay runs in real time: not on the fake device");
+    std::vector<nn_completion> buf(1024);
+    uint64_t first_ticket = 0, i = 0, done = 0, failed = 0, variates = 0;
+    const double t0 = s->now();
+    while (done < n) {
+        const double now = s->now() - t0;
+        while (i < n && t_arrive[i] / time_scale <= now) {
+            uint64_t tk = 0;
+            st = nn_server_submit(s, stream_id[i], count[i], &tk);
+            if (st) return st;
+            if (i == 0) first_ticket = tk;
+            ++i;
+        }
+        uint32_t got = 0;
+        st = nn_server_poll(s, buf.data(), (uint32_t)buf.size(), &got);
+        if (st) return st;
+        for (uint32_t k = 0; k < got; ++k) {
+            const nn_completion& c = buf[k];
+            const uint64_t idx = c.ticket - first_ticket;
+            latency_out[idx] = c.t_done - t0 - t_arrive[idx] / time_scale;
+            if (c.status != NN_OK) ++failed;
+            variates += c.count;
+            st = nn_server_release(s, c.ticket);
+            if (st) return st;
+            ++done;
+        }
+        if (timeout_s > 0 && s->now() - t0 > timeout_s)
+            return fail(NN_ERANGE, "replay timed out with %llu of %llu requests done",
+                        (unsigned long long)done, (unsigned long long)n);
+    }
+    if (stats_out) {
+        stats_out->wall_s = s->now() - t0;
+        stats_out->requests = n;
+        stats_out->variates = variates;
+        stats_out->failed = failed;
+    }
+    return ok();
+}
+
+int nn_replay_per_request(const uint64_t* stream_states, uint32_t n_streams,
+                          const double* t_arrive, const uint32_t* stream_id, const uint64_t* count,
+                          uint64_t n, double time_scale, double timeout_s, void* pool_dev,
+                          uint64_t pool_elems, int kind, void* stream, double* latency_out,
+                          nn_replay_stats* stats_out) {
+    int st = replay_check(t_arrive, stream_id, count, n, time_scale, latency_out);
+    if (st) return st;
+    if (!stream_states || !n_streams) return fail(NN_EINVAL, "no streams");
+    if (!pool_dev || (uintptr_t)pool_dev % 8) return fail(NN_EINVAL, "bad pool");
+    for (uint64_t k = 0; k < n; ++k) {
+        if (stream_id[k] >= n_streams) return fail(NN_EINVAL, "request %llu: unknown stream",
+                                                    (unsigned long long)k);
+        if (count[k] > pool_elems) return fail(NN_ERANGE, "request %llu larger than the pool",
+                                               (unsigned long long)k);
+    }
+    std::vector<uint64_t> pos(n_streams, 0);
+    struct Flight {
+        hipEvent_t ev;
+        uint64_t idx, used;
+    };
+    std::deque<Flight> flights;
+    std::vector<hipEvent_t> free_events;
+    uint64_t head = 0, used = 0, i = 0, done = 0, variates = 0;
+    uint64_t* pool = (uint64_t*)pool_dev;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now = [&] {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    };
+    st = NN_OK;
+    while (done < n && st == NN_OK) {
+        const double t = now();
+        while (i < n && t_arrive[i] / time_scale <= t) {
+            const uint64_t c = count[i];
+            uint64_t start = head, waste = 0;
+            if (head + c > pool_elems) {
+                start = 0;
+                waste = pool_elems - head;
+            }
+            if (used + waste + c > pool_elems) break;  // wait for the oldest to finish
+            uint64_t state = h_skip(stream_states[stream_id[i]], pos[stream_id[i]]);
+            pos[stream_id[i]] = (pos[stream_id[i]] + c) % kPeriod;
+            if (c) {
+                st = nn_generate_ex(&state, c, pool + start, kind, stream, nullptr);
+                if (st) break;
+            }
+            hipEvent_t ev;
+            if (free_events.empty()) {
+                if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                    st = fail(NN_EHIP, "event creation");
+                    break;
+                }
+            } else {
+                ev = free_events.back();
+                free_events.pop_back();
+            }
+            if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+                st = fail(NN_EHIP, "event record");
+                break;
+            }
+            flights.push_back({ev, i, waste + c});
+            used += waste + c;
+            head = start + c;
+            ++i;
+        }
+        while (!flights.empty() && hipEventQuery(flights.front().ev) == hipSuccess) {
+            const Flight f = flights.front();
+            flights.pop_front();
+            latency_out[f.idx] = now() - t_arrive[f.idx] / time_scale;
+            variates += count[f.idx];
+            used -= f.used;
+            free_events.push_back(f.ev);
+            ++done;
+        }
+        if (timeout_s > 0 && now() > timeout_s) {
+            st = fail(NN_ERANGE, "replay timed out with %llu of %llu requests done",
+                      (unsigned long long)done, (unsigned long long)n);
+        }
+    }
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    for (const Flight& f : flights) (void)hipEventDestroy(f.ev);
+    for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+    if (st) return st;
+    if (stats_out) {
+        stats_out->wall_s = now();
+        stats_out->requests = n;
+        stats_out->variates = variates;
+        stats_out->failed = 0;
+    }
     return ok();
 }
 

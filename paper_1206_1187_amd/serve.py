@@ -39,8 +39,8 @@ class Server:
         mulmod = batch_kw.get("mulmod", 0)
         if isinstance(mulmod, str):
             mulmod = MULMOD_NAMES[mulmod]
-        batch = BatchCfg(int(batch_kw.get("block", 0)), int(batch_kw.get("grid", 0)),
-                         int(batch_kw.get("rows", 0)), int(mulmod), 0)
+        batch = BatchCfg(int(batch_kw.get("block", 0)), int(batch_kw.get("grid", 0)), 0,
+                         int(mulmod), 0)
         self.pool_bytes = int(pool_bytes) & ~255
         self.pool = None
         pool_ptr = None
@@ -225,3 +225,56 @@ def replay_plain(trace, stream_states, pool_elems, kind="f64", time_scale=1.0, t
     res = {"requests": n, "variates": total, "wall_s": wall, "variates_per_s": total / wall}
     res.update(_percentiles(lat))
     return res
+
+
+def _trace_arrays(trace, n=None):
+    t = np.ascontiguousarray(trace.t_arrive[:n], dtype=np.float64)
+    s = np.ascontiguousarray(trace.stream_id[:n], dtype=np.uint32)
+    c = np.ascontiguousarray(trace.count[:n], dtype=np.uint64)
+    return t, s, c
+
+
+def _result(lat, st):
+    res = {"requests": int(st.requests), "variates": int(st.variates), "wall_s": st.wall_s,
+           "variates_per_s": st.variates / st.wall_s if st.wall_s > 0 else 0.0,
+           "failed": int(st.failed)}
+    res.update(_percentiles(lat))
+    return res
+
+
+def replay_served_native(server, trace, time_scale=1.0, timeout_s=0.0, n=None):
+    """``replay_served`` with the arrival loop in the library (no Python in
+    the loop); outputs are released as soon as they are reported."""
+    t, s, c = _trace_arrays(trace, n)
+    lat = np.zeros(t.size, dtype=np.float64)
+    st = _native.ReplayStats()
+    pd = ctypes.POINTER(ctypes.c_double)
+    _native.check(_lib().nn_server_replay(
+        server._h, t.ctypes.data_as(pd), s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+        c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), t.size, float(time_scale),
+        float(timeout_s), lat.ctypes.data_as(pd), ctypes.byref(st)))
+    return _result(lat, st)
+
+
+def replay_per_request_native(trace, stream_states, pool_elems, kind="f64", time_scale=1.0,
+                              timeout_s=0.0, n=None):
+    """One nn_generate launch per request on torch's current stream, with the
+    arrival loop in the library."""
+    import torch
+    t, s, c = _trace_arrays(trace, n)
+    states = np.ascontiguousarray(stream_states, dtype=np.uint64)
+    pool = torch.empty(int(pool_elems), dtype=torch.float64 if kind == "f64" else torch.uint64,
+                       device="cuda")
+    lat = np.zeros(t.size, dtype=np.float64)
+    st = _native.ReplayStats()
+    pd = ctypes.POINTER(ctypes.c_double)
+    p64 = ctypes.POINTER(ctypes.c_uint64)
+    _native.check(_lib().nn_replay_per_request(
+        states.ctypes.data_as(p64), states.size, t.ctypes.data_as(pd),
+        s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), c.ctypes.data_as(p64), t.size,
+        float(time_scale), float(timeout_s), ctypes.c_void_p(pool.data_ptr()), pool.numel(),
+        NN_OUT_F64 if kind == "f64" else NN_OUT_U64,
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), lat.ctypes.data_as(pd),
+        ctypes.byref(st)))
+    del pool
+    return _result(lat, st)

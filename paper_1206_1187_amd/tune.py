@@ -130,10 +130,10 @@ def tune_batch(kind, reps=5, log=print, workload=None):
     dt = torch.float64 if kind == "f64" else torch.uint64
     out = torch.empty(total, dtype=dt, device="cuda")
     results = []
-    grids = sorted({max(1, cus * k // 8) for k in (2, 4, 6, 8, 16)})
-    for mulmod, block, rows, grid in itertools.product(("fp64", "shoup"), (256, 512),
-                                                       (4, 8, 16, 32, 64), grids):
-        kw = dict(block=block, rows=rows, grid=grid, mulmod=mulmod)
+    grids = sorted({max(1, cus * k // 8) for k in (1, 2, 3, 4, 5, 6, 8, 12, 16)})
+    for mulmod, block, grid in itertools.product(("fp64", "shoup", "barrett", "montgomery"),
+                                                 (128, 256, 512), grids):
+        kw = dict(block=block, grid=grid, mulmod=mulmod)
         with nn.BatchPlan(kind, len(states), total, **kw) as plan:
             ms = _median_ms(lambda: plan.generate(states, lengths, offsets, out), reps)
         results.append((ms, kw))

@@ -74,11 +74,11 @@ LENGTHS = [0, 1, 2, 3, 4, 63, 64, 65, 511, 512, 513, 1023, 1024, 1025, 8191, 819
 def test_batch_bit_exact_mixed_lengths(kind, mulmod):
     states, lengths, offsets, total = _mixed_batch(11, LENGTHS)
     dt = torch.float64 if kind == "f64" else torch.uint64
-    for block, rows, grid, graph in [(256, 16, 0, True), (64, 1, 3, False), (1024, 3, 7, True),
-                                     (128, 64, 1, True)]:
-        _say("batch", kind, mulmod, block, rows, grid, graph)
+    for block, grid, graph in [(256, 0, True), (64, 3, False), (1024, 7, True), (128, 1, True),
+                               (64, 1000, True)]:
+        _say("batch", kind, mulmod, block, grid, graph)
         buf = _sentinel(total)
-        with nn.BatchPlan(kind, 64, total, block=block, rows=rows, grid=grid, mulmod=mulmod,
+        with nn.BatchPlan(kind, 64, total, block=block, grid=grid, mulmod=mulmod,
                           graph=graph) as plan:
             fin = plan.generate(states, lengths, offsets, buf.view(dt), final_states=True)
             torch.cuda.synchronize()
@@ -91,7 +91,7 @@ def test_graph_replays_with_eager_work_between():
     """Replay one plan's graph many times with other work and syncs in
     between; every replay must equal the oracle."""
     kind = "f64"
-    with nn.BatchPlan(kind, 64, 1 << 22, rows=8) as plan:
+    with nn.BatchPlan(kind, 64, 1 << 22, grid=37) as plan:
         for rep in range(6):
             states, lengths, offsets, total = _mixed_batch(100 + rep, LENGTHS[rep:])
             buf = _sentinel(total)
@@ -107,7 +107,7 @@ def test_graph_replays_with_eager_work_between():
 def test_back_to_back_batches_without_sync():
     """Several batches of one plan enqueued before any host synchronisation."""
     bufs, cases = [], []
-    with nn.BatchPlan("u64", 64, 1 << 21, rows=4) as plan:
+    with nn.BatchPlan("u64", 64, 1 << 21, block=512) as plan:
         for rep in range(5):
             states, lengths, offsets, total = _mixed_batch(200 + rep, LENGTHS)
             buf = _sentinel(total)
@@ -157,7 +157,7 @@ def test_batch_errors_enqueue_nothing():
         good = orc.seed(wl.INDEX_MIN)
         with pytest.raises(nn.NNError):  # too many streams
             plan.generate([good] * 3, [10] * 3, [0, 10, 20], out.view(torch.float64))
-        with pytest.raises(nn.NNError):  # too many outputs / tiles
+        with pytest.raises(nn.NNError):  # too many outputs
             plan.generate([good], [19_999], [0], out.view(torch.float64))
         with pytest.raises(nn.NNError):  # invalid state
             plan.generate([3], [10], [0], out.view(torch.float64))
