@@ -169,21 +169,31 @@ typedef struct nn_stream_desc {
 } nn_stream_desc;
 
 /* Batch configuration (0 = default).  The batch is cut into rows of
- * 2*block outputs; each of the `grid` persistent workgroups takes a
- * contiguous range of rows, steps its states from row to row inside a
- * stream and skips ahead afresh where a new stream starts.
+ * 2*block outputs handed to `grid` persistent workgroups; a workgroup steps
+ * its states while a stream continues and skips ahead afresh where a new
+ * one starts.  By default the workgroups form clusters of `cluster`
+ * consecutive workgroups: each cluster takes a contiguous range of rows and
+ * its members take every cluster-th row of it (cluster 1: each workgroup a
+ * contiguous range).
  * block: threads per workgroup (a multiple of 64 in [64,1024]); grid:
- * workgroups; ilp: 0 or 1 (reserved); mulmod: an nn_mulmod; flags:
- * NN_CFG_TEMPORAL_STORES, NN_BATCH_NO_GRAPH (enqueue a copy and a kernel
- * launch instead of replaying the plan's graph). */
+ * workgroups (a multiple of cluster); cluster: 1..64; mulmod: an
+ * nn_mulmod; flags: NN_CFG_TEMPORAL_STORES, NN_BATCH_NO_GRAPH (enqueue a
+ * copy and a kernel launch instead of replaying the plan's graph),
+ * NN_BATCH_INTERLEAVED. */
 typedef struct nn_batch_cfg {
     uint32_t block;
     uint32_t grid;
-    uint32_t ilp;
+    uint32_t cluster;
     uint32_t mulmod;
     uint32_t flags;
 } nn_batch_cfg;
 #define NN_BATCH_NO_GRAPH 8u
+/* Interleave rows over all workgroups (workgroup w takes rows w, w + grid,
+ * ...) after a pre-pass that maps rows to streams.  Needs the FP64
+ * reduction and at most 256 threads per workgroup; measured slower than
+ * the default on the batched workload, kept for batches of few, long
+ * streams. */
+#define NN_BATCH_INTERLEAVED 16u
 
 /* Opaque batch plan: device workspace, pinned staging and a hipGraph of
  * (staging -> workspace copy, persistent kernel) whose arguments never

@@ -64,7 +64,7 @@ class BatchCfg(ctypes.Structure):
     _fields_ = [
         ("block", ctypes.c_uint32),
         ("grid", ctypes.c_uint32),
-        ("ilp", ctypes.c_uint32),
+        ("cluster", ctypes.c_uint32),
         ("mulmod", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
     ]
@@ -74,6 +74,7 @@ class BatchCfg(ctypes.Structure):
 
 
 NN_BATCH_NO_GRAPH = 8
+NN_BATCH_INTERLEAVED = 16
 
 
 _u64 = ctypes.c_uint64

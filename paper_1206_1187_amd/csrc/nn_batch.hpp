@@ -48,16 +48,33 @@ constexpr uint32_t kSkipBits = 13;
 constexpr uint32_t kSkipSize = 1u << kSkipBits;
 constexpr uint32_t kSkipLevels = 4;
 
+// Interleaved kernel (FP64 reduction): skip tables of 8 bits per level held
+// in LDS, t8[lvl][j] = (2^53)^(j * 2^(8 lvl)), lvl < 7 (2^56 > the period),
+// three doubles (v, qh, ql) per entry.
+constexpr uint32_t kSkip8Levels = 7;
+constexpr uint32_t kSkip8Size = 256;
+
 // Kernel arguments (fixed for the life of a plan).
 struct BatchArgs {
     const BatchHeader* ws;  // device workspace
-    Mult JB;                // (2^53)^(2*block): one row
-    Mult JB2;               // (2^53)^(4*block): two rows
+    uint32_t cluster;       // workgroups sharing a row range (blocked kernel)
+    Mult JB;                // (2^53)^(2*block*cluster): the next row of a lane
+    Mult JB2;               // (2^53)^(4*block*cluster): two such rows
     Mult Minv;              // (2^53)^-1
     const Mult* t_lo;
     const Mult* t_hi;
-    const Mult* t_sk;       // kSkipLevels * kSkipSize entries (indexed batches)
+    const Mult* t_sk;       // kSkipLevels * kSkipSize entries
+    // Interleaved kernel only:
+    Mult JG;                // (2^53)^(2*block*grid): the same lane G rows later
+    const double* t8;       // kSkip8Levels * kSkip8Size * 3 doubles
+    uint32_t* row_desc;     // per batch row: its window (device workspace)
 };
+
+// Interleaved kernels: row_desc[r] = the window of batch row r (pre-pass),
+// then workgroup w takes rows w, w + grid, ... (one write front, as the
+// plain row layout).  FP64 reduction only.
+const void* batch_map_kernel();
+const void* batch_il_kernel(int kind, bool nontemporal, bool indexed);
 
 // The kernel entry for (mulmod, kind, nontemporal, indexed); its single
 // parameter is a BatchArgs passed by value.

@@ -276,10 +276,11 @@ int nn_batch_plan_cfg(const nn_batch_plan* plan, nn_batch_cfg* cfg_out) {
     if (!plan || !cfg_out) return fail(NN_EINVAL, "NULL argument");
     cfg_out->block = plan->block;
     cfg_out->grid = plan->grid;
-    cfg_out->ilp = 1;
+    cfg_out->cluster = plan->cluster;
     cfg_out->mulmod = plan->mulmod;
     cfg_out->flags = (plan->nontemporal ? 0u : NN_CFG_TEMPORAL_STORES) |
-                     (plan->use_graph ? 0u : NN_BATCH_NO_GRAPH);
+                     (plan->use_graph ? 0u : NN_BATCH_NO_GRAPH) |
+                     (plan->interleaved ? NN_BATCH_INTERLEAVED : 0u);
     return ok();
 }
 

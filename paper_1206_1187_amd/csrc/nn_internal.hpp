@@ -22,6 +22,7 @@ struct DeviceTables {
     Mult* t_lo = nullptr;       // kLoSize entries
     Mult* t_hi = nullptr;       // kHiSize entries
     Mult* t_sk = nullptr;       // kSkipLevels * kSkipSize entries
+    double* t8 = nullptr;       // kSkip8Levels * kSkip8Size * 3 doubles
     uint64_t* t_blk = nullptr;  // kFlatMaxBlocks entries (flat layout)
     int cus = 0;
     uint32_t lds_per_cu = 0;
@@ -46,8 +47,11 @@ struct nn_batch_plan {
     int device = 0;
     int kind = 0;
     bool indexed = false;
-    uint32_t mulmod = 0, block = 0, grid = 0;
-    bool nontemporal = true, use_graph = true;
+    uint32_t mulmod = 0, block = 0, grid = 0, cluster = 1;
+    bool nontemporal = true, use_graph = true, interleaved = false;
+    uint64_t cap_rows = 0;
+    uint32_t* row_map = nullptr;  // device, cap_rows entries (interleaved kernel)
+    uint32_t map_grid = 0;
     uint32_t max_streams = 0;
     uint64_t max_outputs = 0;
     uint32_t cap_desc = 0;
@@ -58,7 +62,7 @@ struct nn_batch_plan {
     bool pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy_node = nullptr, kernel_node = nullptr;
+    hipGraphNode_t copy_node = nullptr, map_node = nullptr, kernel_node = nullptr;
     nn::BatchArgs args;
 };
 

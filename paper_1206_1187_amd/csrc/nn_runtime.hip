@@ -87,6 +87,27 @@ const std::vector<Mult>& host_mult_tables() {
     return tab;
 }
 
+// Host copy of the 8-bit skip tables: (v, qh, ql) of (2^53)^(j 2^(8 lvl)).
+const std::vector<double>& host_skip8_table() {
+    static std::vector<double> tab = [] {
+        std::vector<double> t(kSkip8Levels * kSkip8Size * 3);
+        for (uint32_t lvl = 0; lvl < kSkip8Levels; ++lvl) {
+            const uint64_t unit = MultPowers::get().pow(1ull << (8 * lvl));
+            uint64_t r = 1;
+            for (uint32_t j = 0; j < kSkip8Size; ++j) {
+                const Mult m = make_mult(r);
+                double* e = &t[3 * (lvl * kSkip8Size + j)];
+                e[0] = m.v;
+                e[1] = m.qh;
+                e[2] = m.ql;
+                r = h_mulmod(r, unit);
+            }
+        }
+        return t;
+    }();
+    return tab;
+}
+
 // Host copy of the flat layout's workgroup multipliers (2^53)^(512 b).
 const std::vector<uint64_t>& host_block_table() {
     static std::vector<uint64_t> tab = [] {
@@ -117,14 +138,19 @@ int ensure_device_current(int dev, DeviceTables** out) {
                         prop.gcnArchName);
         const std::vector<Mult>& h = host_mult_tables();
         const std::vector<uint64_t>& hb = host_block_table();
+        const std::vector<double>& h8 = host_skip8_table();
         const size_t mult_bytes = h.size() * sizeof(Mult);
         const size_t blk_bytes = hb.size() * sizeof(uint64_t);
+        const size_t t8_bytes = h8.size() * sizeof(double);
         void* mem = nullptr;
-        e = hipMalloc(&mem, mult_bytes + blk_bytes);
+        e = hipMalloc(&mem, mult_bytes + blk_bytes + t8_bytes);
         if (e != hipSuccess) return fail(NN_ENOMEM, "hipMalloc tables: %s", hipGetErrorString(e));
         e = hipMemcpy(mem, h.data(), mult_bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy((char*)mem + mult_bytes, hb.data(), blk_bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((char*)mem + mult_bytes + blk_bytes, h8.data(), t8_bytes,
+                          hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(mem);
             return fail(NN_EHIP, "table upload: %s", hipGetErrorString(e));
@@ -133,6 +159,7 @@ int ensure_device_current(int dev, DeviceTables** out) {
         d.t_hi = d.t_lo + kLoSize;
         d.t_sk = d.t_hi + kHiSize;
         d.t_blk = (uint64_t*)((char*)mem + mult_bytes);
+        d.t8 = (double*)((char*)mem + mult_bytes + blk_bytes);
         d.cus = prop.multiProcessorCount;
         d.lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
         d.lds_per_block = (uint32_t)prop.sharedMemPerBlock;
@@ -161,6 +188,7 @@ void plan_release(nn_batch_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->ws_dev) (void)hipFree(p->ws_dev);
+    if (p->row_map) (void)hipFree(p->row_map);
     if (p->ws_host) (void)hipHostFree(p->ws_host);
     delete p;
 }
@@ -172,7 +200,7 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     if (max_streams == 0) return fail(NN_EINVAL, "max_streams must be positive");
     nn_batch_cfg c = {0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
-    if (c.flags & ~(NN_CFG_TEMPORAL_STORES | NN_BATCH_NO_GRAPH))
+    if (c.flags & ~(NN_CFG_TEMPORAL_STORES | NN_BATCH_NO_GRAPH | NN_BATCH_INTERLEAVED))
         return fail(NN_EINVAL, "unknown batch flags 0x%x", c.flags);
     DeviceTables* d = nullptr;
     int st = current_device(&d);
@@ -181,7 +209,8 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     const uint32_t block = c.block ? c.block : kDefaultBlock;
     if (block < 64 || block > 1024 || block % 64)
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
-    if (c.ilp > 1) return fail(NN_EINVAL, "batch ilp %u: only 1 is supported", c.ilp);
+    const uint32_t cluster = c.cluster ? c.cluster : 1;
+    if (cluster > 64) return fail(NN_EINVAL, "cluster %u: at most 64", cluster);
     const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
     if (mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", mulmod);
     uint32_t grid = c.grid;
@@ -189,7 +218,9 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
         grid = (uint32_t)((uint64_t)d->cus * kd.grid_num / kd.grid_den);
         if (!grid) grid = 1;
     }
+    if (!c.grid) grid = (grid + cluster - 1) / cluster * cluster;
     if (grid > (1u << 20)) return fail(NN_EINVAL, "grid %u too large", grid);
+    if (grid % cluster) return fail(NN_EINVAL, "grid %u is not a multiple of cluster %u", grid, cluster);
     // Direct batches split streams into pieces of at most kBatchMaxLen.
     const uint64_t cap_desc = (uint64_t)max_streams + (indexed ? 0 : max_outputs / kBatchMaxLen + 1);
     if (cap_desc > 0xffffffffull) return fail(NN_ERANGE, "batch capacity too large");
@@ -204,11 +235,22 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->grid = grid;
     p->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
     p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
+    p->interleaved = (c.flags & NN_BATCH_INTERLEAVED) != 0;
+    if (p->interleaved && (mulmod != NN_MULMOD_FP64 || block > 256 || cluster != 1)) {
+        plan_release(p);
+        return fail(NN_EINVAL, "the interleaved batch kernel needs the FP64 reduction, "
+                    "block <= 256 and cluster 1");
+    }
+    p->cluster = cluster;
+    p->cap_rows = max_outputs / (2ull * block) + 2 * cap_desc;
+    p->map_grid = (uint32_t)(d->cus > 0 ? d->cus * 4 : 64);
     p->max_streams = max_streams;
     p->max_outputs = max_outputs;
     p->cap_desc = (uint32_t)cap_desc;
     p->ws_bytes = sizeof(BatchHeader) + cap_desc * sizeof(BatchDesc);
     hipError_t e = hipMalloc(&p->ws_dev, p->ws_bytes);
+    if (e == hipSuccess && p->interleaved)
+        e = hipMalloc((void**)&p->row_map, p->cap_rows * sizeof(uint32_t));
     if (e != hipSuccess) {
         plan_release(p);
         return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", p->ws_bytes, hipGetErrorString(e));
@@ -227,28 +269,46 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
         return fail(NN_EHIP, "event: %s", hipGetErrorString(e));
     }
     p->args.ws = (const BatchHeader*)p->ws_dev;
-    p->args.JB = make_mult(MultPowers::get().pow(2ull * block));
-    p->args.JB2 = make_mult(MultPowers::get().pow(4ull * block));
+    p->args.cluster = cluster;
+    p->args.JB = make_mult(MultPowers::get().pow(2ull * block * cluster));
+    p->args.JB2 = make_mult(MultPowers::get().pow(4ull * block * cluster));
     p->args.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
     p->args.t_lo = d->t_lo;
     p->args.t_hi = d->t_hi;
     p->args.t_sk = d->t_sk;
+    p->args.JG = make_mult(MultPowers::get().pow(2ull * block * grid));
+    p->args.t8 = d->t8;
+    p->args.row_desc = p->row_map;
     if (p->use_graph) {
         e = hipGraphCreate(&p->graph, 0);
         if (e == hipSuccess)
             e = hipGraphAddMemcpyNode1D(&p->copy_node, p->graph, nullptr, 0, p->ws_dev, p->ws_host,
                                         sizeof(BatchHeader), hipMemcpyHostToDevice);
+        hipGraphNode_t last = p->copy_node;
+        void* params[] = {&p->args};
+        if (e == hipSuccess && p->interleaved) {
+            hipKernelNodeParams kp;
+            memset(&kp, 0, sizeof kp);
+            kp.func = const_cast<void*>(batch_map_kernel());
+            kp.gridDim = dim3(p->map_grid);
+            kp.blockDim = dim3(256);
+            kp.kernelParams = params;
+            e = hipGraphAddKernelNode(&p->map_node, p->graph, &last, 1, &kp);
+            last = p->map_node;
+        }
         if (e == hipSuccess) {
             hipKernelNodeParams kp;
             memset(&kp, 0, sizeof kp);
-            void* params[] = {&p->args};
-            kp.func = const_cast<void*>(batch_kernel((int)mulmod, kind, p->nontemporal, indexed));
+            kp.func = p->interleaved
+                          ? const_cast<void*>(batch_il_kernel(kind, p->nontemporal, indexed))
+                          : const_cast<void*>(batch_kernel((int)mulmod, kind, p->nontemporal,
+                                                           indexed));
             kp.gridDim = dim3(grid);
             kp.blockDim = dim3(block);
             kp.sharedMemBytes = 0;
             kp.kernelParams = params;
             kp.extra = nullptr;
-            e = hipGraphAddKernelNode(&p->kernel_node, p->graph, &p->copy_node, 1, &kp);
+            e = hipGraphAddKernelNode(&p->kernel_node, p->graph, &last, 1, &kp);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
@@ -287,6 +347,9 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         dd[k].row_start = rows;
         rows += (dd[k].len + (dd[k].out_off & 1u) + row - 1) / row;
     }
+    if (p->interleaved && rows > p->cap_rows)
+        return fail(NN_ERANGE, "batch of %llu rows, plan holds %llu", (unsigned long long)rows,
+                    (unsigned long long)p->cap_rows);
     hdr->out = (uint64_t*)out;
     hdr->n_desc = nd;
     hdr->n_rows = rows;
@@ -298,9 +361,18 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         if (e == hipSuccess) e = hipGraphLaunch(p->exec, stream);
     } else {
         e = hipMemcpyAsync(p->ws_dev, p->ws_host, bytes, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess)
+        BatchArgs copy = p->args;
+        void* params[] = {&copy};
+        if (e == hipSuccess && p->interleaved) {
+            e = hipLaunchKernel(batch_map_kernel(), dim3(p->map_grid), dim3(256), params, 0,
+                                stream);
+            if (e == hipSuccess)
+                e = hipLaunchKernel(batch_il_kernel(p->kind, p->nontemporal, p->indexed),
+                                    dim3(p->grid), dim3(p->block), params, 0, stream);
+        } else if (e == hipSuccess) {
             e = launch_batch((int)p->mulmod, p->kind, p->nontemporal, p->indexed, p->grid,
                              p->block, stream, p->args);
+        }
     }
     if (e != hipSuccess) return fail(NN_EHIP, "batch launch: %s", hipGetErrorString(e));
     e = hipEventRecord(p->done, stream);

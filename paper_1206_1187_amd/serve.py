@@ -39,8 +39,8 @@ class Server:
         mulmod = batch_kw.get("mulmod", 0)
         if isinstance(mulmod, str):
             mulmod = MULMOD_NAMES[mulmod]
-        batch = BatchCfg(int(batch_kw.get("block", 0)), int(batch_kw.get("grid", 0)), 0,
-                         int(mulmod), 0)
+        batch = BatchCfg(int(batch_kw.get("block", 0)), int(batch_kw.get("grid", 0)),
+                         int(batch_kw.get("cluster", 0)), int(mulmod), 0)
         self.pool_bytes = int(pool_bytes) & ~255
         self.pool = None
         pool_ptr = None

@@ -130,10 +130,14 @@ def tune_batch(kind, reps=5, log=print, workload=None):
     dt = torch.float64 if kind == "f64" else torch.uint64
     out = torch.empty(total, dtype=dt, device="cuda")
     results = []
-    grids = sorted({max(1, cus * k // 8) for k in (1, 2, 3, 4, 5, 6, 8, 12, 16)})
-    for mulmod, block, grid in itertools.product(("fp64", "shoup", "barrett", "montgomery"),
-                                                 (128, 256, 512), grids):
-        kw = dict(block=block, grid=grid, mulmod=mulmod)
+    grids = sorted({max(1, cus * k // 8) for k in (4, 6, 8, 12, 16)})
+    shapes = [dict(mulmod=m, block=b, cluster=k, temporal=t) for m in ("fp64", "shoup")
+              for b in (256, 512) for k in (1, 4, 8, 16) for t in (False, True)]
+    shapes += [dict(mulmod=m, block=256, cluster=8) for m in ("barrett", "montgomery")]
+    for shape, grid in itertools.product(shapes, grids):
+        if grid % shape["cluster"]:
+            continue
+        kw = dict(shape, grid=grid)
         with nn.BatchPlan(kind, len(states), total, **kw) as plan:
             ms = _median_ms(lambda: plan.generate(states, lengths, offsets, out), reps)
         results.append((ms, kw))

@@ -70,16 +70,23 @@ LENGTHS = [0, 1, 2, 3, 4, 63, 64, 65, 511, 512, 513, 1023, 1024, 1025, 8191, 819
 
 
 @pytest.mark.parametrize("kind", ["u64", "f64"])
-@pytest.mark.parametrize("mulmod", ["fp64", "shoup", "barrett", "montgomery"])
-def test_batch_bit_exact_mixed_lengths(kind, mulmod):
+@pytest.mark.parametrize("mulmod,interleaved", [("fp64", False), ("fp64", True), ("shoup", False),
+                                                ("barrett", False), ("montgomery", False)])
+def test_batch_bit_exact_mixed_lengths(kind, mulmod, interleaved):
+    """Both batch kernels, every reduction, many shapes and cluster sizes."""
     states, lengths, offsets, total = _mixed_batch(11, LENGTHS)
     dt = torch.float64 if kind == "f64" else torch.uint64
-    for block, grid, graph in [(256, 0, True), (64, 3, False), (1024, 7, True), (128, 1, True),
-                               (64, 1000, True)]:
-        _say("batch", kind, mulmod, block, grid, graph)
+    for block, grid, cluster, graph in [(256, 0, 0, True), (64, 3, 1, False), (1024, 7, 1, True),
+                                        (128, 1, 1, True), (64, 1000, 8, True),
+                                        (256, 4096, 4, True), (128, 12, 3, True),
+                                        (256, 64, 64, False)]:
+        if interleaved and (block > 256 or cluster > 1):
+            continue
+        _say("batch", kind, mulmod, interleaved, block, grid, cluster, graph)
         buf = _sentinel(total)
-        with nn.BatchPlan(kind, 64, total, block=block, grid=grid, mulmod=mulmod,
-                          graph=graph) as plan:
+        with nn.BatchPlan(kind, 64, total, block=block, grid=grid, cluster=cluster,
+                          mulmod=mulmod, graph=graph, interleaved=interleaved) as plan:
+            assert bool(plan.cfg().flags & 16) == interleaved
             fin = plan.generate(states, lengths, offsets, buf.view(dt), final_states=True)
             torch.cuda.synchronize()
         _check_batch(_bits(buf), states, lengths, offsets, kind)
