@@ -140,14 +140,17 @@ def served_leg(nn, torch):
     res = {"workload": "served: numpy default_rng(4), 1,024 streams, Poisson 20k req/s for "
                        "10 s, sizes log-uniform in [256, 2^24] f64, 64 GB pool",
            "requests": int(tr.count.size), "variates": int(tr.count.sum())}
-    with serve.Server(states, pool, lanes=2) as srv:
+    from paper_1206_1187_amd import tune
+    shape = tune.best_batch_cfg("f64", int(tr.count.sum()))
+    res["batch_cfg"] = shape
+    with serve.Server(states, pool, lanes=2, **shape) as srv:
         res["served"] = serve.replay_served_native(srv, tr, timeout_s=120)
     res["plain_per_request"] = serve.replay_per_request_native(tr, states, pool // 8,
                                                                timeout_s=120)
     n = 20000
     sweep = []
     for scale in (4, 16, 32, 64):
-        with serve.Server(states, pool, lanes=2) as srv:
+        with serve.Server(states, pool, lanes=2, **shape) as srv:
             a = serve.replay_served_native(srv, tr, time_scale=scale, timeout_s=120, n=n)
         b = serve.replay_per_request_native(tr, states, pool // 8, time_scale=scale,
                                             timeout_s=120, n=n)
@@ -325,6 +328,16 @@ def main():
         extras["f64_frac_of_write_ceiling"] = achieved / ceiling
         # Paper's Table 2: generation time net of the store time.
         extras["net_generation_ms"] = (f64_s - min(fill_s, flat_s)) * 1e3
+        # Fused consumer: the same generation summed in registers (no stores),
+        # the analogue of the paper's Table 2 net generation rate.
+        res = torch.zeros(1, dtype=torch.int64, device="cuda")
+        cons_s = _timed_kernel(lambda: nn.consume(nn.seed(case.index), case.count_f64, "u64",
+                                                  result=res), reps, torch)
+        resf = torch.zeros(1, dtype=torch.float64, device="cuda")
+        consf_s = _timed_kernel(lambda: nn.consume(nn.seed(case.index), case.count_f64, "f64",
+                                                   result=resf), reps, torch)
+        extras["fused_consumer_u64_variates_per_s"] = case.count_f64 / cons_s
+        extras["fused_consumer_f64_variates_per_s"] = case.count_f64 / consf_s
         shoot = {}
         for name in ("fp64", "barrett", "shoup", "montgomery"):
             for kind, out in (("f64", out_f), ("u64", out_u)):

@@ -148,6 +148,19 @@ int nn_generate_ex(uint64_t *state, uint64_t count, void *out_dev, int kind, voi
  * outputs of `kind` on the current device (fields all filled in). */
 int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg *cfg_out);
 
+/* nn_consume -- the fused consumer: generates the `count` outputs after
+ * *state exactly as nn_generate would, but reduces them in registers
+ * instead of storing them (variates usually feed a simulation directly,
+ * Section 3.2; Table 2 measures generation with the memory traffic
+ * removed).  Adds to *result_dev (device memory, 8-byte aligned, one
+ * value the caller initialises): for NN_OUT_U64 the sum of the raw states
+ * z_1..z_count modulo 2^64 (exact, independent of the launch shape); for
+ * NN_OUT_F64 the binary64 sum of the variates (summation order depends on
+ * the launch shape).  Sets *state to z_count.  cfg: block, grid and mulmod
+ * only (NULL for the defaults).  Asynchronous on `stream`. */
+int nn_consume(uint64_t *state, uint64_t count, int kind, void *result_dev, void *stream,
+               const nn_launch_cfg *cfg);
+
 /* nn_fill -- the paper's "Constant" measurement kernel (Section 4.2,
  * Table 1): writes `value` to out_dev[0..count) with exactly the store
  * pattern nn_generate_ex uses for the same cfg and NN_OUT_F64 (fields left

@@ -133,6 +133,25 @@ def fill(out, value, stream=None, cfg=None):
     _native.check(rc)
 
 
+def consume(state, count, kind="u64", result=None, stream=None, cfg=None):
+    """The fused consumer: add the sum of the next ``count`` outputs (raw
+    states modulo 2^64 for "u64", variates for "f64") to the one-element
+    cuda tensor ``result`` (allocated and zeroed when None).  Returns
+    (result, new_state)."""
+    import torch
+    k = _kind(kind)
+    if result is None:
+        result = torch.zeros(1, dtype=torch.int64 if k == NN_OUT_U64 else torch.float64,
+                             device="cuda")
+    st = ctypes.c_uint64(int(state))
+    with torch.cuda.device(result.device):
+        rc = _native.lib().nn_consume(ctypes.byref(st), int(count), k,
+                                      ctypes.c_void_p(result.data_ptr()), _stream_handle(stream),
+                                      ctypes.byref(cfg) if cfg is not None else None)
+    _native.check(rc)
+    return result, int(st.value)
+
+
 def debug_mulmod(variant, a, b):
     """Host build of a step-loop reduction: a[i]*b[i] mod 3^33 (numpy uint64)."""
     import numpy as np

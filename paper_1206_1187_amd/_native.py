@@ -136,6 +136,7 @@ SIGNATURES = {
     "nn_generate_ex": (_int, [_pu64, _u64, _vp, _int, _vp, ctypes.POINTER(LaunchCfg)]),
     "nn_default_cfg": (_int, [_int, _u64, ctypes.POINTER(LaunchCfg)]),
     "nn_fill": (_int, [_u64, _vp, _u64, _vp, ctypes.POINTER(LaunchCfg)]),
+    "nn_consume": (_int, [_pu64, _u64, _int, _vp, _vp, ctypes.POINTER(LaunchCfg)]),
     "nn_strerror": (ctypes.c_char_p, [_int]),
     "nn_last_error": (ctypes.c_char_p, []),
     "nn_version": (ctypes.c_char_p, []),

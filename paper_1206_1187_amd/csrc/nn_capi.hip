@@ -232,6 +232,57 @@ int nn_generate(uint64_t* state, uint64_t count, void* out_dev, int kind, void* 
     return nn_generate_ex(state, count, out_dev, kind, stream, nullptr);
 }
 
+int nn_consume(uint64_t* state, uint64_t count, int kind, void* result_dev, void* stream,
+               const nn_launch_cfg* cfg) {
+    if (!state) return fail(NN_EINVAL, "state is NULL");
+    if (kind != NN_OUT_U64 && kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %d unknown", kind);
+    const uint64_t s = *state;
+    if (!valid_state(s))
+        return fail(NN_EINVAL, "state %llu is not a unit modulo 3^33", (unsigned long long)s);
+    if (count == 0) return ok();
+    if (!result_dev || (uintptr_t)result_dev % 8)
+        return fail(NN_EINVAL, "result pointer %p must be non-NULL and 8-byte aligned", result_dev);
+    DeviceTables* d = nullptr;
+    int st = current_device(&d);
+    if (st) return st;
+    nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (cfg) c = *cfg;
+    if (c.flags || c.occupancy || (c.width && c.width != 2) || (c.ilp && c.ilp != 2) || c.unroll)
+        return fail(NN_EINVAL, "nn_consume takes block, grid and mulmod only");
+    const KindDefaults& kd = kind_defaults(NN_OUT_F64);
+    const uint32_t block = c.block ? c.block : kDefaultBlock;
+    if (block < 64 || block > 1024 || block % 64)
+        return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
+    const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
+    if (mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", mulmod);
+    uint32_t grid = c.grid;
+    if (!grid) {
+        // No stores to keep sequential: fill the device.
+        const uint64_t need = (count + 2ull * block - 1) / (2ull * block);
+        const uint64_t cap = (uint64_t)(d->cus > 0 ? d->cus : 1) * 8;
+        grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
+    }
+    if ((uint64_t)grid * block > kMaxThreads)
+        return fail(NN_EINVAL, "grid*block exceeds %llu threads", (unsigned long long)kMaxThreads);
+    GenArgs a;
+    a.out = nullptr;
+    a.T = (uint64_t)grid * block;
+    const uint64_t row = 2 * a.T;
+    a.e_full = count / row;
+    a.rem = (uint32_t)(count % row);
+    a.base = h_mulmod(s, kMult);
+    const uint64_t jump = MultPowers::get().pow(row);
+    a.J = make_mult(jump);
+    a.M1 = make_mult(kMult);
+    a.JI = make_mult(MultPowers::get().pow(2 * row));
+    a.t_lo = d->t_lo;
+    a.t_hi = d->t_hi;
+    hipError_t e = launch_consume((int)mulmod, kind, grid, block, (hipStream_t)stream, a, result_dev);
+    if (e != hipSuccess) return fail(NN_EHIP, "consume launch: %s", hipGetErrorString(e));
+    *state = h_skip(s, count);
+    return ok();
+}
+
 int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const nn_launch_cfg* cfg) {
     if (count == 0) return ok();
     int st = check_out(count, out_dev);

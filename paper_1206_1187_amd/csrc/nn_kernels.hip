@@ -140,6 +140,91 @@ __global__ __launch_bounds__(1024) void k_generate2_ilp(uint64_t* __restrict__ o
     }
 }
 
+// Fused consumer (the paper's point that variates usually feed a simulation
+// directly, Section 3.2; its Table 2 removes the memory traffic): the same
+// generation as k_generate2_ilp with IL = 2, the outputs summed in
+// registers.  Kind 0 sums raw states modulo 2^64 (exact in any order).
+template <class V, int KIND>
+__global__ __launch_bounds__(1024) void k_consume(uint64_t T, uint64_t e_full, uint32_t rem,
+                                                  uint64_t base, Mult J, Mult M1, Mult JI,
+                                                  const Mult* __restrict__ t_lo,
+                                                  const Mult* __restrict__ t_hi, void* result) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    typename V::S za0 = thread_start<V>(base, 2ull * t, t_lo, t_hi);
+    typename V::S zb0 = V::mul(za0, M1);
+    typename V::S za1 = V::mul(za0, J);
+    typename V::S zb1 = V::mul(zb0, J);
+    uint64_t su = 0;
+    double sf = 0.0;
+    auto take = [&](typename V::S z) {
+        if constexpr (KIND == 0)
+            su += V::to_u64(z);
+        else
+            sf += V::to_f64(z);
+    };
+    uint64_t i = 0;
+    for (; i + 2 <= e_full; i += 2) {
+        take(za0);
+        take(zb0);
+        take(za1);
+        take(zb1);
+        za0 = V::mul(za0, JI);
+        zb0 = V::mul(zb0, JI);
+        za1 = V::mul(za1, JI);
+        zb1 = V::mul(zb1, JI);
+    }
+    typename V::S pa = za0, pb = zb0;
+    if (i < e_full) {  // one full row left
+        take(za0);
+        take(zb0);
+        pa = za1;
+        pb = zb1;
+    }
+    const uint32_t rem_pairs = rem >> 1;
+    if (t < rem_pairs) {
+        take(pa);
+        take(pb);
+    } else if ((rem & 1u) && t == rem_pairs) {
+        take(pa);
+    }
+    // Reduce across the wavefront, then one atomic per wavefront.
+    for (int off = 32; off > 0; off >>= 1) {
+        if constexpr (KIND == 0)
+            su += (uint64_t)__shfl_xor((unsigned long long)su, off, 64);
+        else
+            sf += __shfl_xor(sf, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if constexpr (KIND == 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(result), (unsigned long long)su);
+        else
+            atomicAdd(reinterpret_cast<double*>(result), sf);
+    }
+}
+
+template <class V>
+static hipError_t consume_v(int kind, uint32_t grid, uint32_t block, hipStream_t s,
+                            const GenArgs& a, void* result) {
+    if (kind == 0)
+        hipLaunchKernelGGL((k_consume<V, 0>), dim3(grid), dim3(block), 0, s, a.T, a.e_full,
+                           a.rem, a.base, a.J, a.M1, a.JI, a.t_lo, a.t_hi, result);
+    else
+        hipLaunchKernelGGL((k_consume<V, 1>), dim3(grid), dim3(block), 0, s, a.T, a.e_full,
+                           a.rem, a.base, a.J, a.M1, a.JI, a.t_lo, a.t_hi, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_consume(int mulmod, int kind, uint32_t grid, uint32_t block, hipStream_t s,
+                          const GenArgs& a, void* result) {
+    switch (mulmod) {
+        case 1: return consume_v<VarFP64>(kind, grid, block, s, a, result);
+        case 2: return consume_v<VarBarrett>(kind, grid, block, s, a, result);
+        case 3: return consume_v<VarShoup>(kind, grid, block, s, a, result);
+        case 4: return consume_v<VarMontgomery>(kind, grid, block, s, a, result);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // The paper's "Constant" kernel (Section 4.2): the same stores, a fixed value.
 template <int W, int UNROLL, bool NT>
 __global__ __launch_bounds__(1024) void k_fill(uint64_t* __restrict__ out, uint64_t T,

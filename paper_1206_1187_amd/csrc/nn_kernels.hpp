@@ -41,6 +41,13 @@ hipError_t launch_generate(int mulmod, int kind, int width, int unroll, int ilp,
                            bool nontemporal, uint32_t grid, uint32_t block, hipStream_t stream,
                            const GenArgs& a);
 
+// Fused consumer: the row layout's states (W = 2, IL rows in flight) are
+// consumed in registers instead of stored: each thread adds its outputs
+// (raw states modulo 2^64 for kind 0, variates in binary64 for kind 1) and
+// one atomic per thread folds the partial sums into *result.
+hipError_t launch_consume(int mulmod, int kind, uint32_t grid, uint32_t block, hipStream_t s,
+                          const GenArgs& a, void* result);
+
 // Flat layout: workgroup b of 256 threads writes elements
 // [512 b, 512 b + 512) of the launch, two consecutive ones per lane in one
 // 16-byte store, and exits; every workgroup starts from

@@ -41,12 +41,12 @@ const char* last_error() { return g_last_error.c_str(); }
 // 2^28..2^30): 16-byte stores per lane from 256-thread workgroups on a
 // fraction of the CUs (fewer concurrent writers keep the HBM write stream
 // closer to sequential).  F64 output: the FP64 reduction with two rows in
-// flight on CUs/2 workgroups; U64 output: Shoup's reduction (integer state,
-// no conversion) with one row on 3*CUs/4 workgroups.
+// flight on CUs/2 workgroups; U64 output: the FP64 reduction with four rows
+// in flight on 5*CUs/8 workgroups.
 const KindDefaults& kind_defaults(int kind) {
     static const KindDefaults d[2] = {
-        {NN_MULMOD_SHOUP, 3, 4, 2, 1},  // NN_OUT_U64
-        {NN_MULMOD_FP64, 1, 2, 4, 2},   // NN_OUT_F64
+        {NN_MULMOD_FP64, 5, 8, 2, 4},  // NN_OUT_U64
+        {NN_MULMOD_FP64, 1, 2, 4, 2},  // NN_OUT_F64
     };
     return d[kind == NN_OUT_F64 ? 1 : 0];
 }

@@ -95,10 +95,10 @@ def tune_plain(kind, count, reps=9, log=print):
     s0 = nn.seed(nn.INDEX_MIN)
     results = []
     grids = sorted({max(1, cus * k // 8) for k in (2, 3, 4, 5, 6, 8)})
-    for mulmod, grid, ilp, unroll in itertools.product(("fp64", "shoup"), grids, (1, 2, 4),
-                                                       (2, 4, 8)):
+    for mulmod, grid, ilp, unroll, temporal in itertools.product(
+            ("fp64", "shoup"), grids, (1, 2, 4), (2, 4, 8), (False, True)):
         kw = dict(block=256, grid=grid, mulmod=mulmod, ilp=ilp, unroll=unroll, width=2,
-                  layout="rows")
+                  layout="rows", temporal=temporal)
         cfg = nn.make_cfg(**kw)
         ms = _median_ms(lambda: nn.generate_into(s0, out, cfg=cfg), reps)
         results.append((ms, kw))

@@ -271,3 +271,23 @@ def test_flat_chunk_boundary_beyond_one_launch():
         assert np.array_equal(got, ref.view(np.uint64)), start
     del out, flat
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mulmod", VARIANTS)
+def test_fused_consumer_state_sum_exact(mulmod):
+    """nn_consume: the sum of the raw states modulo 2^64 is exact for any
+    launch shape; the variate sum agrees to rounding."""
+    z0 = orc.seed(wl.plain_bulk().index + 17)
+    for count, block, grid in [(1, 0, 0), (1023, 64, 3), (300_001, 256, 7), (1 << 22, 0, 0),
+                               (5_000_000, 512, 129)]:
+        ref, zr = orc.gen(z0, count, "u64", threads=0)
+        want = int(ref.sum(dtype=np.uint64))  # numpy wraps modulo 2^64
+        cfg = nn.make_cfg(block=block, grid=grid, mulmod=mulmod)
+        res, zn = nn.consume(z0, count, "u64", cfg=cfg)
+        torch.cuda.synchronize()
+        assert int(res.view(torch.int64).cpu().numpy().view(np.uint64)[0]) == want
+        assert zn == zr
+        resf, _ = nn.consume(z0, count, "f64", cfg=cfg)
+        torch.cuda.synchronize()
+        reff, _ = orc.gen(z0, count, "f64", threads=0)
+        assert abs(float(resf.cpu()[0]) - float(reff.sum())) <= 1e-9 * max(1.0, float(reff.sum()))
