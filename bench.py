@@ -345,6 +345,13 @@ def main():
                 s = _timed_kernel(
                     lambda: nn.generate_into(nn.seed(case.index), out, cfg=cfg), 10, torch)
                 shoot["%s_%s_GBps" % (name, kind)] = 8.0 * out.numel() / s / 1e9
+        # The paper's own step (Section 3.1's Modified Barrett by 2^53) in
+        # its per-thread consecutive loop, serial order kept through LDS.
+        for kind, out in (("f64", out_f), ("u64", out_u)):
+            cfg = nn.make_cfg(layout="consecutive")
+            s = _timed_kernel(
+                lambda: nn.generate_into(nn.seed(case.index), out, cfg=cfg), 10, torch)
+            shoot["modbarrett_consecutive_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
         extras["mulmod_shootout_default_shape"] = shoot
         result["extras"] = extras
         log("extras", json.dumps(extras))

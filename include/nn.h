@@ -59,7 +59,9 @@ typedef enum nn_mulmod {
     NN_MULMOD_FP64 = 1,     /* FP64 FMA two-product, FP64 quotient estimate */
     NN_MULMOD_BARRETT = 2,  /* integer Barrett, k = 53, mu = floor(2^106/m) */
     NN_MULMOD_SHOUP = 3,    /* integer fixed-multiplier quotient (Shoup)    */
-    NN_MULMOD_MONTGOMERY = 4 /* integer Montgomery, R = 2^64, pre-scaled   */
+    NN_MULMOD_MONTGOMERY = 4, /* integer Montgomery, R = 2^64, pre-scaled  */
+    NN_MULMOD_MODBARRETT = 5  /* Section 3.1's Modified Barrett: the step by
+                                 exactly 2^53 only (consecutive layout)     */
 } nn_mulmod;
 
 #define NN_MODULUS 5559060566555523ULL   /* 3^33 */
@@ -69,23 +71,34 @@ typedef enum nn_mulmod {
 
 /* Launch configuration.  Any field left 0 takes the library default.
  *
- * Two layouts write the same values (serial order in memory):
+ * Three layouts write the same values (serial order in memory):
  *  - rows (default): grid*block threads loop over rows of
  *    width*grid*block outputs, stepping by a jump multiplier;
  *  - flat (NN_CFG_FLAT): every 256-thread workgroup writes 512 consecutive
  *    outputs, two per lane in one 16-byte store, and exits (needs a 16-byte
- *    aligned output).
+ *    aligned output);
+ *  - consecutive (NN_CFG_CONSECUTIVE): the paper's per-thread loop (Section
+ *    3.2): each thread makes `unroll` consecutive outputs with Eq. 3's own
+ *    multiplier 2^53 and Section 3.1's Modified Barrett reduction; the
+ *    workgroup's block*unroll outputs pass through LDS and leave in serial
+ *    order with coalesced stores (the paper instead stored them strided,
+ *    out of order).  Workgroup w takes tiles w, w + grid, ...
  *
- * block: threads per workgroup, a multiple of 64 in [64,1024] (rows).
- * grid: workgroups, block*grid <= 2^24 (rows).
- * mulmod: an nn_mulmod (both layouts).
- * unroll: 1, 2, 4 or 8 iterations of the step loop per trip (rows).
+ * block: threads per workgroup, a multiple of 64 in [64,1024] (rows,
+ * consecutive).
+ * grid: workgroups, block*grid <= 2^24 (rows); block*grid*unroll <= 2^25
+ * (consecutive).
+ * mulmod: an nn_mulmod; NN_MULMOD_MODBARRETT only, and only it, with the
+ * consecutive layout (0 selects it there).
+ * unroll: 1, 2, 4 or 8 iterations of the step loop per trip (rows); outputs
+ * per thread and tile, 2, 4, 8, 16 or 32 (consecutive, default 16).
  * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable (default:
  * non-temporal streaming stores); NN_CFG_ROWS / NN_CFG_FLAT force a layout.
  * width: outputs per lane and store, 1 (8-byte stores) or 2 (16-byte
  * stores, needs a 16-byte aligned output) (rows; flat is always 2).
  * occupancy: 0, or a cap in [2,16] on resident workgroups per compute unit
  * (flat), enforced through unused dynamic LDS.
+ * Consecutive: width 2 (16-byte stores) on a 16-byte aligned output, else 1. 
  * ilp: rows each thread keeps in flight, 1, 2 or 4 (rows with width 2):
  * 2*ilp independent multiplication chains per lane. */
 typedef struct nn_launch_cfg {
@@ -101,6 +114,7 @@ typedef struct nn_launch_cfg {
 #define NN_CFG_TEMPORAL_STORES 1u
 #define NN_CFG_ROWS 2u
 #define NN_CFG_FLAT 4u
+#define NN_CFG_CONSECUTIVE 8u
 
 /* ---------------------------------------------------------------- host -- */
 
@@ -160,6 +174,34 @@ int nn_default_cfg(int kind, uint64_t count, nn_launch_cfg *cfg_out);
  * only (NULL for the defaults).  Asynchronous on `stream`. */
 int nn_consume(uint64_t *state, uint64_t count, int kind, void *result_dev, void *stream,
                const nn_launch_cfg *cfg);
+
+/* ------------------------------------------------ device-side generation --
+ * For consumer kernels that make variates where they use them (nn_device.h,
+ * the header-only device functions built on these two calls). */
+
+/* A multiplier v = (2^53)^k mod 3^33 in the form nn_dev_mulmod takes: v as a
+ * double (exact, v < 2^53) and v / 3^33 as the double-double qh + ql. */
+typedef struct nn_dev_mult {
+    double v;
+    double qh;
+    double ql;
+} nn_dev_mult;
+
+#define NN_DEV_SKIP_LEVELS 7u
+#define NN_DEV_SKIP_SIZE 256u
+
+/* nn_dev_mult_pow -- (2^53)^k mod 3^33 (Eq. 3 applied k times; k is taken
+ * modulo the period) as an nn_dev_mult.  Host only, pure, thread-safe.
+ * NN_EINVAL if out is NULL. */
+int nn_dev_mult_pow(uint64_t k, nn_dev_mult *out);
+
+/* nn_dev_skip_table -- device pointer, on the current HIP device, of the
+ * skip table nn_dev_skip reads: NN_DEV_SKIP_LEVELS x NN_DEV_SKIP_SIZE
+ * entries, entry [lvl][j] = (2^53)^(j * 256^lvl) as an nn_dev_mult.  Owned
+ * by the library, immutable, valid until the process ends; set up as by
+ * nn_init.  NN_EINVAL if table_out is NULL; NN_ENODEV / NN_ENOMEM / NN_EHIP
+ * as nn_init. */
+int nn_dev_skip_table(const nn_dev_mult **table_out);
 
 /* nn_fill -- the paper's "Constant" measurement kernel (Section 4.2,
  * Table 1): writes `value` to out_dev[0..count) with exactly the store
@@ -357,8 +399,9 @@ const char *nn_version(void);
 /* nn_debug_mulmod -- runs the host build of a step-loop modular
  * multiplication (the same source the device compiles) on n pairs:
  * out[i] = a[i] * b[i] mod 3^33, with b[i] taking the role of the fixed
- * multiplier.  Every a[i] and b[i] must be a valid state.  For testing the
- * arithmetic on a CPU; host pointers. */
+ * multiplier.  Every a[i] and b[i] must be a valid state;
+ * NN_MULMOD_MODBARRETT multiplies by 2^53 itself and needs every b[i] to be
+ * 2^53 mod 3^33.  For testing the arithmetic on a CPU; host pointers. */
 int nn_debug_mulmod(int mulmod, const uint64_t *a, const uint64_t *b, uint64_t n,
                     uint64_t *out);
 

@@ -55,7 +55,7 @@ def init(device=0):
 def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layout=None,
              occupancy=0, ilp=0):
     """Launch configuration (include/nn.h, nn_launch_cfg); ``layout`` is
-    None (library default), "flat" or "rows"."""
+    None (library default), "flat", "rows" or "consecutive"."""
     if isinstance(mulmod, str):
         mulmod = MULMOD_NAMES[mulmod]
     flags = _native.NN_CFG_TEMPORAL_STORES if temporal else 0
@@ -63,8 +63,10 @@ def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layou
         flags |= _native.NN_CFG_FLAT
     elif layout == "rows":
         flags |= _native.NN_CFG_ROWS
+    elif layout == "consecutive":
+        flags |= _native.NN_CFG_CONSECUTIVE
     elif layout is not None:
-        raise NNError(_native.NN_EINVAL, "layout must be None, 'flat' or 'rows'")
+        raise NNError(_native.NN_EINVAL, "layout must be None, 'flat', 'rows' or 'consecutive'")
     return LaunchCfg(int(block), int(grid), int(mulmod), int(unroll), flags, int(width),
                      int(occupancy), int(ilp))
 
@@ -150,6 +152,22 @@ def consume(state, count, kind="u64", result=None, stream=None, cfg=None):
                                       ctypes.byref(cfg) if cfg is not None else None)
     _native.check(rc)
     return result, int(st.value)
+
+
+def dev_mult_pow(k):
+    """(2^53)^k mod 3^33 in the device-side form (include/nn_device.h):
+    (v, qh, ql) with qh + ql = v / 3^33 as a double-double."""
+    m = _native.DevMult()
+    _native.check(_native.lib().nn_dev_mult_pow(int(k), ctypes.byref(m)))
+    return m.v, m.qh, m.ql
+
+
+def dev_skip_table():
+    """Device address (int) of the skip table nn_dev_skip reads, on the
+    current device."""
+    p = ctypes.c_void_p()
+    _native.check(_native.lib().nn_dev_skip_table(ctypes.byref(p)))
+    return p.value
 
 
 def debug_mulmod(variant, a, b):

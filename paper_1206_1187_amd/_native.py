@@ -11,10 +11,12 @@ LIB_PATH = os.path.join(HERE, "libnn.so")
 
 NN_OK, NN_EINVAL, NN_ERANGE, NN_EHIP, NN_ENOMEM, NN_ENODEV = range(6)
 NN_OUT_U64, NN_OUT_F64 = 0, 1
-NN_MULMOD_DEFAULT, NN_MULMOD_FP64, NN_MULMOD_BARRETT, NN_MULMOD_SHOUP, NN_MULMOD_MONTGOMERY = range(5)
+(NN_MULMOD_DEFAULT, NN_MULMOD_FP64, NN_MULMOD_BARRETT, NN_MULMOD_SHOUP, NN_MULMOD_MONTGOMERY,
+ NN_MULMOD_MODBARRETT) = range(6)
 NN_CFG_TEMPORAL_STORES = 1
 NN_CFG_ROWS = 2
 NN_CFG_FLAT = 4
+NN_CFG_CONSECUTIVE = 8
 
 MULMOD_NAMES = {
     "default": NN_MULMOD_DEFAULT,
@@ -22,6 +24,7 @@ MULMOD_NAMES = {
     "barrett": NN_MULMOD_BARRETT,
     "shoup": NN_MULMOD_SHOUP,
     "montgomery": NN_MULMOD_MONTGOMERY,
+    "modbarrett": NN_MULMOD_MODBARRETT,
 }
 
 
@@ -128,6 +131,11 @@ class ServerStats(ctypes.Structure):
 
 
 # name -> (restype, argtypes); must match include/nn.h
+class DevMult(ctypes.Structure):
+    """nn_dev_mult (include/nn.h): a multiplier for the device-side API."""
+    _fields_ = [("v", ctypes.c_double), ("qh", ctypes.c_double), ("ql", ctypes.c_double)]
+
+
 SIGNATURES = {
     "nn_seed": (_int, [_u64, _pu64]),
     "nn_skip": (_int, [_u64, _u64, _pu64]),
@@ -137,6 +145,8 @@ SIGNATURES = {
     "nn_default_cfg": (_int, [_int, _u64, ctypes.POINTER(LaunchCfg)]),
     "nn_fill": (_int, [_u64, _vp, _u64, _vp, ctypes.POINTER(LaunchCfg)]),
     "nn_consume": (_int, [_pu64, _u64, _int, _vp, _vp, ctypes.POINTER(LaunchCfg)]),
+    "nn_dev_mult_pow": (_int, [_u64, ctypes.POINTER(DevMult)]),
+    "nn_dev_skip_table": (_int, [ctypes.POINTER(ctypes.c_void_p)]),
     "nn_strerror": (ctypes.c_char_p, [_int]),
     "nn_last_error": (ctypes.c_char_p, []),
     "nn_version": (ctypes.c_char_p, []),

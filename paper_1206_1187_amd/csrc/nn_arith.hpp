@@ -21,6 +21,8 @@
 
 #include <stdint.h>
 
+#include "nn_device.h"
+
 #if defined(__HIPCC__)
 #define NN_HD __host__ __device__ __forceinline__
 #else
@@ -59,26 +61,11 @@ struct Mult {
 };
 
 // ---------------------------------------------------------------- FP64 --
-// r = v z - q m with q = rint(z (qh + ql)).  Exactness (all values are
-// integers below 2^106, m < 2^53 < 2m):
-//  * ph + pl == v z and sh + sl == q m exactly (FMA two-product);
-//  * |q - v z/m| <= 0.75 + 2^-52, because fl(z qh + fl(z ql)) is within
-//    one rounding of v z/m and rint adds at most 0.5 (0.5 in total when the
-//    estimate is >= 2^52, where its ulp is already 1); so |r| < m;
-//  * ph - sh is exact (either both are within a factor two of each other,
-//    Sterbenz, or the difference is an integer below 2^53), pl - sl is an
-//    integer below 2^53 in magnitude, and r itself is an integer below m.
-// The translation unit is built with FP contraction off so none of these
-// products is fused into a neighbouring add.
+// The exact FP64 reduction of the public device header (nn_dev_mulmod, whose
+// comment carries the proof).  Translation units are built with FP
+// contraction off so none of its products is fused into a neighbouring add.
 NN_HD double mm_fp64(double z, double v, double qh, double ql) {
-    const double ph = v * z;
-    const double pl = __builtin_fma(v, z, -ph);
-    const double e = __builtin_fma(z, qh, z * ql);
-    const double q = __builtin_rint(e);
-    const double sh = q * kModD;
-    const double sl = __builtin_fma(q, kModD, -sh);
-    const double r = (ph - sh) + (pl - sl);
-    return r < 0.0 ? r + kModD : r;
+    return nn_dev_mulmod(z, nn_dev_mult{v, qh, ql});
 }
 
 // ------------------------------------------------------------- Barrett --
@@ -110,6 +97,21 @@ NN_HD uint64_t mm_montgomery(uint64_t z, uint64_t vmont) {
     const uint64_t u = (uint64_t)t * kMontNInv;
     const u128 s = t + (u128)u * kMod;
     const uint64_t r = (uint64_t)(s >> 64);
+    return r >= kMod ? r - kMod : r;
+}
+
+// ---------------------------------------------------- Modified Barrett --
+// Section 3.1's Modified Barrett reduction, which only computes the step of
+// Eq. 3 itself, 2^53 z mod m: with x = 2^53 z, Barrett's first quotient
+// digit floor(x / 2^53) is z and x mod 2^53 is 0, so the quotient estimate
+// is q = floor(mu z / 2^53) (mu = floor(2^106/m) as above) and the
+// remainder is 2^53 - (q m mod 2^53), brought below m by one subtraction.
+// Exact for z < m: q is floor(x/m) or one less and the true remainder stays
+// below 2^53 in both cases.
+NN_HD uint64_t mm_modbarrett_step(uint64_t z) {
+    const uint64_t q = (uint64_t)(((u128)kBarrettMu * z) >> 53);
+    const uint64_t low53 = (q * kMod) & ((1ULL << 53) - 1);
+    const uint64_t r = (1ULL << 53) - low53;
     return r >= kMod ? r - kMod : r;
 }
 

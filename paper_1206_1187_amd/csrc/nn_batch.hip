@@ -17,6 +17,17 @@
 
 namespace nn {
 
+// A descriptor read through the scalar unit, field by field.
+__device__ __forceinline__ BatchDesc load_desc(const_ptr<BatchDesc> p) {
+    BatchDesc D;
+    D.src = p->src;
+    D.pos = p->pos;
+    D.len = p->len;
+    D.out_off = p->out_off;
+    D.row_start = p->row_start;
+    return D;
+}
+
 // src * (2^53)^k for any k < 2^52 through the four 13-bit skip tables.
 template <class V>
 __device__ __forceinline__ typename V::S skip_any(uint64_t src, uint64_t k,
@@ -31,24 +42,24 @@ __device__ __forceinline__ typename V::S skip_any(uint64_t src, uint64_t k,
 // Stores row r's pair of lane l: x_b = 2(jr*B + l) + 1 - s, x_a = x_b - 1.
 // `full` (uniform) says every pair of the row lies inside the window.
 template <class V, int KIND, bool NT>
-__device__ __forceinline__ void store_pair(uint64_t* out, const BatchDesc& D, uint64_t xb,
-                                           typename V::S za, typename V::S zb, bool full) {
-    uint64_t* const q = out + (D.out_off + xb - 1);  // global index of x_a, even
+__device__ __forceinline__ void store_pair(global_ptr<uint64_t> out, const BatchDesc& D,
+                                           uint64_t xb, typename V::S za, typename V::S zb,
+                                           bool full) {
+    const global_ptr<uint64_t> p = out + (D.out_off + xb - 1);  // global index of x_a, even
     if (full) {
         u64x2 v;
         v.x = out_bits<V, KIND>(za);
         v.y = out_bits<V, KIND>(zb);
-        put<NT>(reinterpret_cast<u64x2*>(q), v);
+        put<NT>(reinterpret_cast<global_ptr<u64x2>>(p), v);
         return;
     }
     const bool vb = xb < D.len;
     const bool va = xb >= 1 && xb - 1 < D.len;
-    uint64_t* const p = out + (D.out_off + xb - 1);  // global index of x_a, even
     if (va && vb) {
         u64x2 v;
         v.x = out_bits<V, KIND>(za);
         v.y = out_bits<V, KIND>(zb);
-        put<NT>(reinterpret_cast<u64x2*>(p), v);
+        put<NT>(reinterpret_cast<global_ptr<u64x2>>(p), v);
     } else if (vb) {
         put<NT>(p + 1, out_bits<V, KIND>(zb));
     } else if (va) {
@@ -56,19 +67,30 @@ __device__ __forceinline__ void store_pair(uint64_t* out, const BatchDesc& D, ui
     }
 }
 
+template <class V, int KIND>
+__device__ __forceinline__ u64x2 pair_bits(typename V::S za, typename V::S zb) {
+    u64x2 v;
+    v.x = out_bits<V, KIND>(za);
+    v.y = out_bits<V, KIND>(zb);
+    return v;
+}
+
 // Workgroups form clusters of `cluster` consecutive workgroups; cluster c
 // takes the contiguous row range [n_rows*c/C, n_rows*(c+1)/C) of the C =
 // grid/cluster clusters, and member i of the cluster takes its rows
-// r0 + i, r0 + i + cluster, ...  Two rows in flight: (za, zb) hold row r
-// and (zc, zd) row r + cluster of the current window; all four advance by
-// JB2 = (2^53)^(4*block*cluster) per step.
+// r0 + i, r0 + i + cluster, ...  Each window met is one segment: a fresh
+// skip-ahead, then the member's rows of that window in three parts -- the
+// partial first row of a window at an odd output offset, a branch-free loop
+// over full rows with two rows (four chains) in flight, and the window's
+// partial last row.
 template <class V, int KIND, bool NT, bool INDEXED>
 __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
-    const BatchHeader* hdr = a.ws;
+    // The workspace is written before the launch: scalar loads.
+    const const_ptr<BatchHeader> hdr = as_const(a.ws);
     const uint32_t n_desc = hdr->n_desc;
     const uint64_t n_rows = hdr->n_rows;
-    uint64_t* const out = hdr->out;
-    const BatchDesc* __restrict__ desc = reinterpret_cast<const BatchDesc*>(hdr + 1);
+    const global_ptr<uint64_t> out = as_global(hdr->out);
+    const const_ptr<BatchDesc> desc = reinterpret_cast<const_ptr<BatchDesc>>(hdr + 1);
     const uint32_t B = blockDim.x;
     const uint32_t l = threadIdx.x;
     const uint32_t K = a.cluster;
@@ -76,65 +98,80 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
     const uint32_t c = blockIdx.x / K;
     const uint32_t i = blockIdx.x % K;
     const uint64_t r1 = n_rows * (c + 1) / n_clusters;
-    const uint64_t r_first = n_rows * c / n_clusters + i;
-    if (r_first >= r1 || n_desc == 0) return;
-    // The last window whose first row is at or before r_first (binary search).
+    uint64_t r = n_rows * c / n_clusters + i;
+    if (r >= r1 || n_desc == 0) return;
+    // The last window whose first row is at or before r (binary search).
     uint32_t lo = 0, hi = n_desc - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
-        if (desc[mid].row_start <= r_first)
+        if (desc[mid].row_start <= r)
             lo = mid;
         else
             hi = mid - 1;
     }
     uint32_t d = lo;
-    BatchDesc D = desc[d];
-    uint64_t next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
-    bool fresh = true;
-    typename V::S za = V::load(1), zb = V::load(1), zc = V::load(1), zd = V::load(1);
-    for (uint64_t r = r_first; r < r1;) {
-        if (r >= next_start) {  // enter a later window (empty ones have no rows)
-            do {
-                ++d;
-                next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
-            } while (r >= next_start);
-            D = desc[d];
-            fresh = true;
+    const uint64_t BK = (uint64_t)B * K;  // pairs from one of the member's rows to the next
+    while (r < r1) {
+        uint64_t next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
+        while (r >= next_start) {  // a later window (empty ones have no rows)
+            ++d;
+            next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
         }
-        const uint32_t s = (uint32_t)(D.out_off & 1u);
-        const uint64_t xb = 2ull * ((r - D.row_start) * B + l) + 1 - s;
-        if (fresh) {
-            // src * (2^53)^(pos + x_b + 1): the window's element x_b.
-            if constexpr (INDEXED)
-                zb = skip_any<V>(hdr->states[D.src], D.pos + xb + 1, a.t_sk);
-            else
-                zb = skip_any<V>(D.src, D.pos + xb + 1, a.t_sk);
-            za = V::mul(zb, a.Minv);
-            zc = V::mul(za, a.JB);
-            zd = V::mul(zb, a.JB);
-            fresh = false;
-        }
+        const BatchDesc D = load_desc(desc + d);
         const uint64_t seg_end = next_start < r1 ? next_start : r1;
-        // Row jr covers window elements [2 jr B - s, 2 (jr + 1) B - s).
-        const uint64_t jr = r - D.row_start;
-        const bool full0 = (jr > 0 || s == 0) && 2ull * (jr + 1) * B - s <= D.len;
-        const bool full1 = 2ull * (jr + K + 1) * B - s <= D.len;
-        store_pair<V, KIND, NT>(out, D, xb, za, zb, full0);
-        if (r + K < seg_end) {
-            store_pair<V, KIND, NT>(out, D, xb + 2ull * B * K, zc, zd, full1);
-            za = V::mul(za, a.JB2);
-            zb = V::mul(zb, a.JB2);
-            zc = V::mul(zc, a.JB2);
-            zd = V::mul(zd, a.JB2);
-            r += 2ull * K;
-        } else {
-            // The window or the range ends within the next K rows: one row.
+        const uint32_t s = (uint32_t)(D.out_off & 1u);
+        // Row j of the window covers its elements [2 j B - s, 2 (j + 1) B - s);
+        // lane l owns x_a = x_b - 1 and x_b = 2 (j B + l) + 1 - s.
+        uint64_t j = r - D.row_start;
+        const uint64_t j_end = seg_end - D.row_start;
+        uint64_t xb = 2ull * (j * B + l) + 1 - s;
+        // src * (2^53)^(pos + x_b + 1): the window's element x_b.
+        typename V::S zb;
+        if constexpr (INDEXED)
+            zb = skip_any<V>(as_const(hdr->states)[D.src], D.pos + xb + 1, a.t_sk);
+        else
+            zb = skip_any<V>(D.src, D.pos + xb + 1, a.t_sk);
+        typename V::S za = V::mul(zb, a.Minv);
+        if (j < s) {  // row 0 of a window at an odd offset starts with a half pair
+            store_pair<V, KIND, NT>(out, D, xb, za, zb, false);
             za = V::mul(za, a.JB);
             zb = V::mul(zb, a.JB);
-            zc = V::mul(zc, a.JB);
-            zd = V::mul(zd, a.JB);
-            r += K;
+            j += K;
+            xb += 2 * BK;
         }
+        // Rows below j_full lie wholly inside the window.
+        const uint64_t j_full = (D.len + s) / (2ull * B);
+        const uint64_t j_stop = j_full < j_end ? j_full : j_end;
+        if (j < j_stop) {
+            uint64_t m = (j_stop - j + K - 1) / K;  // the member's full rows
+            global_ptr<u64x2> p = reinterpret_cast<global_ptr<u64x2>>(out + (D.out_off + xb - 1));
+            typename V::S zc = V::mul(za, a.JB), zd = V::mul(zb, a.JB);
+            j += m * K;
+            xb += 2 * BK * m;
+            for (; m >= 2; m -= 2) {
+                put<NT>(p, pair_bits<V, KIND>(za, zb));
+                put<NT>(p + BK, pair_bits<V, KIND>(zc, zd));
+                p += 2 * BK;
+                za = V::mul(za, a.JB2);
+                zb = V::mul(zb, a.JB2);
+                zc = V::mul(zc, a.JB2);
+                zd = V::mul(zd, a.JB2);
+            }
+            if (m) {
+                put<NT>(p, pair_bits<V, KIND>(za, zb));
+                za = zc;
+                zb = zd;
+            }
+        }
+        // The window's last row when it ends inside a row.
+        while (j < j_end) {
+            store_pair<V, KIND, NT>(out, D, xb, za, zb, false);
+            za = V::mul(za, a.JB);
+            zb = V::mul(zb, a.JB);
+            j += K;
+            xb += 2 * BK;
+        }
+        r = D.row_start + j;
     }
 }
 
@@ -158,15 +195,10 @@ __global__ __launch_bounds__(256) void k_batch_map(BatchArgs a) {
     }
 }
 
-// src * (2^53)^k, k < 2^56, through the LDS copy of the 8-bit skip tables.
+// src * (2^53)^k, k < 2^56, through the LDS copy of the 8-bit skip tables
+// (the public device-side skip, nn_dev_skip).
 __device__ __forceinline__ double skip8(uint64_t src, uint64_t k, const double* t8) {
-    double z = (double)src;
-#pragma unroll
-    for (uint32_t lvl = 0; lvl < kSkip8Levels; ++lvl) {
-        const double* e = t8 + 3 * (lvl * kSkip8Size + ((k >> (8 * lvl)) & 0xff));
-        z = mm_fp64(z, e[0], e[1], e[2]);
-    }
-    return z;
+    return nn_dev_skip((double)src, k, reinterpret_cast<const nn_dev_mult*>(t8));
 }
 
 // Interleaved batch kernel: workgroup w takes batch rows w, w + G, ...;
@@ -178,10 +210,11 @@ __global__ __launch_bounds__(256) void k_batch_il(BatchArgs a) {
     for (uint32_t i = threadIdx.x; i < kSkip8Levels * kSkip8Size * 3; i += blockDim.x)
         t8[i] = a.t8[i];
     __syncthreads();
-    const BatchHeader* hdr = a.ws;
+    const const_ptr<BatchHeader> hdr = as_const(a.ws);
     const uint64_t n_rows = hdr->n_rows;
-    uint64_t* const out = hdr->out;
-    const BatchDesc* __restrict__ desc = reinterpret_cast<const BatchDesc*>(hdr + 1);
+    const global_ptr<uint64_t> out = as_global(hdr->out);
+    const const_ptr<BatchDesc> desc = reinterpret_cast<const_ptr<BatchDesc>>(hdr + 1);
+    const const_ptr<uint32_t> row_desc = as_const(a.row_desc);
     const uint32_t B = blockDim.x;
     const uint32_t l = threadIdx.x;
     const uint64_t G = gridDim.x;
@@ -189,9 +222,9 @@ __global__ __launch_bounds__(256) void k_batch_il(BatchArgs a) {
     BatchDesc D;
     double za = 1.0, zb = 1.0;
     for (uint64_t r = blockIdx.x; r < n_rows; r += G) {
-        const uint32_t d = a.row_desc[r];
+        const uint32_t d = row_desc[r];
         const bool same = d == d_prev;
-        if (!same) D = desc[d];
+        if (!same) D = load_desc(desc + d);
         const uint32_t s = (uint32_t)(D.out_off & 1u);
         const uint64_t xb = 2ull * ((r - D.row_start) * B + l) + 1 - s;
         if (same) {
@@ -200,7 +233,7 @@ __global__ __launch_bounds__(256) void k_batch_il(BatchArgs a) {
         } else {
             uint64_t src;
             if constexpr (INDEXED)
-                src = hdr->states[D.src];
+                src = as_const(hdr->states)[D.src];
             else
                 src = D.src;
             zb = skip8(src, D.pos + xb + 1, t8);

@@ -51,8 +51,10 @@ constexpr uint32_t kSkipLevels = 4;
 // Interleaved kernel (FP64 reduction): skip tables of 8 bits per level held
 // in LDS, t8[lvl][j] = (2^53)^(j * 2^(8 lvl)), lvl < 7 (2^56 > the period),
 // three doubles (v, qh, ql) per entry.
-constexpr uint32_t kSkip8Levels = 7;
-constexpr uint32_t kSkip8Size = 256;
+constexpr uint32_t kSkip8Levels = NN_DEV_SKIP_LEVELS;
+constexpr uint32_t kSkip8Size = NN_DEV_SKIP_SIZE;
+static_assert(kSkip8Levels == 7 && kSkip8Size == 256, "8-bit levels covering 2^56");
+static_assert(sizeof(nn_dev_mult) == 3 * sizeof(double), "t8 entries are nn_dev_mult");
 
 // Kernel arguments (fixed for the life of a plan).
 struct BatchArgs {

@@ -26,7 +26,7 @@ namespace {
 
 struct Resolved {
     uint32_t block, grid, mulmod, unroll, width, occupancy, ilp;
-    bool nontemporal, flat;
+    bool nontemporal, flat, consec;
     uint32_t lds;  // dynamic LDS bytes per workgroup that cap residency
 };
 
@@ -40,12 +40,58 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
     const bool aligned16 = ((uintptr_t)out % 16) == 0;
-    const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT;
+    const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE;
     if (c.flags & ~known) return fail(NN_EINVAL, "unknown flags 0x%x", c.flags);
-    if ((c.flags & NN_CFG_ROWS) && (c.flags & NN_CFG_FLAT))
-        return fail(NN_EINVAL, "NN_CFG_ROWS and NN_CFG_FLAT are exclusive");
+    const uint32_t layouts = c.flags & (NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE);
+    if (layouts & (layouts - 1))
+        return fail(NN_EINVAL, "NN_CFG_ROWS, NN_CFG_FLAT and NN_CFG_CONSECUTIVE are exclusive");
     r->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
+    r->consec = (c.flags & NN_CFG_CONSECUTIVE) != 0;
+    r->flat = false;
+    if (r->consec) {
+        // The paper's per-thread loop: Eq. 3's multiplier 2^53 with the
+        // Modified Barrett step, serial order restored through LDS.
+        r->mulmod = c.mulmod ? c.mulmod : (uint32_t)NN_MULMOD_MODBARRETT;
+        if (r->mulmod != NN_MULMOD_MODBARRETT)
+            return fail(NN_EINVAL, "the consecutive layout steps with NN_MULMOD_MODBARRETT only");
+        if (c.occupancy) return fail(NN_EINVAL, "occupancy applies to the flat layout only");
+        if (c.ilp > 1) return fail(NN_EINVAL, "ilp applies to the row layout only");
+        r->occupancy = 0;
+        r->lds = 0;
+        r->ilp = 1;
+        r->width = c.width ? c.width : (aligned16 ? 2u : 1u);
+        if (r->width != 1 && r->width != 2)
+            return fail(NN_EINVAL, "width %u: must be 1 or 2", r->width);
+        if (r->width == 2 && !aligned16)
+            return fail(NN_EINVAL, "width 2 needs a 16-byte aligned output (got %p)", out);
+        r->block = c.block ? c.block : kDefaultBlock;
+        if (r->block < 64 || r->block > 1024 || r->block % 64)
+            return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", r->block);
+        r->unroll = c.unroll ? c.unroll : 16u;
+        if (r->unroll < 2 || r->unroll > kConsecMaxE || (r->unroll & (r->unroll - 1)))
+            return fail(NN_EINVAL, "unroll %u: the consecutive layout takes 2, 4, 8, 16 or 32",
+                        r->unroll);
+        if (consec_lds_bytes(r->block, r->unroll) > d.lds_per_block)
+            return fail(NN_EINVAL, "block %u x unroll %u needs %u bytes of LDS (limit %u)",
+                        r->block, r->unroll, consec_lds_bytes(r->block, r->unroll),
+                        d.lds_per_block);
+        const uint64_t per_tile = (uint64_t)r->block * r->unroll;
+        const uint64_t max_grid = kMaxOffset / per_tile;
+        if (c.grid) {
+            if (c.grid > max_grid)
+                return fail(NN_EINVAL, "grid %u: grid*block*unroll must not exceed 2^25", c.grid);
+            r->grid = c.grid;
+        } else {
+            const uint64_t tiles = (count + per_tile - 1) / per_tile;
+            uint64_t cap = (uint64_t)(cus > 0 ? cus : 1) * 2;
+            if (cap > max_grid) cap = max_grid;
+            r->grid = (uint32_t)(tiles < cap ? (tiles ? tiles : 1) : cap);
+        }
+        return NN_OK;
+    }
     r->mulmod = c.mulmod ? c.mulmod : kd.mulmod;
+    if (r->mulmod == NN_MULMOD_MODBARRETT)
+        return fail(NN_EINVAL, "NN_MULMOD_MODBARRETT steps by 2^53 only: consecutive layout");
     if (r->mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", r->mulmod);
     r->occupancy = c.occupancy;
     r->lds = 0;
@@ -135,6 +181,24 @@ int nn_skip(uint64_t state, uint64_t k, uint64_t* state_out) {
     return ok();
 }
 
+int nn_dev_mult_pow(uint64_t k, nn_dev_mult* out) {
+    if (!out) return fail(NN_EINVAL, "out is NULL");
+    const Mult m = make_mult(h_skip(1, k));
+    out->v = m.v;
+    out->qh = m.qh;
+    out->ql = m.ql;
+    return ok();
+}
+
+int nn_dev_skip_table(const nn_dev_mult** table_out) {
+    if (!table_out) return fail(NN_EINVAL, "table_out is NULL");
+    DeviceTables* d = nullptr;
+    const int st = current_device(&d);
+    if (st != NN_OK) return st;
+    *table_out = reinterpret_cast<const nn_dev_mult*>(d->t8);
+    return ok();
+}
+
 int nn_init(int device) {
     int prev = -1;
     hipError_t e = hipGetDevice(&prev);
@@ -187,6 +251,20 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
     st = resolve_cfg(cfg, kind, count, *d, out_dev, &r);
     if (st) return st;
 
+    if (r.consec) {
+        ConsecArgs ca;
+        ca.out = (uint64_t*)out_dev;
+        ca.count = count;
+        ca.base = h_mulmod(s, kMult);
+        ca.J = make_mult(MultPowers::get().pow((uint64_t)r.grid * r.block * r.unroll));
+        ca.t_lo = d->t_lo;
+        ca.t_hi = d->t_hi;
+        hipError_t e = launch_generate_consec(kind, (int)r.unroll, (int)r.width, r.nontemporal,
+                                              r.grid, r.block, (hipStream_t)stream, ca);
+        if (e != hipSuccess) return fail(NN_EHIP, "generate launch: %s", hipGetErrorString(e));
+        *state = h_skip(s, count);
+        return ok();
+    }
     if (r.flat) {
         FlatArgs f;
         f.M1 = make_mult(kMult);
@@ -254,7 +332,9 @@ int nn_consume(uint64_t* state, uint64_t count, int kind, void* result_dev, void
     if (block < 64 || block > 1024 || block % 64)
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
     const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
-    if (mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", mulmod);
+    if (mulmod > NN_MULMOD_MONTGOMERY)
+        return fail(NN_EINVAL, "mulmod %u: nn_consume takes FP64, Barrett, Shoup or Montgomery",
+                    mulmod);
     uint32_t grid = c.grid;
     if (!grid) {
         // No stores to keep sequential: fill the device.
@@ -293,6 +373,7 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     Resolved r;
     st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r);
     if (st) return st;
+    if (r.consec) return fail(NN_EINVAL, "nn_fill has no consecutive layout");
     if (r.flat) {
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
@@ -415,11 +496,19 @@ const char* nn_version(void) { return "nn-alpha23 0.1.0 (gfx950)"; }
 
 int nn_debug_mulmod(int mulmod, const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t* out) {
     if (n && (!a || !b || !out)) return fail(NN_EINVAL, "NULL array");
-    if (mulmod < NN_MULMOD_DEFAULT || mulmod > NN_MULMOD_MONTGOMERY)
+    if (mulmod < NN_MULMOD_DEFAULT || mulmod > NN_MULMOD_MODBARRETT)
         return fail(NN_EINVAL, "mulmod %d unknown", mulmod);
     for (uint64_t i = 0; i < n; ++i)
         if (!valid_state(a[i]) || !valid_state(b[i]))
             return fail(NN_EINVAL, "pair %llu is not a pair of units", (unsigned long long)i);
+    if (mulmod == NN_MULMOD_MODBARRETT) {
+        for (uint64_t i = 0; i < n; ++i)
+            if (b[i] != kMult)
+                return fail(NN_EINVAL, "NN_MULMOD_MODBARRETT multiplies by 2^53 only (pair %llu)",
+                            (unsigned long long)i);
+        for (uint64_t i = 0; i < n; ++i) out[i] = mm_modbarrett_step(a[i]);
+        return ok();
+    }
     for (uint64_t i = 0; i < n; ++i) {
         const Mult f = make_mult(b[i]);
         switch (mulmod) {

@@ -31,6 +31,27 @@ __device__ __forceinline__ uint64_t out_bits(typename V::S z) {
         return (uint64_t)__double_as_longlong(V::to_f64(z));
 }
 
+// Address-space views.  Stores through a global pointer count only against
+// the vector-memory counter; through a generic (flat) pointer they also
+// count against the scalar one, so every wait for a scalar load would wait
+// for them too.  Data read through a constant pointer must not change while
+// the kernel runs (it is written before the launch); uniform loads through
+// it go to the scalar unit, and the loop that consumes them never waits on
+// its own outstanding stores.
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ global_ptr<T> as_global(T* p) {
+    return (global_ptr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ const_ptr<T> as_const(const T* p) {
+    return (const_ptr<T>)p;
+}
+
 template <bool NT, class P, class X>
 __device__ __forceinline__ void put(P* p, X x) {
     if constexpr (NT)

@@ -338,6 +338,86 @@ hipError_t launch_fill_flat(bool nt, uint32_t lds, hipStream_t s, uint64_t* out,
 }
 
 // Kernel selector: W = 1, W = 2, or W = 2 with IL = 2 or 4 rows in flight.
+// ------------------------------------------------------- consecutive --
+// The paper's per-thread loop (Section 3.2) with its Modified Barrett step
+// (Section 3.1), kept in serial memory order by an LDS transpose.  Element
+// j = t*E + e of a tile sits at LDS word j + j/E (one pad word per thread,
+// so the E-strided writes of a wavefront spread over the banks).
+template <int KIND, int E, int W, bool NT>
+__global__ __launch_bounds__(1024) void k_generate_consec(ConsecArgs a) {
+    extern __shared__ uint64_t tile[];
+    const uint32_t B = blockDim.x;
+    const uint32_t t = threadIdx.x;
+    const uint64_t per_tile = (uint64_t)B * E;
+    const uint64_t n_tiles = (a.count + per_tile - 1) / per_tile;
+    uint64_t ti = blockIdx.x;
+    if (ti >= n_tiles) return;
+    // The state of this thread's first element in tile ti.
+    uint64_t z0 = thread_start<VarShoup>(a.base, ti * per_tile + (uint64_t)t * E, a.t_lo, a.t_hi);
+    const global_ptr<uint64_t> out = as_global(a.out);
+    for (; ti < n_tiles; ti += gridDim.x) {
+        uint64_t z = z0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint64_t bits = KIND == 0 ? z : (uint64_t)__double_as_longlong((double)z * kRecip);
+            tile[t * (E + 1) + e] = bits;
+            z = mm_modbarrett_step(z);
+        }
+        z0 = VarShoup::mul(z0, a.J);
+        __syncthreads();
+        const uint64_t first = ti * per_tile;
+        const uint64_t here = a.count - first < per_tile ? a.count - first : per_tile;
+        if (W == 2 && here == per_tile) {
+#pragma unroll
+            for (int i = 0; i < E / 2; ++i) {
+                const uint32_t j = 2 * (i * B + t);  // even, so j and j+1 share a thread
+                const uint32_t w = j + j / E;
+                u64x2 v;
+                v.x = tile[w];
+                v.y = tile[w + 1];
+                put<NT>(reinterpret_cast<global_ptr<u64x2>>(out + first + j), v);
+            }
+        } else {
+            for (uint32_t j = t; j < here; j += B) put<NT>(out + first + j, tile[j + j / E]);
+        }
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
+template <int KIND, int E, int W>
+static hipError_t consec_one(bool nt, uint32_t grid, uint32_t block, hipStream_t s,
+                             const ConsecArgs& a) {
+    const uint32_t lds = consec_lds_bytes(block, E);
+    if (nt) {
+        k_generate_consec<KIND, E, W, true><<<grid, block, lds, s>>>(a);
+    } else {
+        k_generate_consec<KIND, E, W, false><<<grid, block, lds, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <int KIND, int W>
+static hipError_t consec_e(int E, bool nt, uint32_t grid, uint32_t block, hipStream_t s,
+                           const ConsecArgs& a) {
+    switch (E) {
+        case 2: return consec_one<KIND, 2, W>(nt, grid, block, s, a);
+        case 4: return consec_one<KIND, 4, W>(nt, grid, block, s, a);
+        case 8: return consec_one<KIND, 8, W>(nt, grid, block, s, a);
+        case 16: return consec_one<KIND, 16, W>(nt, grid, block, s, a);
+        case 32: return consec_one<KIND, 32, W>(nt, grid, block, s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_generate_consec(int kind, int E, int width, bool nt, uint32_t grid,
+                                  uint32_t block, hipStream_t s, const ConsecArgs& a) {
+    if (kind == 0)
+        return width == 2 ? consec_e<0, 2>(E, nt, grid, block, s, a)
+                          : consec_e<0, 1>(E, nt, grid, block, s, a);
+    return width == 2 ? consec_e<1, 2>(E, nt, grid, block, s, a)
+                      : consec_e<1, 1>(E, nt, grid, block, s, a);
+}
+
 template <class V, int KIND, int W, int IL, int U, bool NT>
 static hipError_t gen_one(uint32_t grid, uint32_t block, hipStream_t s, const GenArgs& a) {
     if constexpr (W == 1)

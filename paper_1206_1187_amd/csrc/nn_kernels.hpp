@@ -72,6 +72,30 @@ hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, uint32_t
 hipError_t launch_fill_flat(bool nontemporal, uint32_t lds_bytes, hipStream_t stream,
                             uint64_t* out, uint64_t count, uint64_t value);
 
+// Consecutive layout: the output is cut into tiles of block*E elements;
+// workgroup w makes tiles w, w + grid, ...  In a tile, thread t makes
+// elements t*E .. t*E + E-1 one after another with the Modified Barrett
+// step by 2^53, parks them in LDS, and the workgroup then stores the tile
+// in serial order, lane-contiguous (16 bytes per lane when width 2).
+// `base` is state * 2^53 (element 0), J = (2^53)^(grid*block*E) moves a
+// thread to its next tile, and grid*block*E <= kMaxOffset.
+constexpr uint32_t kConsecMaxE = 32;
+
+struct ConsecArgs {
+    uint64_t* out;
+    uint64_t count;
+    uint64_t base;
+    Mult J;
+    const Mult* t_lo;
+    const Mult* t_hi;
+};
+
+// E in {2, 4, 8, 16, 32}, width 1 or 2; lds_bytes = block*(E+1)*8.
+hipError_t launch_generate_consec(int kind, int E, int width, bool nontemporal, uint32_t grid,
+                                  uint32_t block, hipStream_t stream, const ConsecArgs& a);
+
+inline uint32_t consec_lds_bytes(uint32_t block, uint32_t E) { return block * (E + 1) * 8; }
+
 hipError_t launch_fill(int width, int unroll, bool nontemporal, uint32_t grid, uint32_t block,
                        hipStream_t stream, uint64_t* out, uint64_t T, uint64_t e_full,
                        uint32_t rem, uint64_t value);

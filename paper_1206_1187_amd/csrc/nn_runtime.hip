@@ -212,7 +212,9 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     const uint32_t cluster = c.cluster ? c.cluster : 1;
     if (cluster > 64) return fail(NN_EINVAL, "cluster %u: at most 64", cluster);
     const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
-    if (mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", mulmod);
+    if (mulmod > NN_MULMOD_MONTGOMERY)
+        return fail(NN_EINVAL, "mulmod %u: batches take FP64, Barrett, Shoup or Montgomery",
+                    mulmod);
     uint32_t grid = c.grid;
     if (!grid) {
         grid = (uint32_t)((uint64_t)d->cus * kd.grid_num / kd.grid_den);

@@ -144,6 +144,29 @@ def test_host_build_of_reductions_is_exact(variant):
     assert bad.size == 0, [(int(a[i]), int(b[i]), int(got[i]), int(want[i])) for i in bad[:5]]
 
 
+def test_host_build_of_modified_barrett_step_is_exact():
+    """Section 3.1's Modified Barrett step (2^53 z mod 3^33) on states whose
+    residue sits at the edges: 1, 2, m-1, m-2, and on both sides of the
+    boundary where the quotient estimate falls one short (residues near
+    (2^53 - m) = 0.62 m), plus random states; expected from Python's
+    integers, a sample also from the oracle's own comparator."""
+    M53 = pow(2, 53, M)
+    inv = pow(M53, -1, M)
+    rng = random.Random(53)
+    edge = [1, 2, 4, M - 1, M - 2, M - 4, 2 ** 53 - M, 2 ** 53 - M - 1, 2 ** 53 - M + 1]
+    edge += [int(M * f) + d for f in (0.6172, 0.6203, 0.5, 0.25) for d in range(-40, 41)]
+    zs = [r * inv % M for r in edge if r % 3]
+    zs += [rng.randrange(1, M) for _ in range(100000)]
+    zs = np.array([z for z in zs if z % 3], dtype=np.uint64)
+    got = nn.debug_mulmod("modbarrett", zs, np.full(zs.size, M53, dtype=np.uint64))
+    want = np.array([(int(z) << 53) % M for z in zs.tolist()], dtype=np.uint64)
+    assert np.array_equal(got, want)
+    for i in range(0, zs.size, 101):
+        assert int(got[i]) == orc.modbarrett_step(int(zs[i]))
+    with pytest.raises(nn.NNError):  # only the multiplier 2^53
+        nn.debug_mulmod("modbarrett", [5], [7])
+
+
 def test_debug_mulmod_rejects_non_units():
     with pytest.raises(nn.NNError):
         nn.debug_mulmod("fp64", [3], [5])
@@ -187,3 +210,26 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_native, "_lib", None)
     with pytest.raises(_native.NativeLibraryMissing):
         nn.seed(wl.INDEX_MIN)
+
+
+def test_dev_mult_pow_is_the_power_and_its_quotient():
+    """nn_dev_mult_pow(k): v = (2^53)^(k mod P) mod 3^33 (Python integers)
+    and qh + ql = v / 3^33 to double-double accuracy (exact rationals), far
+    inside what nn_dev_mulmod needs: its remainder stays in (-3^33, 3^33)
+    while |q - v z / 3^33| < 1, i.e. while z times this error stays below a
+    quarter (z < 2^53)."""
+    from fractions import Fraction
+    mult = pow(2, 53, M)
+    ks = [0, 1, 2, 53, 1023, 1 << 20, P - 1, P, P + 1, 2 ** 63, 2 ** 64 - 1]
+    rng = random.Random(5)
+    ks += [rng.getrandbits(64) for _ in range(20)]
+    for k in ks:
+        v, qh, ql = nn.dev_mult_pow(k)
+        want = pow(mult, k % P, M)
+        assert v == float(want) and int(v) == want, k
+        err = abs(Fraction(qh) + Fraction(ql) - Fraction(want, M))
+        # 106 bits of floor(v 2^128 / 3^33) 2^-128: relative 2^-105 or absolute 2^-128
+        assert err <= Fraction(want, M) / 2 ** 105 + Fraction(1, 2 ** 128), k
+        assert abs(ql) <= abs(qh) * 2.0 ** -52, k
+    with pytest.raises(nn.NNError):
+        _native.check(_native.lib().nn_dev_mult_pow(1, None))

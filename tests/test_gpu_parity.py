@@ -291,3 +291,55 @@ def test_fused_consumer_state_sum_exact(mulmod):
         torch.cuda.synchronize()
         reff, _ = orc.gen(z0, count, "f64", threads=0)
         assert abs(float(resf.cpu()[0]) - float(reff.sum())) <= 1e-9 * max(1.0, float(reff.sum()))
+
+
+def test_consecutive_layout_bit_exact():
+    """The consecutive layout (the paper's per-thread loop with the Modified
+    Barrett step, serial order restored through LDS): tile sizes from 2 to
+    32 outputs per thread, ragged and single-element tails, several tiles
+    per workgroup, 16- and 8-byte stores, both kinds."""
+    z0 = orc.seed(wl.INDEX_MIN + 4099)
+    ref_u, _ = orc.gen(z0, 300_000, "u64", threads=0)
+    ref_f, _ = orc.gen(z0, 300_000, "f64", threads=0)
+    for block, E, grid in [(256, 0, 0), (64, 2, 3), (128, 32, 5), (512, 8, 0), (1024, 4, 7),
+                           (64, 32, 1), (192, 16, 2)]:
+        tile = block * (E or 16)
+        for count in (1, 2, 17, tile - 1, tile, tile + 1, 3 * tile + 5, 99_991, 300_000):
+            if count > 300_000:
+                continue
+            cfg = nn.make_cfg(block=block, grid=grid, unroll=E, layout="consecutive")
+            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                for guard in (512, 513):  # 16-byte and 8-byte aligned outputs
+                    _say("consecutive", block, E, grid, count, kind, guard)
+                    got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=guard)
+                    assert np.array_equal(got, ref.view(np.uint64)[:count]), \
+                        (block, E, grid, count, kind, guard)
+                    assert zn == orc.skip(z0, count)
+    cfg = nn.make_cfg(layout="consecutive", temporal=True, width=1)
+    got, _ = _gen_guarded(z0, 99_991, "f64", cfg=cfg)
+    assert np.array_equal(got, ref_f.view(np.uint64)[:99_991])
+
+
+def test_consecutive_layout_validation():
+    z0 = orc.seed(wl.INDEX_MIN)
+    buf = _sentinel_buffer(4097)
+    out = buf[:4096].view(torch.float64)
+    bad = [nn.make_cfg(layout="consecutive", mulmod="fp64"),
+           nn.make_cfg(layout="consecutive", unroll=3),
+           nn.make_cfg(layout="consecutive", unroll=64),
+           nn.make_cfg(layout="consecutive", ilp=2),
+           nn.make_cfg(layout="consecutive", occupancy=3),
+           nn.make_cfg(layout="consecutive", block=1024, unroll=32),   # LDS
+           nn.make_cfg(layout="consecutive", grid=(1 << 25) // (256 * 16) + 1),
+           nn.make_cfg(mulmod="modbarrett"),                           # rows
+           nn.make_cfg(mulmod="modbarrett", layout="flat")]
+    for cfg in bad:
+        with pytest.raises(nn.NNError):
+            nn.generate_into(z0, out, cfg=cfg)
+    with pytest.raises(nn.NNError):  # 16-byte stores on an 8-byte aligned output
+        nn.generate_into(z0, buf[1:4097].view(torch.float64),
+                         cfg=nn.make_cfg(layout="consecutive", width=2))
+    with pytest.raises(nn.NNError):
+        nn.fill(out, 0, cfg=nn.make_cfg(layout="consecutive"))
+    torch.cuda.synchronize()
+    assert (_bits(buf) == SENTINEL).all()
