@@ -91,7 +91,8 @@ typedef enum nn_mulmod {
  * mulmod: an nn_mulmod; NN_MULMOD_MODBARRETT only, and only it, with the
  * consecutive layout (0 selects it there).
  * unroll: 1, 2, 4 or 8 iterations of the step loop per trip (rows); outputs
- * per thread and tile, 2, 4, 8, 16 or 32 (consecutive, default 16).
+ * per thread and tile, 2, 4, 8, 16 or 32 (consecutive, default 4 with 512
+ * threads per workgroup).
  * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable (default:
  * non-temporal streaming stores); NN_CFG_ROWS / NN_CFG_FLAT force a layout.
  * width: outputs per lane and store, 1 (8-byte stores) or 2 (16-byte

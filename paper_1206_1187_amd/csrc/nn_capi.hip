@@ -64,10 +64,12 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
             return fail(NN_EINVAL, "width %u: must be 1 or 2", r->width);
         if (r->width == 2 && !aligned16)
             return fail(NN_EINVAL, "width 2 needs a 16-byte aligned output (got %p)", out);
-        r->block = c.block ? c.block : kDefaultBlock;
+        // Defaults from a sweep on MI355X (2^30 f64 outputs): 512 threads
+        // making 4 consecutive outputs each per tile, one workgroup per CU.
+        r->block = c.block ? c.block : 512u;
         if (r->block < 64 || r->block > 1024 || r->block % 64)
             return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", r->block);
-        r->unroll = c.unroll ? c.unroll : 16u;
+        r->unroll = c.unroll ? c.unroll : 4u;
         if (r->unroll < 2 || r->unroll > kConsecMaxE || (r->unroll & (r->unroll - 1)))
             return fail(NN_EINVAL, "unroll %u: the consecutive layout takes 2, 4, 8, 16 or 32",
                         r->unroll);
@@ -83,7 +85,7 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
             r->grid = c.grid;
         } else {
             const uint64_t tiles = (count + per_tile - 1) / per_tile;
-            uint64_t cap = (uint64_t)(cus > 0 ? cus : 1) * 2;
+            uint64_t cap = (uint64_t)(cus > 0 ? cus : 1);
             if (cap > max_grid) cap = max_grid;
             r->grid = (uint32_t)(tiles < cap ? (tiles ? tiles : 1) : cap);
         }

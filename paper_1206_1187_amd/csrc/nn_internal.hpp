@@ -41,7 +41,23 @@ constexpr uint32_t kDefaultBlock = 256;
 
 }  // namespace nn
 
-// A batch plan: workspace, pinned staging, and a graph of (copy, kernel).
+// A batch plan: two slots, each a device workspace, a pinned staging copy
+// of it and a graph of the batch kernel (with the interleaved kernel's
+// row-map pre-pass before it).  Batches alternate between the slots, so the
+// host prepares batch i+1 while batch i runs; a slot is reused only after
+// the batch that last used it has finished.
+struct nn_batch_slot {
+    size_t ws_bytes = 0;
+    void* ws_dev = nullptr;
+    void* ws_host = nullptr;      // pinned staging, same layout as ws_dev
+    uint32_t* row_map = nullptr;  // device, cap_rows entries (interleaved kernel)
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    nn::BatchArgs args;
+};
+
 struct nn_batch_plan {
     std::mutex mu;  // one batch call at a time per plan
     int device = 0;
@@ -50,20 +66,12 @@ struct nn_batch_plan {
     uint32_t mulmod = 0, block = 0, grid = 0, cluster = 1;
     bool nontemporal = true, use_graph = true, interleaved = false;
     uint64_t cap_rows = 0;
-    uint32_t* row_map = nullptr;  // device, cap_rows entries (interleaved kernel)
     uint32_t map_grid = 0;
     uint32_t max_streams = 0;
     uint64_t max_outputs = 0;
     uint32_t cap_desc = 0;
-    size_t ws_bytes = 0;
-    void* ws_dev = nullptr;
-    void* ws_host = nullptr;  // pinned staging, same layout as ws_dev
-    hipEvent_t done = nullptr;
-    bool pending = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy_node = nullptr, map_node = nullptr, kernel_node = nullptr;
-    nn::BatchArgs args;
+    nn_batch_slot slot[2];
+    int next = 0;  // the slot of the next batch
 };
 
 namespace nn {
@@ -74,14 +82,16 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
                 bool indexed, const uint64_t* states, nn_batch_plan** out);
 void plan_release(nn_batch_plan* p);
 
-// Waits until the plan's previous batch has consumed its staging.
+// Waits until the next batch's slot is free (the batch before the previous
+// one has finished).
 int plan_wait(nn_batch_plan* p);
-// True when the plan's last batch (if any) has finished on the device.
+// True when every batch of the plan has finished on the device.
 bool plan_idle(nn_batch_plan* p);
 // Staged descriptors of the next batch (capacity p->cap_desc); valid after
 // plan_wait().
 inline BatchDesc* plan_staged_descs(nn_batch_plan* p) {
-    return reinterpret_cast<BatchDesc*>(reinterpret_cast<BatchHeader*>(p->ws_host) + 1);
+    return reinterpret_cast<BatchDesc*>(reinterpret_cast<BatchHeader*>(p->slot[p->next].ws_host) +
+                                        1);
 }
 // Fills in the row prefix of the `nd` staged descriptors (their src, pos,
 // len and out_off set by the caller), uploads them and launches on

@@ -181,17 +181,88 @@ int current_device(DeviceTables** out) {
 // ---------------------------------------------------------------- plans --
 
 void plan_release(nn_batch_plan* p) {
-    if (p->done) {
-        (void)hipEventSynchronize(p->done);
-        (void)hipEventDestroy(p->done);
+    for (nn_batch_slot& q : p->slot) {
+        if (q.done) {
+            (void)hipEventSynchronize(q.done);
+            (void)hipEventDestroy(q.done);
+        }
+        if (q.exec) (void)hipGraphExecDestroy(q.exec);
+        if (q.graph) (void)hipGraphDestroy(q.graph);
+        if (q.ws_dev) (void)hipFree(q.ws_dev);
+        if (q.row_map) (void)hipFree(q.row_map);
+        if (q.ws_host) (void)hipHostFree(q.ws_host);
     }
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->ws_dev) (void)hipFree(p->ws_dev);
-    if (p->row_map) (void)hipFree(p->row_map);
-    if (p->ws_host) (void)hipHostFree(p->ws_host);
     delete p;
 }
+
+namespace {
+
+// Device and pinned memory, event and graph of one slot.
+int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
+                const uint64_t* states) {
+    q.ws_bytes = sizeof(BatchHeader) + (size_t)p->cap_desc * sizeof(BatchDesc);
+    hipError_t e = hipMalloc(&q.ws_dev, q.ws_bytes);
+    if (e == hipSuccess && p->interleaved)
+        e = hipMalloc((void**)&q.row_map, p->cap_rows * sizeof(uint32_t));
+    if (e != hipSuccess)
+        return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", q.ws_bytes, hipGetErrorString(e));
+    e = hipHostMalloc(&q.ws_host, q.ws_bytes, hipHostMallocDefault);
+    if (e != hipSuccess)
+        return fail(NN_ENOMEM, "pinned staging (%zu bytes): %s", q.ws_bytes, hipGetErrorString(e));
+    BatchHeader* hdr = (BatchHeader*)q.ws_host;
+    memset(hdr, 0, sizeof *hdr);
+    hdr->states = states;
+    e = hipEventCreateWithFlags(&q.done, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(NN_EHIP, "event: %s", hipGetErrorString(e));
+    const uint32_t block = p->block, cluster = p->cluster;
+    q.args.ws = (const BatchHeader*)q.ws_dev;
+    q.args.cluster = cluster;
+    q.args.JB = make_mult(MultPowers::get().pow(2ull * block * cluster));
+    q.args.JB2 = make_mult(MultPowers::get().pow(4ull * block * cluster));
+    q.args.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
+    q.args.t_lo = d.t_lo;
+    q.args.t_hi = d.t_hi;
+    q.args.t_sk = d.t_sk;
+    q.args.JG = make_mult(MultPowers::get().pow(2ull * block * p->grid));
+    q.args.t8 = d.t8;
+    q.args.row_desc = q.row_map;
+    if (!p->use_graph) return NN_OK;
+    // The graph holds the kernels; the descriptor upload before each replay
+    // is an ordinary async copy on the same stream (a copy node from pinned
+    // host memory measured slower on MI355X).
+    e = hipGraphCreate(&q.graph, 0);
+    hipGraphNode_t last = nullptr;
+    void* params[] = {&q.args};
+    if (e == hipSuccess && p->interleaved) {
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof kp);
+        kp.func = const_cast<void*>(batch_map_kernel());
+        kp.gridDim = dim3(p->map_grid);
+        kp.blockDim = dim3(256);
+        kp.kernelParams = params;
+        e = hipGraphAddKernelNode(&last, q.graph, nullptr, 0, &kp);
+    }
+    if (e == hipSuccess) {
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof kp);
+        kp.func = p->interleaved
+                      ? const_cast<void*>(batch_il_kernel(p->kind, p->nontemporal, p->indexed))
+                      : const_cast<void*>(
+                            batch_kernel((int)p->mulmod, p->kind, p->nontemporal, p->indexed));
+        kp.gridDim = dim3(p->grid);
+        kp.blockDim = dim3(block);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = params;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        e = hipGraphAddKernelNode(&node, q.graph, last ? &last : nullptr, last ? 1 : 0, &kp);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&q.exec, q.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(NN_EHIP, "batch graph: %s", hipGetErrorString(e));
+    return NN_OK;
+}
+
+}  // namespace
 
 int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_batch_cfg* cfg,
                 bool indexed, const uint64_t* states, nn_batch_plan** plan_out) {
@@ -249,73 +320,11 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->max_streams = max_streams;
     p->max_outputs = max_outputs;
     p->cap_desc = (uint32_t)cap_desc;
-    p->ws_bytes = sizeof(BatchHeader) + cap_desc * sizeof(BatchDesc);
-    hipError_t e = hipMalloc(&p->ws_dev, p->ws_bytes);
-    if (e == hipSuccess && p->interleaved)
-        e = hipMalloc((void**)&p->row_map, p->cap_rows * sizeof(uint32_t));
-    if (e != hipSuccess) {
-        plan_release(p);
-        return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", p->ws_bytes, hipGetErrorString(e));
-    }
-    e = hipHostMalloc(&p->ws_host, p->ws_bytes, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        plan_release(p);
-        return fail(NN_ENOMEM, "pinned staging (%zu bytes): %s", p->ws_bytes, hipGetErrorString(e));
-    }
-    BatchHeader* hdr = (BatchHeader*)p->ws_host;
-    memset(hdr, 0, sizeof *hdr);
-    hdr->states = states;
-    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        plan_release(p);
-        return fail(NN_EHIP, "event: %s", hipGetErrorString(e));
-    }
-    p->args.ws = (const BatchHeader*)p->ws_dev;
-    p->args.cluster = cluster;
-    p->args.JB = make_mult(MultPowers::get().pow(2ull * block * cluster));
-    p->args.JB2 = make_mult(MultPowers::get().pow(4ull * block * cluster));
-    p->args.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
-    p->args.t_lo = d->t_lo;
-    p->args.t_hi = d->t_hi;
-    p->args.t_sk = d->t_sk;
-    p->args.JG = make_mult(MultPowers::get().pow(2ull * block * grid));
-    p->args.t8 = d->t8;
-    p->args.row_desc = p->row_map;
-    if (p->use_graph) {
-        e = hipGraphCreate(&p->graph, 0);
-        if (e == hipSuccess)
-            e = hipGraphAddMemcpyNode1D(&p->copy_node, p->graph, nullptr, 0, p->ws_dev, p->ws_host,
-                                        sizeof(BatchHeader), hipMemcpyHostToDevice);
-        hipGraphNode_t last = p->copy_node;
-        void* params[] = {&p->args};
-        if (e == hipSuccess && p->interleaved) {
-            hipKernelNodeParams kp;
-            memset(&kp, 0, sizeof kp);
-            kp.func = const_cast<void*>(batch_map_kernel());
-            kp.gridDim = dim3(p->map_grid);
-            kp.blockDim = dim3(256);
-            kp.kernelParams = params;
-            e = hipGraphAddKernelNode(&p->map_node, p->graph, &last, 1, &kp);
-            last = p->map_node;
-        }
-        if (e == hipSuccess) {
-            hipKernelNodeParams kp;
-            memset(&kp, 0, sizeof kp);
-            kp.func = p->interleaved
-                          ? const_cast<void*>(batch_il_kernel(kind, p->nontemporal, indexed))
-                          : const_cast<void*>(batch_kernel((int)mulmod, kind, p->nontemporal,
-                                                           indexed));
-            kp.gridDim = dim3(grid);
-            kp.blockDim = dim3(block);
-            kp.sharedMemBytes = 0;
-            kp.kernelParams = params;
-            kp.extra = nullptr;
-            e = hipGraphAddKernelNode(&p->kernel_node, p->graph, &last, 1, &kp);
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
+    for (nn_batch_slot& q : p->slot) {
+        st = slot_create(p, q, *d, states);
+        if (st) {
             plan_release(p);
-            return fail(NN_EHIP, "batch graph: %s", hipGetErrorString(e));
+            return st;
         }
     }
     *plan_out = p;
@@ -323,26 +332,31 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
 }
 
 int plan_wait(nn_batch_plan* p) {
-    if (!p->pending) return NN_OK;
-    hipError_t e = hipEventSynchronize(p->done);
+    nn_batch_slot& q = p->slot[p->next];
+    if (!q.pending) return NN_OK;
+    hipError_t e = hipEventSynchronize(q.done);
     if (e != hipSuccess)
-        return fail(NN_EHIP, "waiting for the previous batch: %s", hipGetErrorString(e));
-    p->pending = false;
+        return fail(NN_EHIP, "waiting for an earlier batch: %s", hipGetErrorString(e));
+    q.pending = false;
     return NN_OK;
 }
 
 bool plan_idle(nn_batch_plan* p) {
-    if (!p->pending) return true;
-    if (hipEventQuery(p->done) == hipSuccess) {
-        p->pending = false;
-        return true;
+    bool idle = true;
+    for (nn_batch_slot& q : p->slot) {
+        if (!q.pending) continue;
+        if (hipEventQuery(q.done) == hipSuccess)
+            q.pending = false;
+        else
+            idle = false;
     }
-    return false;
+    return idle;
 }
 
 int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t stream) {
+    nn_batch_slot& q = p->slot[p->next];
     const uint64_t row = 2ull * p->block;
-    BatchHeader* hdr = (BatchHeader*)p->ws_host;
+    BatchHeader* hdr = (BatchHeader*)q.ws_host;
     BatchDesc* dd = plan_staged_descs(p);
     uint64_t rows = 0;
     for (uint32_t k = 0; k < nd; ++k) {
@@ -356,30 +370,28 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     hdr->n_desc = nd;
     hdr->n_rows = rows;
     const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc);
-    hipError_t e;
-    if (p->use_graph) {
-        e = hipGraphExecMemcpyNodeSetParams1D(p->exec, p->copy_node, p->ws_dev, p->ws_host, bytes,
-                                              hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipGraphLaunch(p->exec, stream);
-    } else {
-        e = hipMemcpyAsync(p->ws_dev, p->ws_host, bytes, hipMemcpyHostToDevice, stream);
-        BatchArgs copy = p->args;
+    hipError_t e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && p->use_graph) {
+        e = hipGraphLaunch(q.exec, stream);
+    } else if (e == hipSuccess) {
+        BatchArgs copy = q.args;
         void* params[] = {&copy};
-        if (e == hipSuccess && p->interleaved) {
+        if (p->interleaved) {
             e = hipLaunchKernel(batch_map_kernel(), dim3(p->map_grid), dim3(256), params, 0,
                                 stream);
             if (e == hipSuccess)
                 e = hipLaunchKernel(batch_il_kernel(p->kind, p->nontemporal, p->indexed),
                                     dim3(p->grid), dim3(p->block), params, 0, stream);
-        } else if (e == hipSuccess) {
+        } else {
             e = launch_batch((int)p->mulmod, p->kind, p->nontemporal, p->indexed, p->grid,
-                             p->block, stream, p->args);
+                             p->block, stream, q.args);
         }
     }
     if (e != hipSuccess) return fail(NN_EHIP, "batch launch: %s", hipGetErrorString(e));
-    e = hipEventRecord(p->done, stream);
+    e = hipEventRecord(q.done, stream);
     if (e != hipSuccess) return fail(NN_EHIP, "batch event: %s", hipGetErrorString(e));
-    p->pending = true;
+    q.pending = true;
+    p->next ^= 1;
     return NN_OK;
 }
 

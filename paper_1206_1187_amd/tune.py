@@ -130,7 +130,7 @@ def tune_batch(kind, reps=5, log=print, workload=None):
     dt = torch.float64 if kind == "f64" else torch.uint64
     out = torch.empty(total, dtype=dt, device="cuda")
     results = []
-    grids = sorted({max(1, cus * k // 8) for k in (4, 6, 8, 12, 16)})
+    grids = sorted({max(1, cus * k // 8) for k in (2, 3, 4, 5, 6, 8, 12, 16)})
     shapes = [dict(mulmod=m, block=b, cluster=k, temporal=t) for m in ("fp64", "shoup")
               for b in (256, 512) for k in (1, 4, 8, 16) for t in (False, True)]
     shapes += [dict(mulmod=m, block=256, cluster=8) for m in ("barrett", "montgomery")]

@@ -229,3 +229,23 @@ def test_batched_workload_full_size_sampled():
                                   tail.view(np.uint64)), i
     del out, flat
     torch.cuda.empty_cache()
+
+
+def test_slots_alternate_across_streams():
+    """Back-to-back batches of one plan on three different streams: the plan
+    alternates two staging slots, and a slot is reused only after the batch
+    that last used it has finished, whatever stream it ran on."""
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    bufs, cases = [], []
+    with nn.BatchPlan("f64", 64, 1 << 21) as plan:
+        for rep in range(7):
+            states, lengths, offsets, total = _mixed_batch(300 + rep, LENGTHS)
+            buf = _sentinel(total)
+            torch.cuda.synchronize()
+            s = streams[rep % 3]
+            plan.generate(states, lengths, offsets, buf.view(torch.float64), stream=s)
+            bufs.append(buf)
+            cases.append((states, lengths, offsets))
+        torch.cuda.synchronize()
+    for buf, (states, lengths, offsets) in zip(bufs, cases):
+        _check_batch(_bits(buf), states, lengths, offsets, "f64")
