@@ -330,7 +330,8 @@ def test_consecutive_layout_validation():
            nn.make_cfg(layout="consecutive", ilp=2),
            nn.make_cfg(layout="consecutive", occupancy=3),
            nn.make_cfg(layout="consecutive", block=1024, unroll=32),   # LDS
-           nn.make_cfg(layout="consecutive", grid=(1 << 25) // (256 * 16) + 1),
+           nn.make_cfg(layout="consecutive", block=256, unroll=16,
+                       grid=(1 << 25) // (256 * 16) + 1),                # skip tables
            nn.make_cfg(mulmod="modbarrett"),                           # rows
            nn.make_cfg(mulmod="modbarrett", layout="flat")]
     for cfg in bad:
