@@ -24,8 +24,11 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 METRIC = "uniform variates/sec at 1 GPU and % of HBM write BW; batched/served vs plain"
 # Profile summary holding the HBM byte counters of the dominant kernel.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_generate2_ilp_fp64_f64.plain_bulk.md")
+# Every source the dominant kernel is compiled from: its counters are void
+# once any of them changes.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1206_1187_amd", "csrc", f)
-                  for f in ("nn_kernels.hip", "nn_kernels.hpp", "nn_arith.hpp")]
+                  for f in ("nn_kernels.hip", "nn_kernels.hpp", "nn_arith.hpp", "nn_device.hpp")]
+KERNEL_SOURCES += [os.path.join(ROOT, "include", f) for f in ("nn.h", "nn_device.h")]
 
 
 def log(*a):
