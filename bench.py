@@ -28,7 +28,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_generate2_ilp_fp64_f64.plain
 # once any of them changes.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1206_1187_amd", "csrc", f)
                   for f in ("nn_kernels.hip", "nn_kernels.hpp", "nn_arith.hpp", "nn_device.hpp")]
-KERNEL_SOURCES += [os.path.join(ROOT, "include", f) for f in ("nn.h", "nn_device.h")]
+KERNEL_SOURCES += [os.path.join(ROOT, "include", "nn_device.h")]
 
 
 def log(*a):
