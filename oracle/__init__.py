@@ -51,6 +51,12 @@ def _load():
         "orc_g_step": (_u64, [_u64, ctypes.c_int, ctypes.c_int]),
         "orc_g_index_state": (_u64, [_u64, ctypes.c_int]),
         "orc_g_digit_sum": (_u64, [_u64, ctypes.c_int]),
+        "orc_e40_seed": (ctypes.c_int, [_u64, ctypes.POINTER(_u64)]),
+        "orc_e40_step": (_u64, [_u64]),
+        "orc_e40_skip": (_u64, [_u64, _u64]),
+        "orc_e40_to_f64": (ctypes.c_double, [_u64]),
+        "orc_e40_gen_u64": (_u64, [_u64, _u64, ctypes.c_void_p]),
+        "orc_e40_gen_f64": (_u64, [_u64, _u64, ctypes.c_void_p]),
         "orc_modbarrett_step": (_u64, [_u64]),
         "orc_gen_f64_modbarrett": (_u64, [_u64, _u64, ctypes.c_void_p]),
     }
@@ -153,4 +159,42 @@ def modbarrett_step(z):
 def gen_f64_modbarrett(z, n):
     out = np.empty(int(n), dtype=np.float64)
     zn = _load().orc_gen_f64_modbarrett(z, n, out.ctypes.data_as(ctypes.c_void_p))
+    return out, int(zn)
+
+
+# ------------------------------------------------------------ modulus 3^40 --
+#: 3^40, the larger modulus Section 2 names for a longer period.
+E40_MOD = 3 ** 40
+E40_INDEX_MIN = E40_MOD + 100
+E40_INDEX_MAX = 2 ** 64 - 1
+
+
+def e40_seed(index):
+    """Eq. 2 at modulus 3^40; ValueError outside [3^40+100, 2^64-1]."""
+    z = _u64(0)
+    if index < 0 or index >= 2 ** 64 or _load().orc_e40_seed(index, ctypes.byref(z)) != 0:
+        raise ValueError("seed index %r outside [3^40+100, 2^64-1]" % (index,))
+    return int(z.value)
+
+
+def e40_step(z):
+    return int(_load().orc_e40_step(z))
+
+
+def e40_skip(z, k):
+    return int(_load().orc_e40_skip(z, k))
+
+
+def e40_to_f64(z):
+    return float(_load().orc_e40_to_f64(z))
+
+
+def e40_gen(z, n, kind="u64"):
+    """Serial outputs z_1..z_n after z at modulus 3^40 (numpy) and z_n."""
+    if kind == "u64":
+        out = np.empty(n, dtype=np.uint64)
+        zn = _load().orc_e40_gen_u64(z, n, out.ctypes.data_as(ctypes.c_void_p))
+    else:
+        out = np.empty(n, dtype=np.float64)
+        zn = _load().orc_e40_gen_f64(z, n, out.ctypes.data_as(ctypes.c_void_p))
     return out, int(zn)

@@ -100,7 +100,8 @@ uint64_t orc_g_digit_sum(uint64_t n, int e)
         three_k *= 3; /* 3^k */
         uint64_t term = orc_powmod(2, n - three_k, three_k); /* 2^(n-3^k) mod 3^k */
         uint64_t scale = m / three_k;                        /* 3^(e-k) */
-        acc = (acc + orc_mulmod(term, scale, m)) % m;
+        /* the sum of two residues can pass 2^64 once m > 2^63 (e = 40) */
+        acc = (uint64_t)(((u128)acc + orc_mulmod(term, scale, m)) % m);
     }
     return acc;
 }
@@ -162,6 +163,51 @@ uint64_t orc_gen_par(uint64_t z, uint64_t n, void *out, int kind, int nthreads)
             orc_gen_f64(start, hi - lo, (double *)out + lo);
     }
     return orc_skip(z, n);
+}
+
+/* ------------------------------------------------------ modulus 3^40 -- */
+
+static const double ORC_E40_RECIP = 1.0 / 12157665459056928801.0; /* RN(1/3^40) */
+
+int orc_e40_seed(uint64_t a, uint64_t *z0)
+{
+    if (a < ORC_E40_INDEX_MIN)
+        return -1;
+    *z0 = orc_g_index_state(a, 40);
+    return 0;
+}
+
+uint64_t orc_e40_step(uint64_t z)
+{
+    return orc_mulmod(1ULL << 53, z, ORC_E40_MOD); /* 2^53 < 3^40 */
+}
+
+uint64_t orc_e40_skip(uint64_t z, uint64_t k)
+{
+    return orc_mulmod(z, orc_powmod(1ULL << 53, k, ORC_E40_MOD), ORC_E40_MOD);
+}
+
+double orc_e40_to_f64(uint64_t z)
+{
+    return (double)z * ORC_E40_RECIP;
+}
+
+uint64_t orc_e40_gen_u64(uint64_t z, uint64_t n, uint64_t *out)
+{
+    for (uint64_t k = 0; k < n; k++) {
+        z = orc_e40_step(z);
+        out[k] = z;
+    }
+    return z;
+}
+
+uint64_t orc_e40_gen_f64(uint64_t z, uint64_t n, double *out)
+{
+    for (uint64_t k = 0; k < n; k++) {
+        z = orc_e40_step(z);
+        out[k] = orc_e40_to_f64(z);
+    }
+    return z;
 }
 
 /* Modified Barrett (Section 3.1): with mu = floor(2^106 / m) and k = 53,

@@ -77,8 +77,8 @@ uint64_t orc_gen_par(uint64_t z, uint64_t n, void *out, int kind, int nthreads);
 /* Number of threads orc_gen_par would use for nthreads <= 0. */
 int orc_max_threads(void);
 
-/* Generic small analogue (Section 2, the LCG behind Eq. 1 at modulus 3^e):
- * modulus 3^e, multiplier 2^b mod 3^e, for 1 <= e <= 33. */
+/* Generic analogue (Section 2, the LCG behind Eq. 1 at modulus 3^e):
+ * modulus 3^e, multiplier 2^b mod 3^e, for 1 <= e <= 40. */
 uint64_t orc_g_modulus(int e);
 uint64_t orc_g_step(uint64_t z, int e, int b);
 /* 2^(n - 3^e) * floor(3^e / 2) mod 3^e (Eq. 1 numerator); n >= 3^e. */
@@ -86,6 +86,27 @@ uint64_t orc_g_index_state(uint64_t n, int e);
 /* sum_{k=1}^{e} 3^(e-k) * (2^(n-3^k) mod 3^k) mod 3^e: the definition of
  * alpha_{2,3} truncated after k = e, scaled by 3^e; n >= 3^e. */
 uint64_t orc_g_digit_sum(uint64_t n, int e);
+
+/* The larger modulus 3^40 that Section 2 names for a longer period: the same
+ * generator with m = 3^40 (period 2*3^39), multiplier 2^53 (53 bits per
+ * step, as Eq. 3), seeded by Eq. 2 with 3^40 in place of 3^33.  Readings:
+ * starting indices a in [3^40 + 100, 2^64 - 1] (Algorithm BB's lower bound
+ * carried over, the upper bound is the 64-bit index type); variates
+ * RN(RN(z) * RN(1/3^40)), where RN(z) rounds the 64-bit state to binary64. */
+#define ORC_E40_MOD 12157665459056928801ULL /* 3^40 */
+#define ORC_E40_INDEX_MIN (ORC_E40_MOD + 100ULL)
+#define ORC_E40_INDEX_MAX 18446744073709551615ULL /* 2^64 - 1 */
+/* Eq. 2 at modulus 3^40; 0 and *z0 written for a in range, -1 otherwise. */
+int orc_e40_seed(uint64_t a, uint64_t *z0);
+/* One step z -> 2^53 z mod 3^40. */
+uint64_t orc_e40_step(uint64_t z);
+/* z * (2^53)^k mod 3^40, k used as given. */
+uint64_t orc_e40_skip(uint64_t z, uint64_t k);
+/* RN(RN(z) * RN(1/3^40)). */
+double orc_e40_to_f64(uint64_t z);
+/* Serial generation at modulus 3^40, step-then-emit; returns z_n. */
+uint64_t orc_e40_gen_u64(uint64_t z, uint64_t n, uint64_t *out);
+uint64_t orc_e40_gen_f64(uint64_t z, uint64_t n, double *out);
 
 /* Modified Barrett step of Section 3.1 (the paper's fastest serial method),
  * valid for 0 < z < 3^33: 2^53 * z mod 3^33 without a division.  Kept only
