@@ -360,6 +360,11 @@ def main():
                 lambda: nn.generate_into(nn.seed(case.index), out, cfg=cfg), 10, torch)
             shoot["modbarrett_consecutive_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
         extras["mulmod_shootout_default_shape"] = shoot
+        # Section 2's larger modulus 3^40 (64-bit states, Montgomery step).
+        for kind, out in (("f64", out_f), ("u64", out_u)):
+            s = _timed_kernel(
+                lambda: nn.e40_generate_into(nn.e40_seed(nn.E40_INDEX_MIN), out), 10, torch)
+            extras["modulus_3e40_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
         result["extras"] = extras
         log("extras", json.dumps(extras))
 

@@ -395,6 +395,38 @@ const char *nn_last_error(void);
 /* Library version string. */
 const char *nn_version(void);
 
+/* ------------------------------------------------------ modulus 3^40 -- */
+/* The larger modulus Section 2 names for a longer period: the same
+ * generator with m = 3^40 (period 2*3^39), the multiplier 2^53 of Eq. 3
+ * (53 bits of alpha_{2,3} per step, now at positions 3^40 and above) and
+ * Eq. 2 with 3^40 in place of 3^33.  A state is a unit modulo 3^40 (all 64
+ * bits are used).  F64 outputs are RN(RN(z) * RN(1/3^40)), RN(z) being the
+ * rounding of the 64-bit state to binary64; they lie in (0,1).  Same output
+ * convention as above (step-then-emit, *state left at the last output). */
+#define NN_E40_MODULUS 12157665459056928801ULL   /* 3^40 */
+#define NN_E40_PERIOD 8105110306037952534ULL     /* 2 * 3^39 */
+#define NN_E40_INDEX_MIN 12157665459056928901ULL /* 3^40 + 100 */
+#define NN_E40_INDEX_MAX 18446744073709551615ULL /* 2^64 - 1 (the index type) */
+
+/* Eq. 2 at modulus 3^40: the state of starting index `index` in
+ * [NN_E40_INDEX_MIN, NN_E40_INDEX_MAX]; NN_EINVAL otherwise.  Host, pure. */
+int nn_e40_seed(uint64_t index, uint64_t *state_out);
+
+/* The state k steps after `state` at modulus 3^40 (k reduced modulo the
+ * period).  NN_EINVAL for a non-unit state or NULL state_out.  Host, pure. */
+int nn_e40_skip(uint64_t state, uint64_t k, uint64_t *state_out);
+
+/* nn_generate at modulus 3^40: writes z_1..z_count after *state to out_dev
+ * (device memory, 8-byte aligned, count*8 bytes, owned by the caller) as
+ * uint64 or binary64 and sets *state to z_count; asynchronous on `stream`.
+ * cfg (NULL for the defaults) may set block, grid, unroll (1, 2, 4), ilp
+ * (1, 2, 4) and NN_CFG_TEMPORAL_STORES (defaults: 256 threads, 2 workgroups
+ * per CU, ilp 2, unroll 1); the reduction is Montgomery's (R = 2^64), the
+ * layout the row layout with 16-byte stores.  Errors as nn_generate_ex. */
+int nn_e40_generate_ex(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream,
+                       const nn_launch_cfg *cfg);
+int nn_e40_generate(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream);
+
 /* ---------------------------------------------------------- diagnostic -- */
 
 /* nn_debug_mulmod -- runs the host build of a step-loop modular
@@ -403,6 +435,10 @@ const char *nn_version(void);
  * multiplier.  Every a[i] and b[i] must be a valid state;
  * NN_MULMOD_MODBARRETT multiplies by 2^53 itself and needs every b[i] to be
  * 2^53 mod 3^33.  For testing the arithmetic on a CPU; host pointers. */
+/* nn_e40_debug_mulmod -- the host build of the 3^40 step's reduction:
+ * out[i] = a[i] * b[i] mod 3^40 for units a[i], b[i]; host pointers. */
+int nn_e40_debug_mulmod(const uint64_t *a, const uint64_t *b, uint64_t n, uint64_t *out);
+
 int nn_debug_mulmod(int mulmod, const uint64_t *a, const uint64_t *b, uint64_t n,
                     uint64_t *out);
 

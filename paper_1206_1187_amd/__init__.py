@@ -154,6 +154,52 @@ def consume(state, count, kind="u64", result=None, stream=None, cfg=None):
     return result, int(st.value)
 
 
+E40_MODULUS = 3 ** 40
+E40_INDEX_MIN = E40_MODULUS + 100
+E40_INDEX_MAX = 2 ** 64 - 1
+
+
+def e40_seed(index):
+    """Eq. 2 at modulus 3^40 (include/nn.h, nn_e40_seed)."""
+    z = ctypes.c_uint64()
+    _native.check(_native.lib().nn_e40_seed(int(index), ctypes.byref(z)))
+    return z.value
+
+
+def e40_skip(state, k):
+    z = ctypes.c_uint64()
+    _native.check(_native.lib().nn_e40_skip(int(state), int(k) % (1 << 64), ctypes.byref(z)))
+    return z.value
+
+
+def e40_generate_into(state, out, stream=None, cfg=None):
+    """The modulus-3^40 generator into the contiguous cuda tensor ``out``
+    (uint64 or float64); returns the new state."""
+    kind = _kind(out.dtype)
+    if not out.is_cuda or not out.is_contiguous():
+        raise NNError(_native.NN_EINVAL, "out must be a contiguous cuda tensor")
+    st = ctypes.c_uint64(int(state))
+    import torch
+    with torch.cuda.device(out.device):
+        rc = _native.lib().nn_e40_generate_ex(
+            ctypes.byref(st), out.numel(), ctypes.c_void_p(out.data_ptr()), kind,
+            _stream_handle(stream), ctypes.byref(cfg) if cfg is not None else None)
+    _native.check(rc)
+    return st.value
+
+
+def e40_debug_mulmod(a, b):
+    """Host build of the 3^40 reduction: a[i]*b[i] mod 3^40 (numpy uint64)."""
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    out = np.empty_like(a)
+    p = ctypes.POINTER(ctypes.c_uint64)
+    _native.check(_native.lib().nn_e40_debug_mulmod(a.ctypes.data_as(p), b.ctypes.data_as(p),
+                                                    a.size, out.ctypes.data_as(p)))
+    return out
+
+
 def dev_mult_pow(k):
     """(2^53)^k mod 3^33 in the device-side form (include/nn_device.h):
     (v, qh, ql) with qh + ql = v / 3^33 as a double-double."""

@@ -146,6 +146,11 @@ SIGNATURES = {
     "nn_fill": (_int, [_u64, _vp, _u64, _vp, ctypes.POINTER(LaunchCfg)]),
     "nn_consume": (_int, [_pu64, _u64, _int, _vp, _vp, ctypes.POINTER(LaunchCfg)]),
     "nn_dev_mult_pow": (_int, [_u64, ctypes.POINTER(DevMult)]),
+    "nn_e40_seed": (_int, [_u64, _pu64]),
+    "nn_e40_skip": (_int, [_u64, _u64, _pu64]),
+    "nn_e40_generate": (_int, [_pu64, _u64, _vp, _int, _vp]),
+    "nn_e40_generate_ex": (_int, [_pu64, _u64, _vp, _int, _vp, ctypes.POINTER(LaunchCfg)]),
+    "nn_e40_debug_mulmod": (_int, [_pu64, _pu64, _u64, _pu64]),
     "nn_dev_skip_table": (_int, [ctypes.POINTER(ctypes.c_void_p)]),
     "nn_strerror": (ctypes.c_char_p, [_int]),
     "nn_last_error": (ctypes.c_char_p, []),

@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["nn_capi.hip", "nn_runtime.hip", "nn_server.hip", "nn_kernels.hip", "nn_batch.hip"]
+SOURCES = ["nn_capi.hip", "nn_runtime.hip", "nn_server.hip", "nn_kernels.hip", "nn_batch.hip",
+           "nn_e40.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950",

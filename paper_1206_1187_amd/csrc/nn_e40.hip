@@ -1,0 +1,350 @@
+// nn_e40.hip -- the modulus-3^40 generator (Section 2's longer-period
+// variant): host arithmetic, device tables, the row-layout kernel and the
+// extern "C" entry points nn_e40_* of include/nn.h.
+//
+// Layout as the 3^33 row kernel: T = grid*block threads, two consecutive
+// outputs per lane and row (one 16-byte store), row i covering elements
+// [2 T i, 2 T (i+1)), IL rows in flight per thread, each chain advanced by
+// (2^53)^(2 T IL) per trip.  A thread starts at element 2t by two table
+// multiplications.  An output that is only 8-byte aligned gets its first
+// element from lane 0 of workgroup 0 with an 8-byte store, the rest from
+// the aligned row loop.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "nn.h"
+#include "nn_device.hpp"
+#include "nn_e40.hpp"
+#include "nn_internal.hpp"
+
+namespace nn {
+namespace e40 {
+namespace {
+
+// ------------------------------------------------------------------ host --
+inline uint64_t h_mul(uint64_t a, uint64_t b) { return (uint64_t)(((u128)a * b) % kMod); }
+
+inline uint64_t h_pow(uint64_t base, uint64_t e) {
+    uint64_t r = 1, b = base % kMod;
+    while (e) {
+        if (e & 1) r = h_mul(r, b);
+        b = h_mul(b, b);
+        e >>= 1;
+    }
+    return r;
+}
+
+inline bool valid_state(uint64_t s) { return s != 0 && s < kMod && s % 3 != 0; }
+
+// (2^53)^k mod 3^40 through byte tables; k is reduced by the period first
+// (2^53 has order exactly 2*3^39: 53 is prime to it).
+class Powers {
+  public:
+    static const Powers& get() {
+        static Powers p;
+        return p;
+    }
+    uint64_t pow(uint64_t k) const {
+        k %= kPeriod;
+        uint64_t r = 1;
+        for (int i = 0; k != 0; ++i, k >>= 8) {
+            const uint32_t j = (uint32_t)(k & 0xff);
+            if (j) r = h_mul(r, tab_[i][j]);
+        }
+        return r;
+    }
+
+  private:
+    Powers() {
+        uint64_t step = kMult;
+        for (int i = 0; i < 8; ++i) {
+            tab_[i][0] = 1;
+            for (int j = 1; j < 256; ++j) tab_[i][j] = h_mul(tab_[i][j - 1], step);
+            step = h_mul(tab_[i][255], step);
+        }
+    }
+    uint64_t tab_[8][256];
+};
+
+inline Mult40 make_mult40(uint64_t v) {
+    Mult40 f;
+    f.v = v;
+    f.mont = (uint64_t)(((u128)v << 64) % kMod);
+    return f;
+}
+
+constexpr uint32_t kLo = 1024;      // t_lo[l] = (2^53)^l
+constexpr uint32_t kHi = 1u << 15;  // t_hi[j] = (2^53)^(1024 j)
+constexpr uint64_t kMaxThreads = (uint64_t)kLo * kHi / 2;
+constexpr int kMaxDev = 64;
+
+std::mutex g_mu;
+Mult40* g_tab[kMaxDev];  // kLo + kHi entries per device
+
+int device_tables(const Mult40** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(NN_ENODEV, "hipGetDevice: %s", hipGetErrorString(e));
+    DeviceTables* d = nullptr;  // checks the architecture
+    const int st = current_device(&d);
+    if (st) return st;
+    if (dev < 0 || dev >= kMaxDev) return fail(NN_ENODEV, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_tab[dev]) {
+        static std::vector<Mult40> host = [] {
+            std::vector<Mult40> t(kLo + kHi);
+            uint64_t r = 1;
+            for (uint32_t l = 0; l < kLo; ++l, r = h_mul(r, kMult)) t[l] = make_mult40(r);
+            const uint64_t step = Powers::get().pow(kLo);
+            r = 1;
+            for (uint32_t j = 0; j < kHi; ++j, r = h_mul(r, step)) t[kLo + j] = make_mult40(r);
+            return t;
+        }();
+        void* mem = nullptr;
+        e = hipMalloc(&mem, host.size() * sizeof(Mult40));
+        if (e != hipSuccess) return fail(NN_ENOMEM, "hipMalloc e40 tables: %s", hipGetErrorString(e));
+        e = hipMemcpy(mem, host.data(), host.size() * sizeof(Mult40), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(mem);
+            return fail(NN_EHIP, "e40 table upload: %s", hipGetErrorString(e));
+        }
+        g_tab[dev] = (Mult40*)mem;
+    }
+    *out = g_tab[dev];
+    return NN_OK;
+}
+
+// ---------------------------------------------------------------- device --
+struct E40Args {
+    uint64_t* out;  // 16-byte aligned: the row loop's first element
+    uint64_t T;
+    uint64_t e_full;
+    uint32_t rem;
+    uint64_t base;  // state of out[0]
+    Mult40 J;       // (2^53)^(2T)
+    Mult40 M1;      // 2^53
+    Mult40 JI;      // J^IL
+    const Mult40* t_lo;
+    const Mult40* t_hi;
+    uint64_t* head;       // 8-byte aligned output's first element, or null
+    uint64_t head_state;  // its state
+};
+
+template <int KIND>
+__device__ __forceinline__ uint64_t bits40(uint64_t z) {
+    if constexpr (KIND == 0)
+        return z;
+    else
+        return (uint64_t)__double_as_longlong(to_f64(z));
+}
+
+template <int KIND, int IL, int UNROLL, bool NT>
+__global__ __launch_bounds__(1024) void k_e40(E40Args a) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0 && a.head) put<NT>(as_global(a.head), bits40<KIND>(a.head_state));
+    const uint32_t rem_pairs = a.rem >> 1;
+    const bool extra_pair = t < rem_pairs;
+    const bool extra_one = (a.rem & 1u) && t == rem_pairs;
+    if (a.e_full == 0 && !extra_pair && !extra_one) return;
+    const uint64_t k = 2ull * t;  // < 2^25
+    uint64_t za[IL], zb[IL];
+    za[0] = mm40(mm40(a.base, a.t_hi[k >> 10].mont), a.t_lo[k & (kLo - 1)].mont);
+    zb[0] = mm40(za[0], a.M1.mont);
+#pragma unroll
+    for (int r = 1; r < IL; ++r) {
+        za[r] = mm40(za[r - 1], a.J.mont);
+        zb[r] = mm40(zb[r - 1], a.J.mont);
+    }
+    const global_ptr<u64x2> out = reinterpret_cast<global_ptr<u64x2>>(as_global(a.out));
+    global_ptr<u64x2> row = out;
+    const uint64_t T = a.T;
+    uint64_t i = 0;
+#pragma unroll UNROLL
+    for (; i + IL <= a.e_full; i += IL) {
+#pragma unroll
+        for (int r = 0; r < IL; ++r) {
+            u64x2 v;
+            v.x = bits40<KIND>(za[r]);
+            v.y = bits40<KIND>(zb[r]);
+            put<NT>(row + r * T + t, v);
+        }
+        row += IL * T;
+#pragma unroll
+        for (int r = 0; r < IL; ++r) {
+            za[r] = mm40(za[r], a.JI.mont);
+            zb[r] = mm40(zb[r], a.JI.mont);
+        }
+    }
+    const uint32_t left = (uint32_t)(a.e_full - i);
+    uint64_t pa = za[0], pb = zb[0];
+#pragma unroll
+    for (int r = 0; r < IL; ++r) {
+        if ((uint32_t)r < left) {
+            u64x2 v;
+            v.x = bits40<KIND>(za[r]);
+            v.y = bits40<KIND>(zb[r]);
+            put<NT>(row + r * T + t, v);
+        }
+        if ((uint32_t)r == left) {
+            pa = za[r];
+            pb = zb[r];
+        }
+    }
+    row += left * T;
+    if (extra_pair) {
+        u64x2 v;
+        v.x = bits40<KIND>(pa);
+        v.y = bits40<KIND>(pb);
+        put<NT>(row + t, v);
+    } else if (extra_one) {
+        put<NT>(reinterpret_cast<global_ptr<uint64_t>>(row + t), bits40<KIND>(pa));
+    }
+}
+
+template <int KIND, int IL, int U, bool NT>
+hipError_t launch_one(uint32_t grid, uint32_t block, hipStream_t s, const E40Args& a) {
+    k_e40<KIND, IL, U, NT><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int KIND, int IL, bool NT>
+hipError_t launch_u(int unroll, uint32_t grid, uint32_t block, hipStream_t s, const E40Args& a) {
+    switch (unroll) {
+        case 1: return launch_one<KIND, IL, 1, NT>(grid, block, s, a);
+        case 2: return launch_one<KIND, IL, 2, NT>(grid, block, s, a);
+        case 4: return launch_one<KIND, IL, 4, NT>(grid, block, s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int KIND, bool NT>
+hipError_t launch_il(int ilp, int unroll, uint32_t grid, uint32_t block, hipStream_t s,
+                     const E40Args& a) {
+    switch (ilp) {
+        case 1: return launch_u<KIND, 1, NT>(unroll, grid, block, s, a);
+        case 2: return launch_u<KIND, 2, NT>(unroll, grid, block, s, a);
+        case 4: return launch_u<KIND, 4, NT>(unroll, grid, block, s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch(int kind, int ilp, int unroll, bool nt, uint32_t grid, uint32_t block,
+                  hipStream_t s, const E40Args& a) {
+    if (kind == 0)
+        return nt ? launch_il<0, true>(ilp, unroll, grid, block, s, a)
+                  : launch_il<0, false>(ilp, unroll, grid, block, s, a);
+    return nt ? launch_il<1, true>(ilp, unroll, grid, block, s, a)
+              : launch_il<1, false>(ilp, unroll, grid, block, s, a);
+}
+
+}  // namespace
+}  // namespace e40
+}  // namespace nn
+
+using namespace nn;
+
+extern "C" {
+
+int nn_e40_seed(uint64_t index, uint64_t* state_out) {
+    if (!state_out) return fail(NN_EINVAL, "state_out is NULL");
+    if (index < e40::kIndexMin)
+        return fail(NN_EINVAL, "index %llu below 3^40+100", (unsigned long long)index);
+    *state_out = e40::h_mul(e40::h_pow(2, index - e40::kMod), e40::kHalf);
+    return ok();
+}
+
+int nn_e40_skip(uint64_t state, uint64_t k, uint64_t* state_out) {
+    if (!state_out) return fail(NN_EINVAL, "state_out is NULL");
+    if (!e40::valid_state(state))
+        return fail(NN_EINVAL, "state %llu is not a unit modulo 3^40", (unsigned long long)state);
+    *state_out = e40::h_mul(state, e40::Powers::get().pow(k));
+    return ok();
+}
+
+int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, void* stream,
+                       const nn_launch_cfg* cfg) {
+    if (!state) return fail(NN_EINVAL, "state is NULL");
+    if (kind != NN_OUT_U64 && kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %d unknown", kind);
+    const uint64_t s = *state;
+    if (!e40::valid_state(s))
+        return fail(NN_EINVAL, "state %llu is not a unit modulo 3^40", (unsigned long long)s);
+    if (count == 0) return ok();
+    if (count > UINT64_MAX / 8) return fail(NN_ERANGE, "count*8 overflows");
+    if (!out_dev) return fail(NN_EINVAL, "output pointer is NULL");
+    if ((uintptr_t)out_dev % 8) return fail(NN_EINVAL, "output pointer %p is not 8-byte aligned", out_dev);
+    if ((uintptr_t)out_dev > UINTPTR_MAX - count * 8)
+        return fail(NN_ERANGE, "output range wraps the address space");
+    nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (cfg) c = *cfg;
+    if ((c.flags & ~(uint32_t)(NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS)) || c.occupancy ||
+        (c.width && c.width != 2) || (c.mulmod && c.mulmod != NN_MULMOD_MONTGOMERY))
+        return fail(NN_EINVAL, "the 3^40 generator takes block, grid, unroll, ilp and "
+                               "NN_CFG_TEMPORAL_STORES (rows, 16-byte stores, Montgomery)");
+    const uint32_t block = c.block ? c.block : 256u;
+    if (block < 64 || block > 1024 || block % 64)
+        return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
+    // Defaults from a sweep on MI355X (2^30 f64 outputs): 256 threads, two
+    // workgroups per CU, two rows in flight, no unrolling (4.8 TB/s; the
+    // Montgomery step makes this kernel compute-bound, unlike the 3^33 one).
+    const uint32_t unroll = c.unroll ? c.unroll : 1u;
+    if (unroll != 1 && unroll != 2 && unroll != 4)
+        return fail(NN_EINVAL, "unroll %u: must be 1, 2 or 4", unroll);
+    const uint32_t ilp = c.ilp ? c.ilp : 2u;
+    if (ilp != 1 && ilp != 2 && ilp != 4) return fail(NN_EINVAL, "ilp %u: must be 1, 2 or 4", ilp);
+    const e40::Mult40* tab = nullptr;
+    int st = e40::device_tables(&tab);
+    if (st) return st;
+    DeviceTables* d = nullptr;
+    st = current_device(&d);
+    if (st) return st;
+    // An 8-byte aligned output: its first element separately, then rows.
+    const uint64_t head = ((uintptr_t)out_dev % 16) ? 1 : 0;
+    const uint64_t n = count - head;
+    uint32_t grid = c.grid;
+    if (!grid) {
+        const uint64_t need = (n + 2ull * block - 1) / (2ull * block);
+        const uint64_t cap = (uint64_t)(d->cus > 0 ? d->cus : 1) * 2;
+        grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
+    }
+    if ((uint64_t)grid * block > e40::kMaxThreads)
+        return fail(NN_EINVAL, "grid*block exceeds %llu threads",
+                    (unsigned long long)e40::kMaxThreads);
+    e40::E40Args a;
+    a.T = (uint64_t)grid * block;
+    const uint64_t row = 2 * a.T;
+    a.e_full = n / row;
+    a.rem = (uint32_t)(n % row);
+    a.head = head ? (uint64_t*)out_dev : nullptr;
+    a.head_state = e40::h_mul(s, e40::kMult);  // element 0: z_1
+    a.out = (uint64_t*)out_dev + head;
+    a.base = head ? e40::h_mul(a.head_state, e40::kMult) : a.head_state;
+    a.J = e40::make_mult40(e40::Powers::get().pow(row));
+    a.M1 = e40::make_mult40(e40::kMult);
+    a.JI = e40::make_mult40(e40::Powers::get().pow(row * ilp));
+    a.t_lo = tab;
+    a.t_hi = tab + e40::kLo;
+    hipError_t e = e40::launch(kind, (int)ilp, (int)unroll, !(c.flags & NN_CFG_TEMPORAL_STORES),
+                               grid, block, (hipStream_t)stream, a);
+    if (e != hipSuccess) return fail(NN_EHIP, "e40 launch: %s", hipGetErrorString(e));
+    *state = e40::h_mul(s, e40::Powers::get().pow(count));
+    return ok();
+}
+
+int nn_e40_generate(uint64_t* state, uint64_t count, void* out_dev, int kind, void* stream) {
+    return nn_e40_generate_ex(state, count, out_dev, kind, stream, nullptr);
+}
+
+int nn_e40_debug_mulmod(const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t* out) {
+    if (n && (!a || !b || !out)) return fail(NN_EINVAL, "NULL array");
+    for (uint64_t i = 0; i < n; ++i)
+        if (!e40::valid_state(a[i]) || !e40::valid_state(b[i]))
+            return fail(NN_EINVAL, "pair %llu is not a pair of units modulo 3^40",
+                        (unsigned long long)i);
+    for (uint64_t i = 0; i < n; ++i) out[i] = e40::mm40(a[i], e40::make_mult40(b[i]).mont);
+    return ok();
+}
+
+}  // extern "C"

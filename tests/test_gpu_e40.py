@@ -1,0 +1,107 @@
+"""GPU parity of the modulus-3^40 generator (nn_e40_generate_ex) against the
+oracle: bit-exact raw states and variates, ragged tails, 8- and 16-byte
+aligned outputs, several launch shapes, chained calls, extreme states."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1206_1187_amd as nn  # noqa: E402
+
+M = 3 ** 40
+SENTINEL = 0xDEADBEEFCAFEF00D
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _bits(t):
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)
+
+
+def _gen_guarded(state, count, kind, cfg=None, guard=512):
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    host = np.full(count + 2 * guard, SENTINEL, dtype=np.uint64)
+    buf = torch.from_numpy(host.view(np.int64)).cuda()
+    new_state = nn.e40_generate_into(state, buf[guard:guard + count].view(dt), cfg=cfg)
+    torch.cuda.synchronize()
+    got = _bits(buf)
+    assert (got[:guard] == SENTINEL).all(), "write before the output"
+    assert (got[guard + count:] == SENTINEL).all(), "write past the output"
+    return got[guard:guard + count], new_state
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available()
+    nn.init(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def test_e40_bit_exact_shapes_and_tails():
+    z0 = orc.e40_seed(orc.E40_INDEX_MIN + 12345)
+    ref_u, _ = orc.e40_gen(z0, 300_000, "u64")
+    ref_f, _ = orc.e40_gen(z0, 300_000, "f64")
+    shapes = [dict(), dict(block=64, grid=3, ilp=1, unroll=1), dict(block=1024, grid=7, ilp=4, unroll=4),
+              dict(block=512, grid=129, ilp=2, unroll=2), dict(block=256, grid=1, ilp=4, unroll=1)]
+    for kw in shapes:
+        cfg = nn.make_cfg(**kw)
+        for count in (1, 2, 3, 511, 512, 513, 4097, 99_991, 300_000):
+            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                for guard in (512, 513):
+                    _say("e40", kw, count, kind, guard)
+                    got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=guard)
+                    assert np.array_equal(got, ref.view(np.uint64)[:count]), (kw, count, kind, guard)
+                    assert zn == orc.e40_skip(z0, count)
+    got, _ = _gen_guarded(z0, 99_991, "f64", cfg=nn.make_cfg(temporal=True))
+    assert np.array_equal(got, ref_f.view(np.uint64)[:99_991])
+
+
+def test_e40_chained_and_extreme_states():
+    for s in (1, 2, M - 1, M - 2, 2 ** 63 + 1, orc.e40_seed(orc.E40_INDEX_MAX)):
+        if s % 3 == 0:
+            continue
+        ref, zr = orc.e40_gen(s, 70_001, "u64")
+        out = torch.empty(70_001, dtype=torch.uint64, device="cuda")
+        z = s
+        for lo, hi in ((0, 1), (1, 1000), (1000, 1001), (1001, 70_001)):
+            z = nn.e40_generate_into(z, out[lo:hi])
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(out), ref), s
+        assert z == zr
+
+
+def test_e40_large_sampled():
+    """2^26 outputs in the default shape; windows of the output compared
+    with the oracle started there by skip-ahead."""
+    n = 1 << 26
+    z0 = orc.e40_seed(orc.E40_INDEX_MIN + 987654321)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    zn = nn.e40_generate_into(z0, out)
+    torch.cuda.synchronize()
+    assert zn == orc.e40_skip(z0, n)
+    flat = out.view(torch.int64)
+    rng = np.random.default_rng(40)
+    starts = [0, n - 4096] + rng.integers(0, n - 4096, 30).tolist()
+    for st in starts:
+        ref, _ = orc.e40_gen(orc.e40_skip(z0, int(st)), 4096, "f64")
+        got = flat[st:st + 4096].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref.view(np.uint64)), st
+    del out, flat
+
+
+def test_e40_config_validation():
+    z0 = orc.e40_seed(orc.E40_INDEX_MIN)
+    out = torch.empty(4096, dtype=torch.float64, device="cuda")
+    for cfg in [nn.make_cfg(layout="flat"), nn.make_cfg(width=1), nn.make_cfg(mulmod="fp64"),
+                nn.make_cfg(unroll=8), nn.make_cfg(ilp=3), nn.make_cfg(block=100),
+                nn.make_cfg(occupancy=3), nn.make_cfg(grid=1 << 20, block=1024)]:
+        with pytest.raises(nn.NNError):
+            nn.e40_generate_into(z0, out, cfg=cfg)
