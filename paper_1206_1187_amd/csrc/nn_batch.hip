@@ -84,9 +84,7 @@ __device__ __forceinline__ u64x2 pair_bits(typename V::S za, typename V::S zb) {
 // over full rows with two rows (four chains) in flight, and the window's
 // partial last row.
 template <class V, int KIND, bool NT, bool INDEXED>
-__global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
-    // The workspace is written before the launch: scalar loads.
-    const const_ptr<BatchHeader> hdr = as_const(a.ws);
+__device__ __forceinline__ void batch_body(const BatchArgs& a, const const_ptr<BatchHeader> hdr) {
     const uint32_t n_desc = hdr->n_desc;
     const uint64_t n_rows = hdr->n_rows;
     const global_ptr<uint64_t> out = as_global(hdr->out);
@@ -173,6 +171,20 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
         }
         r = D.row_start + j;
     }
+}
+
+// The batch read from the device workspace, written before the launch:
+// scalar loads.
+template <class V, int KIND, bool NT, bool INDEXED>
+__global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
+    batch_body<V, KIND, NT, INDEXED>(a, as_const(a.ws));
+}
+
+// A small batch carried in the kernel arguments: no upload before the
+// launch, so its latency is that of a plain launch.
+template <class V, int KIND, bool NT, bool INDEXED>
+__global__ __launch_bounds__(1024) void k_batch_inline(BatchArgs a, BatchInline in) {
+    batch_body<V, KIND, NT, INDEXED>(a, as_const(&in.hdr));
 }
 
 // Pre-pass of the interleaved kernel: the window of every batch row.
@@ -283,6 +295,35 @@ const void* batch_kernel(int mulmod, int kind, bool nt, bool indexed) {
         case 4: return kernel_v<VarMontgomery>(kind, nt, indexed);
         default: return nullptr;
     }
+}
+
+template <class V, int KIND, bool NT>
+static const void* inline_kvn(bool indexed) {
+    return indexed ? reinterpret_cast<const void*>(&k_batch_inline<V, KIND, NT, true>)
+                   : reinterpret_cast<const void*>(&k_batch_inline<V, KIND, NT, false>);
+}
+
+template <class V>
+static const void* inline_v(int kind, bool nt, bool indexed) {
+    if (kind == 0) return nt ? inline_kvn<V, 0, true>(indexed) : inline_kvn<V, 0, false>(indexed);
+    return nt ? inline_kvn<V, 1, true>(indexed) : inline_kvn<V, 1, false>(indexed);
+}
+
+hipError_t launch_batch_inline(int mulmod, int kind, bool nt, bool indexed, uint32_t grid,
+                               uint32_t block, hipStream_t s, const BatchArgs& a,
+                               const BatchInline& in) {
+    const void* k = nullptr;
+    switch (mulmod) {
+        case 1: k = inline_v<VarFP64>(kind, nt, indexed); break;
+        case 2: k = inline_v<VarBarrett>(kind, nt, indexed); break;
+        case 3: k = inline_v<VarShoup>(kind, nt, indexed); break;
+        case 4: k = inline_v<VarMontgomery>(kind, nt, indexed); break;
+        default: return hipErrorInvalidValue;
+    }
+    BatchArgs ca = a;
+    BatchInline ci = in;
+    void* params[] = {&ca, &ci};
+    return hipLaunchKernel(k, dim3(grid), dim3(block), params, 0, s);
 }
 
 hipError_t launch_batch(int mulmod, int kind, bool nt, bool indexed, uint32_t grid,

@@ -85,4 +85,19 @@ const void* batch_kernel(int mulmod, int kind, bool nontemporal, bool indexed);
 hipError_t launch_batch(int mulmod, int kind, bool nontemporal, bool indexed, uint32_t grid,
                         uint32_t block, hipStream_t stream, const BatchArgs& a);
 
+// A batch of at most kInlineDescs windows passed by value in the kernel
+// arguments (the header, then the descriptors, laid out as in the
+// workspace), launched without an upload.
+constexpr uint32_t kInlineDescs = 16;
+struct BatchInline {
+    BatchHeader hdr;
+    BatchDesc desc[kInlineDescs];
+};
+static_assert(sizeof(BatchInline) == sizeof(BatchHeader) + kInlineDescs * sizeof(BatchDesc),
+              "descriptors follow the header as in the workspace");
+
+hipError_t launch_batch_inline(int mulmod, int kind, bool nontemporal, bool indexed,
+                               uint32_t grid, uint32_t block, hipStream_t stream,
+                               const BatchArgs& a, const BatchInline& in);
+
 }  // namespace nn

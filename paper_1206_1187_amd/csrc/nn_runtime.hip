@@ -370,7 +370,22 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     hdr->n_desc = nd;
     hdr->n_rows = rows;
     const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc);
-    hipError_t e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, stream);
+    hipError_t e;
+    if (nd <= kInlineDescs && !p->interleaved) {
+        // A small batch travels in the kernel arguments: no upload to wait for.
+        BatchInline in;
+        memset(&in, 0, sizeof in);
+        memcpy(&in, q.ws_host, bytes);
+        e = launch_batch_inline((int)p->mulmod, p->kind, p->nontemporal, p->indexed, p->grid,
+                                p->block, stream, q.args, in);
+        if (e != hipSuccess) return fail(NN_EHIP, "batch launch: %s", hipGetErrorString(e));
+        e = hipEventRecord(q.done, stream);
+        if (e != hipSuccess) return fail(NN_EHIP, "batch event: %s", hipGetErrorString(e));
+        q.pending = true;
+        p->next ^= 1;
+        return NN_OK;
+    }
+    e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && p->use_graph) {
         e = hipGraphLaunch(q.exec, stream);
     } else if (e == hipSuccess) {

@@ -249,3 +249,35 @@ def test_slots_alternate_across_streams():
         torch.cuda.synchronize()
     for buf, (states, lengths, offsets) in zip(bufs, cases):
         _check_batch(_bits(buf), states, lengths, offsets, "f64")
+
+
+@pytest.mark.parametrize("kind", ["u64", "f64"])
+@pytest.mark.parametrize("mulmod", ["fp64", "shoup", "barrett", "montgomery"])
+def test_small_batches_in_kernel_arguments(kind, mulmod):
+    """Batches of up to 16 windows travel in the kernel arguments (no
+    upload); 1, 2, 15, 16 and 17 windows (17 takes the workspace path), odd
+    offsets, ragged lengths, one window long enough to be split in pieces."""
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    lengths_all = [1, 511, 512, 513, 70_001, 3, 1024, 8193, 2, 65, 100_003, 17, 4096, 9, 300, 1025,
+                   33]
+    with nn.BatchPlan(kind, 32, 1 << 26, mulmod=mulmod, block=128, grid=9) as plan:
+        for nwin in (1, 2, 15, 16, 17):
+            states, lengths, offsets, total = _mixed_batch(400 + nwin, lengths_all[:nwin])
+            _say("inline", kind, mulmod, nwin)
+            buf = _sentinel(total)
+            fin = plan.generate(states, lengths, offsets, buf.view(dt), final_states=True)
+            torch.cuda.synchronize()
+            _check_batch(_bits(buf), states, lengths, offsets, kind)
+            for s, n, f in zip(states.tolist(), lengths.tolist(), fin.tolist()):
+                assert f == orc.skip(s, n)
+        # one stream of 2^25 + 5 outputs: three pieces, still inline
+        s0 = orc.seed(wl.INDEX_MIN + 77)
+        n = (1 << 25) + 5
+        buf = _sentinel(n + 2)
+        plan.generate([s0], [n], [1], buf.view(dt))
+        torch.cuda.synchronize()
+        got = _bits(buf)
+        assert got[0] == SENTINEL and got[n + 1] == SENTINEL
+        for start in (0, (1 << 24) - 3, (1 << 25) - 8):
+            ref, _ = orc.gen(orc.skip(s0, start), 13, kind)
+            assert np.array_equal(got[1 + start:1 + start + 13], ref.view(np.uint64)), start
