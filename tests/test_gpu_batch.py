@@ -281,3 +281,38 @@ def test_small_batches_in_kernel_arguments(kind, mulmod):
         for start in (0, (1 << 24) - 3, (1 << 25) - 8):
             ref, _ = orc.gen(orc.skip(s0, start), 13, kind)
             assert np.array_equal(got[1 + start:1 + start + 13], ref.view(np.uint64)), start
+
+
+def test_batch_offsets_beyond_32_bit_indexing():
+    """Windows whose output offsets lie past 2^32 elements (a 34 GiB output),
+    one of them at an odd offset, in the workspace and the kernel-argument
+    paths."""
+    base = (1 << 32) + 1
+    lengths = [5000, 1 << 20, 77, 300_001]
+    offsets = [base, base + 5000 + 3, base + 5000 + 3 + (1 << 20) + 1, 3]
+    total = offsets[2] + lengths[2] + 16
+    states = [orc.seed(wl.INDEX_MIN + 31 * i) for i in range(4)]
+    out = torch.empty(total, dtype=torch.uint64, device="cuda")
+    for graph in (True, False):
+        with nn.BatchPlan("u64", 32, total, graph=graph) as plan:
+            plan.generate(states, lengths, offsets, out)
+            torch.cuda.synchronize()
+        flat = out.view(torch.int64)
+        for s, n, o in zip(states, lengths, offsets):
+            for st in (0, n - 64):
+                ref, _ = orc.gen(orc.skip(s, st), 64, "u64")
+                got = flat[o + st:o + st + 64].cpu().numpy().view(np.uint64)
+                assert np.array_equal(got, ref), (o, st)
+        # more than 16 windows: the workspace path with the same offsets
+        st2 = states * 5
+        ln2 = [64] * 20
+        of2 = [base + 128 * i + (i & 1) for i in range(20)]
+        with nn.BatchPlan("u64", 32, total, graph=graph) as plan:
+            plan.generate(st2, ln2, of2, out)
+            torch.cuda.synchronize()
+        for s, o in zip(st2, of2):
+            ref, _ = orc.gen(s, 64, "u64")
+            got = out.view(torch.int64)[o:o + 64].cpu().numpy().view(np.uint64)
+            assert np.array_equal(got, ref), o
+    del out
+    torch.cuda.empty_cache()

@@ -344,3 +344,22 @@ def test_consecutive_layout_validation():
         nn.fill(out, 0, cfg=nn.make_cfg(layout="consecutive"))
     torch.cuda.synchronize()
     assert (_bits(buf) == SENTINEL).all()
+
+
+def test_counts_beyond_32_bit_indexing():
+    """2^33 + 3 raw states (64 GiB) in one call: row pointers, row counts and
+    the ragged tail past 2^32 elements; windows sampled against the oracle
+    started there by skip-ahead, and the state hand-off."""
+    n = (1 << 33) + 3
+    z0 = orc.seed(wl.INDEX_MIN + 2024)
+    out = torch.empty(n, dtype=torch.uint64, device="cuda")
+    zn = nn.generate_into(z0, out)
+    torch.cuda.synchronize()
+    assert zn == orc.skip(z0, n)
+    flat = out.view(torch.int64)
+    for st in (0, (1 << 32) - 2048, (1 << 32) + 12345, (1 << 33) - 4096, n - 4096):
+        ref, _ = orc.gen(orc.skip(z0, st), 4096, "u64")
+        got = flat[st:st + 4096].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), st
+    del out, flat
+    torch.cuda.empty_cache()
