@@ -67,6 +67,23 @@ __device__ __forceinline__ void store_pair(global_ptr<uint64_t> out, const Batch
     }
 }
 
+// The window holding row r, given a window d at or before it (row_start
+// of d <= r): each lane of the wavefront reads the first row of one of the
+// next 64 windows, and a ballot finds the first that starts past r, so a
+// member of a cluster passes windows it has no rows in 64 per load instead
+// of one dependent load each.  Wave-uniform result.
+__device__ __forceinline__ uint32_t window_of(const_ptr<BatchDesc> desc, uint32_t n_desc,
+                                              uint32_t d, uint64_t r) {
+    const uint32_t lane = threadIdx.x & 63u;
+    for (;;) {
+        const uint32_t cand = d + 1 + lane;
+        const bool past = cand >= n_desc || desc[cand].row_start > r;
+        const uint64_t mask = __ballot(past);
+        if (mask) return d + (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+        d += 64;
+    }
+}
+
 template <class V, int KIND>
 __device__ __forceinline__ u64x2 pair_bits(typename V::S za, typename V::S zb) {
     u64x2 v;
@@ -109,10 +126,10 @@ __device__ __forceinline__ void batch_body(const BatchArgs& a, const const_ptr<B
     }
     uint32_t d = lo;
     const uint64_t BK = (uint64_t)B * K;  // pairs from one of the member's rows to the next
+    uint64_t next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
     while (r < r1) {
-        uint64_t next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
-        while (r >= next_start) {  // a later window (empty ones have no rows)
-            ++d;
+        if (r >= next_start) {
+            d = window_of(desc, n_desc, d, r);
             next_start = d + 1 < n_desc ? desc[d + 1].row_start : n_rows;
         }
         const BatchDesc D = load_desc(desc + d);
