@@ -90,3 +90,64 @@ def test_served_trace_slice_checked_per_request():
         res = serve.replay_served(srv, sl, consumer=consumer, timeout_s=60)
     _say("served slice", res)
     assert not bad and res["failed"] == 0 and res["requests"] == n
+
+
+def test_pool_pressure_admission_and_cancel_on_device():
+    """A pool far smaller than the demand: requests wait at the head of the
+    queue until releases free memory, a queued request cancelled meanwhile
+    completes with NN_ECANCELED and keeps its window, and every served
+    request equals the oracle on its window."""
+    states = _states(4, 31)
+    pool_bytes = 8 << 20  # 1 Mi f64
+    rng = np.random.default_rng(32)
+    reqs = [(int(rng.integers(0, 4)), int(rng.integers(1, 300_000))) for _ in range(80)]
+    with serve.Server(states, pool_bytes, lanes=2) as srv:
+        tickets = [srv.submit(s, n) for s, n in reqs]
+        victim = tickets[-1]
+        srv.cancel(victim)
+        done = {}
+        guard = 0
+        while len(done) < len(reqs):
+            for c in srv.poll():
+                done[c.ticket] = c
+                if c.ticket == victim:
+                    assert c.status == serve.NN_ECANCELED
+                    continue
+                assert c.status == 0
+                st = int(states[c.stream_id])
+                k = min(64, c.count)
+                d = srv.data(c)
+                head, _ = orc.gen(orc.skip(st, c.position), k, "f64")
+                tail, _ = orc.gen(orc.skip(st, c.position + c.count - k), k, "f64")
+                assert np.array_equal(_bits(d[:k]), head.view(np.uint64))
+                assert np.array_equal(_bits(d[c.count - k:]), tail.view(np.uint64))
+                srv.release(c.ticket)
+            guard += 1
+            assert guard < 10_000_000
+        srv.release(victim)
+        pos = [0] * 4
+        for t, (s, n) in zip(tickets, reqs):
+            assert done[t].position == pos[s]  # windows fixed at submission
+            pos[s] += n
+        st = srv.stats()
+        assert st["pool_used"] == 0 and st["pool_peak"] <= pool_bytes
+
+
+def test_destroy_with_batches_in_flight():
+    """Closing a server while its batches run waits for them; a new server
+    on the same device then works."""
+    states = _states(2, 41)
+    srv = serve.Server(states, 1 << 30, lanes=2)
+    for _ in range(20):
+        srv.submit(0, 1 << 22)
+    srv.poll()  # admits and launches
+    srv.close()
+    torch.cuda.synchronize()
+    with serve.Server(states, 1 << 24, lanes=1) as srv2:
+        t = srv2.submit(1, 1000)
+        got = []
+        while not got:
+            got = srv2.poll()
+        ref, _ = orc.gen(int(states[1]), 1000, "f64")
+        assert got[0].ticket == t and np.array_equal(_bits(srv2.data(got[0])), ref.view(np.uint64))
+        srv2.release(t)
