@@ -152,6 +152,9 @@ def served_leg(nn, torch):
     res["batch_cfg"] = shape
     with serve.Server(states, pool, lanes=2, **shape) as srv:
         res["served"] = serve.replay_served_native(srv, tr, timeout_s=120)
+    # Requests up to 2^16 outputs through the persistent device queue.
+    with serve.Server(states, pool, lanes=2, device_queue=True, **shape) as srv:
+        res["served_device_queue"] = serve.replay_served_native(srv, tr, timeout_s=120)
     res["plain_per_request"] = serve.replay_per_request_native(tr, states, pool // 8,
                                                                timeout_s=120)
     n = 20000
@@ -159,11 +162,14 @@ def served_leg(nn, torch):
     for scale in (4, 16, 32, 64):
         with serve.Server(states, pool, lanes=2, **shape) as srv:
             a = serve.replay_served_native(srv, tr, time_scale=scale, timeout_s=120, n=n)
+        with serve.Server(states, pool, lanes=2, device_queue=True, **shape) as srv:
+            q = serve.replay_served_native(srv, tr, time_scale=scale, timeout_s=120, n=n)
         b = serve.replay_per_request_native(tr, states, pool // 8, time_scale=scale,
                                             timeout_s=120, n=n)
-        sweep.append({"load_x": scale,
-                      "served": {k: a[k] for k in ("variates_per_s", "p50_ms", "p99_ms")},
-                      "plain": {k: b[k] for k in ("variates_per_s", "p50_ms", "p99_ms")}})
+        keys = ("variates_per_s", "p50_ms", "p99_ms")
+        sweep.append({"load_x": scale, "served": {k: a[k] for k in keys},
+                      "served_device_queue": {k: q[k] for k in keys},
+                      "plain": {k: b[k] for k in keys}})
     res["load_sweep_first_20000"] = sweep
     torch.cuda.empty_cache()
     return res

@@ -309,12 +309,28 @@ typedef struct nn_server_cfg {
     nn_batch_cfg batch;          /* kernel shape of every lane's plan */
     double fake_latency_s;       /* fake device: seconds per batch */
     double fake_bytes_per_s;     /* fake device: write rate (0 = instant) */
+    /* NN_SERVER_DEVICE_QUEUE only: */
+    uint64_t queue_max_outputs;  /* requests of at most this many outputs go to
+                                    the device queue; 0 = 2^16 */
+    uint32_t queue_workgroups;   /* workgroups of the queue kernel; 0 = 16 */
+    uint32_t queue_capacity;     /* ring entries, a power of two; 0 = 1024 */
+    double queue_idle_s;         /* the queue kernel leaves after this long
+                                    without work (and is relaunched on demand);
+                                    0 = 0.05 */
 } nn_server_cfg;
 /* Fake device: host memory pool, outputs computed on the host by the
  * library's exact host arithmetic, completions on a clock set by the caller
  * (nn_server_set_clock), launch failures injectable.  For testing the
  * scheduler without a GPU. */
 #define NN_SERVER_FAKE_DEVICE 1u
+/* Device request queue: admitted requests up to queue_max_outputs skip the
+ * batch launch.  A persistent kernel on its own stream serves them from a
+ * ring in host-mapped memory that the server publishes into, so such a
+ * request costs no launch; its workgroups claim the request's rows as they
+ * reach it.  Larger requests, and any that find the ring full, take the
+ * batch lanes.  Outputs are the same either way (windows are fixed at
+ * submission).  GPU only. */
+#define NN_SERVER_DEVICE_QUEUE 2u
 
 typedef struct nn_completion {
     uint64_t ticket;

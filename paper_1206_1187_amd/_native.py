@@ -86,6 +86,7 @@ _vp = ctypes.c_void_p
 _int = ctypes.c_int
 
 NN_SERVER_FAKE_DEVICE = 1
+NN_SERVER_DEVICE_QUEUE = 2
 NN_ECANCELED = 6
 
 
@@ -102,6 +103,10 @@ class ServerCfg(ctypes.Structure):
         ("batch", BatchCfg),
         ("fake_latency_s", ctypes.c_double),
         ("fake_bytes_per_s", ctypes.c_double),
+        ("queue_max_outputs", ctypes.c_uint64),
+        ("queue_workgroups", ctypes.c_uint32),
+        ("queue_capacity", ctypes.c_uint32),
+        ("queue_idle_s", ctypes.c_double),
     ]
 
 

@@ -275,6 +275,124 @@ __global__ __launch_bounds__(256) void k_batch_il(BatchArgs a) {
     }
 }
 
+// The device request queue (see nn_batch.hpp).  Thread 0 of a workgroup
+// waits for the next entry with acquire loads of the host's `head`, copies
+// the entry to LDS, and claims rows with a compare-and-swap that also checks
+// the slot's round, so a workgroup arriving after the entry is complete (its
+// slot already reset for the next round) claims nothing.  Each claimed row
+// is generated as in the batch kernel.  The workgroup whose finished rows
+// complete the entry resets the slot for the next round, then publishes
+// seq + 1 to the host with a system-scope release.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_queue(QueueArgs a) {
+    __shared__ QueueEntry s_e;
+    __shared__ uint32_t s_go;
+    __shared__ uint64_t s_claim;
+    const uint32_t B = blockDim.x;
+    const uint32_t l = threadIdx.x;
+    const uint64_t t0 = (uint64_t)wall_clock64();
+    uint64_t last = t0;
+    for (uint64_t seq = a.start;; ++seq) {
+        const uint32_t slot = (uint32_t)(seq & (a.cap - 1));
+        if (l == 0) {
+            uint32_t go = 0;
+            for (;;) {
+                const uint64_t h =
+                    __hip_atomic_load(&a.sh->head, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                const uint64_t now = (uint64_t)wall_clock64();
+                if (h > seq) {
+                    go = 1;
+                    last = now;
+                    break;
+                }
+                if (__hip_atomic_load(&a.sh->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM))
+                    break;
+                if (now - last > a.idle_ticks || now - t0 > a.max_ticks) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+            if (go) s_e = a.entries[slot];
+            s_go = go;
+        }
+        __syncthreads();
+        if (!s_go) return;
+        const QueueEntry E = s_e;
+        const uint64_t rows = (E.count + 2ull * B - 1) / (2ull * B);
+        const uint64_t round = (seq >> a.cap_log2) & 0xffffffffull;
+        const uint64_t src = a.states[E.src_row];
+        const global_ptr<uint64_t> out = as_global(reinterpret_cast<uint64_t*>(E.out));
+        uint64_t mine = 0;
+        for (;;) {
+            __syncthreads();  // s_claim and s_e are rewritten below
+            if (l == 0) {
+                uint64_t first = ~0ull;
+                uint64_t old =
+                    __hip_atomic_load(&a.claim[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                while ((old >> 32) == round && (old & 0xffffffffull) < rows) {
+                    if (__hip_atomic_compare_exchange_strong(
+                            &a.claim[slot], &old, old + kQueueRowsPerClaim, __ATOMIC_RELAXED,
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        first = old & 0xffffffffull;
+                        break;
+                    }
+                }
+                s_claim = first;
+            }
+            __syncthreads();
+            const uint64_t c0 = s_claim;
+            if (c0 == ~0ull) break;
+            const uint64_t c1 = c0 + kQueueRowsPerClaim < rows ? c0 + kQueueRowsPerClaim : rows;
+            // Row j covers outputs [2 j B, 2 (j + 1) B); lane l owns x_b - 1 and
+            // x_b = 2 (j B + l) + 1, the state src * (2^53)^(pos + x_b + 1).
+            uint64_t xb = 2ull * (c0 * B + l) + 1;
+            VarFP64::S zb = skip_any<VarFP64>(src, E.pos + xb + 1, a.t_sk);
+            VarFP64::S za = VarFP64::mul(zb, a.Minv);
+            for (uint64_t j = c0; j < c1; ++j) {
+                const global_ptr<uint64_t> p = out + (xb - 1);
+                if (xb < E.count) {
+                    u64x2 v;
+                    v.x = out_bits<VarFP64, KIND>(za);
+                    v.y = out_bits<VarFP64, KIND>(zb);
+                    put<true>(reinterpret_cast<global_ptr<u64x2>>(p), v);
+                } else if (xb - 1 < E.count) {
+                    put<true>(p, out_bits<VarFP64, KIND>(za));
+                }
+                za = VarFP64::mul(za, a.JB);
+                zb = VarFP64::mul(zb, a.JB);
+                xb += 2ull * B;
+            }
+            mine += c1 - c0;
+        }
+        if (mine) {
+            __threadfence();  // this wave's outputs are visible device-wide
+            __syncthreads();
+            if (l == 0) {
+                const uint64_t before = __hip_atomic_fetch_add(&a.fin[slot], mine, __ATOMIC_ACQ_REL,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                if (before + mine == rows) {
+                    __hip_atomic_store(&a.fin[slot], 0ull, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&a.claim[slot], (round + 1) << 32, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __threadfence_system();
+                    __hip_atomic_store(&a.done[slot], seq + 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+            }
+        }
+        __syncthreads();  // s_go and s_e are rewritten by thread 0 next
+    }
+}
+
+hipError_t launch_queue(int kind, uint32_t grid, uint32_t block, hipStream_t s,
+                        const QueueArgs& a) {
+    if (block != 256) return hipErrorInvalidValue;
+    if (kind == 0)
+        k_queue<0><<<grid, block, 0, s>>>(a);
+    else
+        k_queue<1><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 const void* batch_map_kernel() { return reinterpret_cast<const void*>(&k_batch_map); }
 
 template <int KIND, bool NT>

@@ -100,4 +100,49 @@ hipError_t launch_batch_inline(int mulmod, int kind, bool nontemporal, bool inde
                                uint32_t grid, uint32_t block, hipStream_t stream,
                                const BatchArgs& a, const BatchInline& in);
 
+// --------------------------------------------------- device request queue --
+// The served form's low-latency path: a persistent kernel serves requests
+// that the host publishes in a ring in fine-grained (coherent) host memory,
+// so a request costs no launch.  Every live workgroup walks the ring in
+// order; the rows of an entry (2*block outputs each) are claimed a few at a
+// time by whichever workgroups reach it, so any workgroup may leave between
+// entries and the rest finish the work.  A workgroup leaves when the host
+// sets `stop`, after `idle_ticks` without a new entry, or after `max_ticks`
+// of life; an entry is then either complete or untouched, and the host
+// relaunches from the first incomplete one.
+struct QueueEntry {
+    uint64_t src_row;  // row of the device stream-state table
+    uint64_t pos;      // window position (reduced modulo the period)
+    uint64_t count;    // outputs, > 0
+    uint64_t out;      // device address of output 0, 16-byte aligned
+};
+
+struct QueueShared {  // host memory, fine-grained
+    uint64_t head;    // host: entries [0, head) are published
+    uint64_t stop;    // host: leave once no published entry is left
+    uint64_t pad[6];
+};
+
+constexpr uint32_t kQueueRowsPerClaim = 4;
+
+struct QueueArgs {
+    QueueShared* sh;
+    const QueueEntry* entries;  // host memory, cap entries (ring)
+    uint64_t* done;             // host memory, cap entries: seq + 1 once entry seq is complete
+    uint64_t* claim;            // device, cap entries: (round << 32) | rows claimed
+    uint64_t* fin;              // device, cap entries: rows finished
+    uint32_t cap;               // ring capacity, a power of two
+    uint32_t cap_log2;
+    uint64_t start;             // first entry of this launch
+    const uint64_t* states;     // device stream-state table
+    const Mult* t_sk;
+    Mult JB;                    // (2^53)^(2*block): a lane's next row
+    Mult Minv;                  // (2^53)^-1
+    uint64_t idle_ticks;        // wall-clock ticks
+    uint64_t max_ticks;
+};
+
+hipError_t launch_queue(int kind, uint32_t grid, uint32_t block, hipStream_t stream,
+                        const QueueArgs& a);
+
 }  // namespace nn

@@ -134,6 +134,8 @@ struct nn_server {
     bool own_pool = true;
     PoolAllocator* alloc = nullptr;
     std::vector<Lane> lanes;
+    nn::DeviceQueue* dq = nullptr;                          // NN_SERVER_DEVICE_QUEUE
+    std::vector<std::pair<uint64_t, uint64_t>> qflight;     // (queue entry, ticket)
     std::unordered_map<uint64_t, Request> reqs;
     std::deque<uint64_t> queue;    // arrival order, not yet admitted
     std::vector<uint64_t> pending;  // admitted, not yet launched
@@ -160,6 +162,7 @@ constexpr uint32_t kDefaultSlots = 65536;
 constexpr uint32_t kDefaultLanes = 2;
 
 void server_free(nn_server* s) {
+    if (s->dq) queue_destroy(s->dq);  // before the pool and the state table
     for (Lane& l : s->lanes) {
         if (l.plan) plan_release(l.plan);
         if (l.stream) (void)hipStreamDestroy(l.stream);
@@ -203,6 +206,21 @@ void fake_fill(nn_server* s, const Request& r) {
 
 void harvest(nn_server* s) {
     const double t = s->now();
+    if (s->dq && !s->qflight.empty()) {
+        for (size_t i = 0; i < s->qflight.size();) {
+            if (queue_done(s->dq, s->qflight[i].first)) {
+                finish(s, s->reqs[s->qflight[i].second], NN_OK, t);
+                s->qflight[i] = s->qflight.back();
+                s->qflight.pop_back();
+            } else {
+                ++i;
+            }
+        }
+        if (!s->qflight.empty() && queue_keep_running(s->dq) != NN_OK) {
+            for (auto& f : s->qflight) finish(s, s->reqs[f.second], NN_EHIP, t);
+            s->qflight.clear();
+        }
+    }
     for (Lane& l : s->lanes) {
         if (!l.busy) continue;
         bool done;
@@ -225,8 +243,11 @@ bool admit(nn_server* s) {
     while (!s->queue.empty()) {
         Request& r = s->reqs[s->queue.front()];
         if (s->slots_used >= s->cfg.max_slots) break;
-        if (s->pending.size() >= s->cfg.max_batch_requests) break;
-        if (s->pending_outputs + r.count > s->cfg.max_batch_outputs) break;
+        const bool small = s->dq && r.count && r.count <= s->cfg.queue_max_outputs;
+        if (!small) {
+            if (s->pending.size() >= s->cfg.max_batch_requests) break;
+            if (s->pending_outputs + r.count > s->cfg.max_batch_outputs) break;
+        }
         if (r.count) {
             uint64_t off = 0;
             if (!s->alloc->alloc(r.count * 8, &off)) break;  // head of line waits for memory
@@ -237,6 +258,26 @@ bool admit(nn_server* s) {
         r.t_admit = t;
         ++s->slots_used;
         s->queue.pop_front();
+        if (small) {
+            // Straight to the device queue, no batch launch.
+            uint64_t seq = 0;
+            const int st = queue_submit(s->dq, r.stream, r.pos, r.count, s->pool + r.pool_off, &seq);
+            if (st == NN_OK) {
+                r.state = kInFlight;
+                r.t_launch = t;
+                ++s->stats.in_flight;
+                s->qflight.emplace_back(seq, r.ticket);
+                any = true;
+                continue;
+            }
+            if (st != NN_ERANGE) {  // the queue kernel could not be launched
+                ++s->stats.in_flight;
+                finish(s, r, st, t);
+                any = true;
+                continue;
+            }
+            // The ring is full: the batch path takes it.
+        }
         if (r.count == 0) {
             ++s->stats.in_flight;
             finish(s, r, NN_OK, t);
@@ -336,7 +377,14 @@ int nn_server_create(const nn_server_cfg* cfg, const uint64_t* stream_states, ui
                         (unsigned long long)stream_states[i]);
     nn_server_cfg c = *cfg;
     if (c.kind != NN_OUT_U64 && c.kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %u unknown", c.kind);
-    if (c.flags & ~(NN_SERVER_FAKE_DEVICE)) return fail(NN_EINVAL, "unknown server flags 0x%x", c.flags);
+    if (c.flags & ~(NN_SERVER_FAKE_DEVICE | NN_SERVER_DEVICE_QUEUE))
+        return fail(NN_EINVAL, "unknown server flags 0x%x", c.flags);
+    if ((c.flags & NN_SERVER_DEVICE_QUEUE) && (c.flags & NN_SERVER_FAKE_DEVICE))
+        return fail(NN_EINVAL, "the device queue needs a GPU");
+    if (!c.queue_max_outputs) c.queue_max_outputs = 1ull << 16;
+    if (!c.queue_workgroups) c.queue_workgroups = 16;
+    if (!c.queue_capacity) c.queue_capacity = 1024;
+    if (!(c.queue_idle_s > 0.0)) c.queue_idle_s = 0.05;
     if (!c.pool_bytes) return fail(NN_EINVAL, "pool_bytes must be positive");
     if (!c.max_batch_outputs) c.max_batch_outputs = kDefaultBatchOutputs;
     if (!c.max_batch_requests) c.max_batch_requests = kDefaultBatchRequests;
@@ -407,6 +455,14 @@ int nn_server_create(const nn_server_cfg* cfg, const uint64_t* stream_states, ui
         }
         int st = plan_create((int)c.kind, c.max_batch_requests, c.max_batch_outputs, &c.batch,
                              true, s->dev_states, &l.plan);
+        if (st) {
+            server_free(s);
+            return st;
+        }
+    }
+    if (c.flags & NN_SERVER_DEVICE_QUEUE) {
+        int st = queue_create((int)c.kind, c.queue_workgroups, c.queue_capacity, c.queue_idle_s,
+                              s->dev_states, &s->dq);
         if (st) {
             server_free(s);
             return st;

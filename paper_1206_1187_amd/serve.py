@@ -31,7 +31,8 @@ class Server:
 
     def __init__(self, stream_states, pool_bytes, kind="f64", lanes=2, max_batch_outputs=0,
                  max_batch_requests=0, max_slots=0, fake=False, fake_latency_s=0.0,
-                 fake_bytes_per_s=0.0, **batch_kw):
+                 fake_bytes_per_s=0.0, device_queue=False, queue_max_outputs=0,
+                 queue_workgroups=0, queue_capacity=0, queue_idle_s=0.0, **batch_kw):
         from . import MULMOD_NAMES
         kind = NN_OUT_U64 if kind in ("u64", NN_OUT_U64) else NN_OUT_F64
         self.kind = kind
@@ -49,10 +50,12 @@ class Server:
             import torch
             self.pool = torch.empty(self.pool_bytes // 8, dtype=torch.int64, device="cuda")
             pool_ptr = self.pool.data_ptr()
+        flags = (NN_SERVER_FAKE_DEVICE if self.fake else 0) | \
+            (_native.NN_SERVER_DEVICE_QUEUE if device_queue else 0)
         cfg = ServerCfg(pool_ptr, self.pool_bytes, int(max_batch_outputs),
-                        int(max_batch_requests), int(max_slots), int(lanes), kind,
-                        NN_SERVER_FAKE_DEVICE if self.fake else 0, batch,
-                        float(fake_latency_s), float(fake_bytes_per_s))
+                        int(max_batch_requests), int(max_slots), int(lanes), kind, flags, batch,
+                        float(fake_latency_s), float(fake_bytes_per_s), int(queue_max_outputs),
+                        int(queue_workgroups), int(queue_capacity), float(queue_idle_s))
         st = np.ascontiguousarray(stream_states, dtype=np.uint64)
         h = ctypes.c_void_p()
         _native.check(_lib().nn_server_create(ctypes.byref(cfg), st.ctypes.data, st.size,

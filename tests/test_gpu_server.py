@@ -151,3 +151,88 @@ def test_destroy_with_batches_in_flight():
         ref, _ = orc.gen(int(states[1]), 1000, "f64")
         assert got[0].ticket == t and np.array_equal(_bits(srv2.data(got[0])), ref.view(np.uint64))
         srv2.release(t)
+
+
+def _drain(srv, n, limit=5_000_000):
+    done = {}
+    k = 0
+    while len(done) < n:
+        for c in srv.poll():
+            done[c.ticket] = c
+        k += 1
+        assert k < limit, "server did not finish"
+    return done
+
+
+@pytest.mark.parametrize("kind", ["f64", "u64"])
+def test_device_queue_requests_equal_oracle(kind):
+    """Requests served by the persistent device queue (no launch per
+    request) and, above its size limit or with its ring full, by the batch
+    lanes: every request equals the oracle on its window and the plain path
+    run alone."""
+    states = _states(8, 51)
+    rng = np.random.default_rng(52)
+    sizes = [1, 2, 3, 511, 512, 513, 1023, 1024, 1025, 65_535, 65_536, 65_537, 300_000]
+    reqs = [(int(rng.integers(0, 8)), s) for s in sizes]
+    reqs += [(int(rng.integers(0, 8)), int(np.floor(np.exp(rng.uniform(0, np.log(1 << 17))))))
+             for _ in range(400)]
+    with serve.Server(states, 1 << 28, kind=kind, lanes=2, device_queue=True,
+                      queue_max_outputs=1 << 16, queue_capacity=64) as srv:
+        tickets = [srv.submit(s, n) for s, n in reqs]
+        done = _drain(srv, len(reqs))
+        pos = [0] * 8
+        for t, (s, n) in zip(tickets, reqs):
+            c = done[t]
+            assert c.status == 0 and c.position == pos[s]
+            pos[s] += n
+            got = _bits(srv.data(c))
+            ref, _ = orc.gen(orc.skip(int(states[s]), c.position), n, kind)
+            assert np.array_equal(got, ref.view(np.uint64)), (t, s, n)
+            if n <= 1 << 12:
+                alone, _ = nn.generate(nn.skip(int(states[s]), c.position), n, kind)
+                torch.cuda.synchronize()
+                assert np.array_equal(_bits(alone), got)
+            srv.release(t)
+        assert srv.stats()["pool_used"] == 0
+
+
+def test_device_queue_idle_exit_and_relaunch():
+    """The queue kernel leaves after a short idle time and is relaunched on
+    the next request, which is served correctly."""
+    import time
+    states = _states(2, 61)
+    with serve.Server(states, 1 << 24, lanes=1, device_queue=True, queue_idle_s=0.002) as srv:
+        pos = 0
+        for rep in range(4):
+            t = srv.submit(1, 5000 + rep)
+            c = _drain(srv, 1)[t]
+            ref, _ = orc.gen(orc.skip(int(states[1]), pos), 5000 + rep, "f64")
+            assert c.position == pos and np.array_equal(_bits(srv.data(c)), ref.view(np.uint64))
+            pos += 5000 + rep
+            srv.release(t)
+            time.sleep(0.03)  # the kernel leaves meanwhile
+
+
+def test_device_queue_trace_slice():
+    """A slice of the served workload with the device queue: first and last
+    outputs of every request against the oracle."""
+    tr = wl.served()
+    n = 600
+    sl = wl.ServedTrace(tr.stream_indices, tr.t_arrive[:n], tr.stream_id[:n], tr.count[:n])
+    states = np.array([orc.seed(int(a)) for a in tr.stream_indices], dtype=np.uint64)
+    bad = []
+
+    def consumer(server, c):
+        d = server.data(c)
+        k = min(32, c.count)
+        s0 = int(states[c.stream_id])
+        head, _ = orc.gen(orc.skip(s0, c.position), k, "f64")
+        tail, _ = orc.gen(orc.skip(s0, c.position + c.count - k), k, "f64")
+        if not (np.array_equal(_bits(d[:k]), head.view(np.uint64)) and
+                np.array_equal(_bits(d[c.count - k:]), tail.view(np.uint64))):
+            bad.append(c.ticket)
+
+    with serve.Server(states, 16 << 30, lanes=2, device_queue=True) as srv:
+        res = serve.replay_served(srv, sl, consumer=consumer, timeout_s=60)
+    _say("device queue slice", res)
+    assert not bad and res["failed"] == 0 and res["requests"] == n

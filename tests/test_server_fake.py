@@ -226,3 +226,10 @@ def test_same_result_alone_and_in_the_mix():
             c, d = mixed[tickets[k]]
             assert got[t].position == c.position
             assert np.array_equal(alone.data(got[t]), d)
+
+
+def test_device_queue_needs_a_gpu():
+    from paper_1206_1187_amd import NNError
+    with pytest.raises(NNError):
+        serve.Server(np.array([orc.seed(wl.INDEX_MIN)], dtype=np.uint64), 1 << 20, fake=True,
+                     device_queue=True)
