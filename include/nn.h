@@ -327,8 +327,8 @@ typedef struct nn_server_cfg {
  * batch launch.  A persistent kernel on its own stream serves them from a
  * ring in host-mapped memory that the server publishes into, so such a
  * request costs no launch; its workgroups claim the request's rows as they
- * reach it.  Larger requests, and any that find the ring full, take the
- * batch lanes.  Outputs are the same either way (windows are fixed at
+ * reach it.  Larger requests, and small ones while two per queue workgroup
+ * are already in flight or the ring is full, take the batch lanes.  Outputs are the same either way (windows are fixed at
  * submission).  GPU only. */
 #define NN_SERVER_DEVICE_QUEUE 2u
 

@@ -243,7 +243,11 @@ bool admit(nn_server* s) {
     while (!s->queue.empty()) {
         Request& r = s->reqs[s->queue.front()];
         if (s->slots_used >= s->cfg.max_slots) break;
-        const bool small = s->dq && r.count && r.count <= s->cfg.queue_max_outputs;
+        // Small requests take the device queue while it keeps up (at most two
+        // entries in flight per queue workgroup); under heavier load the
+        // batch lanes, which spread each batch over the whole device.
+        const bool small = s->dq && r.count && r.count <= s->cfg.queue_max_outputs &&
+                           s->qflight.size() < 2ull * s->cfg.queue_workgroups;
         if (!small) {
             if (s->pending.size() >= s->cfg.max_batch_requests) break;
             if (s->pending_outputs + r.count > s->cfg.max_batch_outputs) break;
