@@ -365,6 +365,11 @@ def main():
             s = _timed_kernel(
                 lambda: nn.generate_into(nn.seed(case.index), out, cfg=cfg), 10, torch)
             shoot["modbarrett_consecutive_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
+            # ... and in the paper's own transposed layout (512 threads x 4096).
+            cfg = nn.make_cfg(layout="paper_strided")
+            s = _timed_kernel(
+                lambda: nn.generate_into(nn.seed(case.index), out, cfg=cfg), 10, torch)
+            shoot["modbarrett_paper_strided_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
         extras["mulmod_shootout_default_shape"] = shoot
         # Section 2's larger modulus 3^40 (64-bit states, Montgomery step).
         for kind, out in (("f64", out_f), ("u64", out_u)):

@@ -116,6 +116,14 @@ typedef struct nn_launch_cfg {
 #define NN_CFG_ROWS 2u
 #define NN_CFG_FLAT 4u
 #define NN_CFG_CONSECUTIVE 8u
+/* The paper's own layout (Section 3.2), for comparison: T = count / unroll
+ * threads (block threads per workgroup, default 512), thread t makes
+ * elements t*E .. t*E + E-1 (E = unroll, default 4096, must divide count)
+ * with the Modified Barrett step and stores its i-th one at out[t + i*T]:
+ * coalesced 8-byte stores, but the array holds the sequence TRANSPOSED,
+ * out[t + i*T] = z_(t*E + i + 1), not in serial order.  mulmod 0 or
+ * NN_MULMOD_MODBARRETT; grid, width, ilp and occupancy must be 0. */
+#define NN_CFG_PAPER_STRIDED 16u
 
 /* ---------------------------------------------------------------- host -- */
 

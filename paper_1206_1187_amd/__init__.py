@@ -55,7 +55,8 @@ def init(device=0):
 def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layout=None,
              occupancy=0, ilp=0):
     """Launch configuration (include/nn.h, nn_launch_cfg); ``layout`` is
-    None (library default), "flat", "rows" or "consecutive"."""
+    None (library default), "flat", "rows", "consecutive" or "paper_strided"
+    (the paper's transposed order: out[t + i*T] = element t*E + i)."""
     if isinstance(mulmod, str):
         mulmod = MULMOD_NAMES[mulmod]
     flags = _native.NN_CFG_TEMPORAL_STORES if temporal else 0
@@ -65,8 +66,11 @@ def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layou
         flags |= _native.NN_CFG_ROWS
     elif layout == "consecutive":
         flags |= _native.NN_CFG_CONSECUTIVE
+    elif layout == "paper_strided":
+        flags |= _native.NN_CFG_PAPER_STRIDED
     elif layout is not None:
-        raise NNError(_native.NN_EINVAL, "layout must be None, 'flat', 'rows' or 'consecutive'")
+        raise NNError(_native.NN_EINVAL, "layout must be None, 'flat', 'rows', 'consecutive' "
+                      "or 'paper_strided'")
     return LaunchCfg(int(block), int(grid), int(mulmod), int(unroll), flags, int(width),
                      int(occupancy), int(ilp))
 

@@ -17,6 +17,7 @@ NN_CFG_TEMPORAL_STORES = 1
 NN_CFG_ROWS = 2
 NN_CFG_FLAT = 4
 NN_CFG_CONSECUTIVE = 8
+NN_CFG_PAPER_STRIDED = 16
 
 MULMOD_NAMES = {
     "default": NN_MULMOD_DEFAULT,

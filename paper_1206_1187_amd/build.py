@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libnn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["nn_capi.hip", "nn_runtime.hip", "nn_server.hip", "nn_kernels.hip", "nn_batch.hip",
-           "nn_e40.hip", "nn_queue.hip"]
+           "nn_e40.hip", "nn_queue.hip", "nn_strided.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950",

@@ -14,6 +14,7 @@
 
 #include "nn_batch.hpp"
 #include "nn_device.hpp"
+#include "nn_skip.hpp"
 
 namespace nn {
 
@@ -26,17 +27,6 @@ __device__ __forceinline__ BatchDesc load_desc(const_ptr<BatchDesc> p) {
     D.out_off = p->out_off;
     D.row_start = p->row_start;
     return D;
-}
-
-// src * (2^53)^k for any k < 2^52 through the four 13-bit skip tables.
-template <class V>
-__device__ __forceinline__ typename V::S skip_any(uint64_t src, uint64_t k,
-                                                  const Mult* __restrict__ t_sk) {
-    typename V::S z = V::load(src);
-#pragma unroll
-    for (uint32_t lvl = 0; lvl < kSkipLevels; ++lvl)
-        z = V::mul(z, t_sk[lvl * kSkipSize + ((k >> (kSkipBits * lvl)) & (kSkipSize - 1))]);
-    return z;
 }
 
 // Stores row r's pair of lane l: x_b = 2(jr*B + l) + 1 - s, x_a = x_b - 1.

@@ -145,4 +145,10 @@ struct QueueArgs {
 hipError_t launch_queue(int kind, uint32_t grid, uint32_t block, hipStream_t stream,
                         const QueueArgs& a);
 
+// The paper's strided layout (nn_strided.hip): T threads, E consecutive
+// elements each, out[t + i*T] = element t*E + i; base is element 0's state.
+hipError_t launch_generate_strided(int kind, bool nontemporal, uint32_t grid, uint32_t block,
+                                   hipStream_t stream, uint64_t* out, uint64_t T, uint32_t E,
+                                   uint64_t base, const Mult* t_sk);
+
 }  // namespace nn

@@ -26,7 +26,7 @@ namespace {
 
 struct Resolved {
     uint32_t block, grid, mulmod, unroll, width, occupancy, ilp;
-    bool nontemporal, flat, consec;
+    bool nontemporal, flat, consec, strided;
     uint32_t lds;  // dynamic LDS bytes per workgroup that cap residency
 };
 
@@ -40,14 +40,42 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
     const bool aligned16 = ((uintptr_t)out % 16) == 0;
-    const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE;
+    const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE |
+                           NN_CFG_PAPER_STRIDED;
     if (c.flags & ~known) return fail(NN_EINVAL, "unknown flags 0x%x", c.flags);
-    const uint32_t layouts = c.flags & (NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE);
-    if (layouts & (layouts - 1))
-        return fail(NN_EINVAL, "NN_CFG_ROWS, NN_CFG_FLAT and NN_CFG_CONSECUTIVE are exclusive");
+    const uint32_t layouts =
+        c.flags & (NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE | NN_CFG_PAPER_STRIDED);
+    if (layouts & (layouts - 1)) return fail(NN_EINVAL, "the layout flags are exclusive");
     r->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
     r->consec = (c.flags & NN_CFG_CONSECUTIVE) != 0;
+    r->strided = (c.flags & NN_CFG_PAPER_STRIDED) != 0;
     r->flat = false;
+    if (r->strided) {
+        // The paper's layout: E consecutive elements per thread, stored
+        // transposed (out[t + i*T] = element t*E + i), 8-byte stores.
+        r->mulmod = c.mulmod ? c.mulmod : (uint32_t)NN_MULMOD_MODBARRETT;
+        if (r->mulmod != NN_MULMOD_MODBARRETT)
+            return fail(NN_EINVAL, "the strided layout steps with NN_MULMOD_MODBARRETT only");
+        if (c.occupancy || c.ilp > 1 || (c.width && c.width != 1) || c.grid)
+            return fail(NN_EINVAL, "the strided layout takes block, unroll (elements per thread) "
+                                   "and NN_CFG_TEMPORAL_STORES only");
+        r->block = c.block ? c.block : 512u;
+        if (r->block < 64 || r->block > 1024 || r->block % 64)
+            return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", r->block);
+        r->unroll = c.unroll ? c.unroll : 4096u;
+        if (r->unroll == 0 || r->unroll > (1u << 20) || count % r->unroll)
+            return fail(NN_EINVAL, "unroll %u: elements per thread must divide count (%llu)",
+                        r->unroll, (unsigned long long)count);
+        const uint64_t T = count / r->unroll;
+        const uint64_t grid = (T + r->block - 1) / r->block;
+        if (grid > 0x7fffffffull) return fail(NN_ERANGE, "too many threads");
+        r->grid = (uint32_t)(grid ? grid : 1);
+        r->width = 1;
+        r->ilp = 1;
+        r->occupancy = 0;
+        r->lds = 0;
+        return NN_OK;
+    }
     if (r->consec) {
         // The paper's per-thread loop: Eq. 3's multiplier 2^53 with the
         // Modified Barrett step, serial order restored through LDS.
@@ -253,6 +281,15 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
     st = resolve_cfg(cfg, kind, count, *d, out_dev, &r);
     if (st) return st;
 
+    if (r.strided) {
+        hipError_t e = launch_generate_strided(kind, r.nontemporal, r.grid, r.block,
+                                               (hipStream_t)stream, (uint64_t*)out_dev,
+                                               count / r.unroll, r.unroll, h_mulmod(s, kMult),
+                                               d->t_sk);
+        if (e != hipSuccess) return fail(NN_EHIP, "generate launch: %s", hipGetErrorString(e));
+        *state = h_skip(s, count);
+        return ok();
+    }
     if (r.consec) {
         ConsecArgs ca;
         ca.out = (uint64_t*)out_dev;
@@ -375,7 +412,7 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     Resolved r;
     st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r);
     if (st) return st;
-    if (r.consec) return fail(NN_EINVAL, "nn_fill has no consecutive layout");
+    if (r.consec || r.strided) return fail(NN_EINVAL, "nn_fill has no consecutive layout");
     if (r.flat) {
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;

@@ -363,3 +363,30 @@ def test_counts_beyond_32_bit_indexing():
         assert np.array_equal(got, ref), st
     del out, flat
     torch.cuda.empty_cache()
+
+
+def test_paper_strided_layout_is_the_transposed_sequence():
+    """The paper's own layout (Section 3.2), kept for comparison: thread t
+    of T = count/E makes elements t*E .. t*E+E-1 and stores its i-th at
+    t + i*T; read back transposed it is the serial sequence."""
+    z0 = orc.seed(wl.INDEX_MIN + 555)
+    ref_u, _ = orc.gen(z0, 1 << 20, "u64", threads=0)
+    ref_f, _ = orc.gen(z0, 1 << 20, "f64", threads=0)
+    for count, E, block in [(4096, 4096, 512), (1 << 20, 4096, 512), (1 << 20, 16, 64),
+                            (3 * 1000, 3, 1024), (999_999, 1, 256), (1 << 20, 2, 128),
+                            (65_536 * 7, 7 * 512, 256)]:
+        cfg = nn.make_cfg(layout="paper_strided", unroll=E, block=block)
+        for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+            _say("strided", count, E, block, kind)
+            got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=513)
+            T = count // E
+            serial = got.reshape(E, T).T.reshape(-1)
+            assert np.array_equal(serial, ref.view(np.uint64)[:count]), (count, E, block, kind)
+            assert zn == orc.skip(z0, count)
+    out = torch.empty(4096, dtype=torch.float64, device="cuda")
+    for cfg in [nn.make_cfg(layout="paper_strided", unroll=3000),       # does not divide
+                nn.make_cfg(layout="paper_strided", unroll=16, grid=4),
+                nn.make_cfg(layout="paper_strided", unroll=16, mulmod="fp64"),
+                nn.make_cfg(layout="paper_strided", unroll=16, width=2)]:
+        with pytest.raises(nn.NNError):
+            nn.generate_into(z0, out, cfg=cfg)
