@@ -225,7 +225,7 @@ def main():
                          "to scale hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        log("bench.py measures one GPU only: this build has no multi-GPU path "
+        log("bench.py measures one GPU only: this program has no multi-GPU path "
             "(--gpus %d requested)." % args.gpus)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -31,7 +31,7 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        from . import build as _build  # the checker may be built on demand
+        from . import build as _build  # the oracle library is built on demand
         _build.build()
     lib = ctypes.CDLL(LIB_PATH)
     sig = {

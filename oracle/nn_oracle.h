@@ -13,7 +13,7 @@
  * power by square-and-multiply over the full 64-bit exponent; nothing is
  * blocked, fused or reordered beyond the definitions cited per function.
  *
- * Conventions (readings of the paper, recorded with reasons in the design doc):
+ * Conventions (readings of the paper where it leaves a choice open):
  *  - step-then-emit: a call that emits n values from state z emits
  *    z_1..z_n (Eq. 3 applied before each output) and returns z_n;
  *  - f64 output is the IEEE round-to-nearest product double(z) * R with
