@@ -236,3 +236,11 @@ def test_device_queue_trace_slice():
         res = serve.replay_served(srv, sl, consumer=consumer, timeout_s=60)
     _say("device queue slice", res)
     assert not bad and res["failed"] == 0 and res["requests"] == n
+
+
+def test_device_queue_config_validation():
+    states = _states(2, 71)
+    for kw in (dict(queue_capacity=1000), dict(queue_capacity=1 << 21), dict(queue_workgroups=2000),
+               dict(queue_idle_s=30.0)):
+        with pytest.raises(nn.NNError):
+            serve.Server(states, 1 << 20, device_queue=True, **kw)
