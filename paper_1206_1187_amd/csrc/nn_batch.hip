@@ -154,13 +154,17 @@ __device__ __forceinline__ void batch_body(const BatchArgs& a, const const_ptr<B
             j += m * K;
             xb += 2 * BK * m;
             for (; m >= 2; m -= 2) {
+                // each row's store next to its own multiplications (as in
+                // the plain row kernel: bunched stores write slower)
                 put<NT>(p, pair_bits<V, KIND>(za, zb));
-                put<NT>(p + BK, pair_bits<V, KIND>(zc, zd));
-                p += 2 * BK;
                 za = V::mul(za, a.JB2);
                 zb = V::mul(zb, a.JB2);
+                __builtin_amdgcn_sched_barrier(0);
+                put<NT>(p + BK, pair_bits<V, KIND>(zc, zd));
                 zc = V::mul(zc, a.JB2);
                 zd = V::mul(zd, a.JB2);
+                __builtin_amdgcn_sched_barrier(0);
+                p += 2 * BK;
             }
             if (m) {
                 put<NT>(p, pair_bits<V, KIND>(za, zb));

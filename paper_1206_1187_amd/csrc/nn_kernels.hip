@@ -104,13 +104,14 @@ __global__ __launch_bounds__(1024) void k_generate2_ilp(uint64_t* __restrict__ o
             v.x = out_bits<V, KIND>(za[r]);
             v.y = out_bits<V, KIND>(zb[r]);
             put<NT>(row + r * T + t, v);
-        }
-        row += IL * T;
-#pragma unroll
-        for (int r = 0; r < IL; ++r) {
             za[r] = V::mul(za[r], JI);
             zb[r] = V::mul(zb[r], JI);
+            // Each row's store stays next to its own two multiplications:
+            // left to itself the scheduler bunches the stores of a trip
+            // together, which writes about 8 % slower on MI355X.
+            __builtin_amdgcn_sched_barrier(0);
         }
+        row += IL * T;
     }
     // Fewer than IL full rows remain, then the partial row; za[r], zb[r]
     // hold rows i + r.

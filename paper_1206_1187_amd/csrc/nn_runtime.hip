@@ -40,13 +40,13 @@ const char* last_error() { return g_last_error.c_str(); }
 // Defaults from launch-shape sweeps on MI355X (256 CUs, bulk outputs of
 // 2^28..2^30): 16-byte stores per lane from 256-thread workgroups on a
 // fraction of the CUs (fewer concurrent writers keep the HBM write stream
-// closer to sequential).  F64 output: the FP64 reduction with two rows in
-// flight on CUs/2 workgroups; U64 output: the FP64 reduction with four rows
-// in flight on 5*CUs/8 workgroups.
+// closer to sequential).  F64 output: the FP64 reduction with four rows in
+// flight, unrolled 8 times, on CUs/2 workgroups; U64 output: the FP64
+// reduction with two rows in flight on 3*CUs/4 workgroups.
 const KindDefaults& kind_defaults(int kind) {
     static const KindDefaults d[2] = {
-        {NN_MULMOD_FP64, 5, 8, 2, 4},  // NN_OUT_U64
-        {NN_MULMOD_FP64, 1, 2, 4, 2},  // NN_OUT_F64
+        {NN_MULMOD_FP64, 3, 4, 2, 2},  // NN_OUT_U64
+        {NN_MULMOD_FP64, 1, 2, 8, 4},  // NN_OUT_F64
     };
     return d[kind == NN_OUT_F64 ? 1 : 0];
 }
