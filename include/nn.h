@@ -252,11 +252,14 @@ typedef struct nn_batch_cfg {
     uint32_t flags;
 } nn_batch_cfg;
 #define NN_BATCH_NO_GRAPH 8u
-/* Interleave rows over all workgroups (workgroup w takes rows w, w + grid,
- * ...) after a pre-pass that maps rows to streams.  Needs the FP64
- * reduction and at most 256 threads per workgroup; measured slower than
- * the default on the batched workload, kept for batches of few, long
- * streams. */
+/* Interleave rows over all workgroups: a pre-pass writes one record per
+ * row of 2*block outputs (its first state and output index; rows aligned to
+ * the output), then workgroup w writes rows w, w + grid, ..., so all
+ * workgroups write one region of the output at a time, as the plain
+ * generator does.  Needs the FP64 reduction, block 64, 128 or 256, cluster
+ * 1, and output indices below 2^51 (NN_ERANGE otherwise).  Measured on
+ * MI355X: ahead of the default on batches of few long streams, 3-4 %
+ * behind it on 10,000 streams of mixed lengths. */
 #define NN_BATCH_INTERLEAVED 16u
 
 /* Opaque batch plan: device workspace, pinned staging and a hipGraph of

@@ -198,74 +198,219 @@ __global__ __launch_bounds__(1024) void k_batch_inline(BatchArgs a, BatchInline 
     batch_body<V, KIND, NT, INDEXED>(a, as_const(&in.hdr));
 }
 
-// Pre-pass of the interleaved kernel: the window of every batch row.
-__global__ __launch_bounds__(256) void k_batch_map(BatchArgs a) {
-    const BatchHeader* hdr = a.ws;
+// Pre-pass of the interleaved kernel: every row's record.  Its rows are
+// aligned to the output: row j of a window at output offset o covers
+// outputs [W (floor(o / W) + j), W (floor(o / W) + j + 1)), W = 2*kIlPairs*block,
+// which are its elements W j - s + k, k < W, with s = o mod W.  (Adjacent
+// rows go to different workgroups, and rows that shared a cache line would
+// leave partial lines in two L2s.)  Workgroups take windows d = blockIdx.x,
+// + gridDim.x, ...; thread t of 256 takes the window's rows t, t + 256, ...:
+// one skip-ahead to its first row, then a step of (2^53)^(W*256) per row.
+template <bool INDEXED>
+__global__ __launch_bounds__(256) void k_batch_rec(BatchArgs a) {
+    const const_ptr<BatchHeader> hdr = as_const(a.ws);
     const uint32_t n_desc = hdr->n_desc;
     const uint64_t n_rows = hdr->n_rows;
-    const BatchDesc* __restrict__ desc = reinterpret_cast<const BatchDesc*>(hdr + 1);
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
-         r += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t lo = 0, hi = n_desc - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (desc[mid].row_start <= r)
-                lo = mid;
-            else
-                hi = mid - 1;
+    const const_ptr<BatchDesc> desc = reinterpret_cast<const_ptr<BatchDesc>>(hdr + 1);
+    const uint64_t G = a.grid;
+    const uint64_t per = (n_rows + G - 1) / G;
+    const uint64_t W = a.row_outs;  // outputs per row, a power of two
+    const global_ptr<u64x2> rec = reinterpret_cast<global_ptr<u64x2>>(as_global(a.rec));
+    for (uint32_t d = blockIdx.x; d < n_desc; d += gridDim.x) {
+        const BatchDesc D = load_desc(desc + d);
+        const uint64_t s = D.out_off & (W - 1);
+        const uint64_t nr = (D.len + s + W - 1) / W;
+        uint64_t j = threadIdx.x;
+        if (j >= nr) continue;
+        uint64_t src;
+        if constexpr (INDEXED)
+            src = as_const(hdr->states)[D.src];
+        else
+            src = D.src;
+        // element W j - s of the window: src * (2^53)^(pos + W j - s + 1),
+        // the exponent taken modulo the period where it would be negative
+        uint64_t e = D.pos + 1 + W * j;
+        e = e >= s ? e - s : e + kPeriod - s;
+        double z = skip_any<VarFP64>(src, e, a.t_sk);
+        for (; j < nr; j += 256) {
+            const uint64_t r = D.row_start + j;
+            const uint64_t first = W * j;  // s + (window index of element 0)
+            const uint64_t hi = D.len + s - first < W ? D.len + s - first : W;
+            u64x2 R;  // a RowRec
+            R.x = __builtin_bit_cast(uint64_t, z);
+            R.y = (D.out_off - s + first) | (j == 0 ? s : 0) | (hi << kRecHiShift);
+            rec[(r % G) * per + r / G] = R;
+            z = VarFP64::mul(z, a.JR);
         }
-        a.row_desc[r] = lo;
     }
 }
 
-// src * (2^53)^k, k < 2^56, through the LDS copy of the 8-bit skip tables
-// (the public device-side skip, nn_dev_skip).
-__device__ __forceinline__ double skip8(uint64_t src, uint64_t k, const double* t8) {
-    return nn_dev_skip((double)src, k, reinterpret_cast<const nn_dev_mult*>(t8));
+// Lane l's pair of outputs k and k + 1 of a row (states za, zb) at p,
+// storing only those in [lo, hi).
+template <int KIND, bool NT>
+__device__ __forceinline__ void put_pair_in(global_ptr<uint64_t> p, double za, double zb,
+                                            uint32_t k, uint32_t lo, uint32_t hi) {
+    const bool va = k >= lo && k < hi;
+    const bool vb = k + 1 >= lo && k + 1 < hi;
+    if (va && vb)
+        put<NT>(reinterpret_cast<global_ptr<u64x2>>(p), pair_bits<VarFP64, KIND>(za, zb));
+    else if (va)
+        put<NT>(p, out_bits<VarFP64, KIND>(za));
+    else if (vb)
+        put<NT>(p + 1, out_bits<VarFP64, KIND>(zb));
 }
 
-// Interleaved batch kernel: workgroup w takes batch rows w, w + G, ...;
-// while a lane's window continues its state moves G rows with JG,
-// otherwise it skips ahead afresh through the LDS tables.
-template <int KIND, bool NT, bool INDEXED>
-__global__ __launch_bounds__(256) void k_batch_il(BatchArgs a) {
-    __shared__ double t8[kSkip8Levels * kSkip8Size * 3];
-    for (uint32_t i = threadIdx.x; i < kSkip8Levels * kSkip8Size * 3; i += blockDim.x)
-        t8[i] = a.t8[i];
-    __syncthreads();
+// Stores one row of the interleaved kernel: lane l's outputs 2 (e B + l)
+// and 2 (e B + l) + 1, e < P (states z[2e], z[2e+1]; B = block), of the
+// row whose record info is `info`.  CHECK: the row may be partial (a
+// uniform test, then per-lane masks); otherwise it is known to lie wholly in
+// its window.
+template <int KIND, bool NT, bool CHECK, int P>
+__device__ __forceinline__ void store_rec(global_ptr<uint64_t> out, uint64_t info,
+                                          const double (&z)[2 * P], uint32_t l, uint32_t B) {
+    const uint32_t W = 2u * P * B;
+    const global_ptr<uint64_t> p = out + ((info & kRecIndexMask & ~(uint64_t)(W - 1)) + 2u * l);
+    if constexpr (CHECK) {
+        const uint32_t hi = (uint32_t)(info >> kRecHiShift);
+        const uint32_t lo = (uint32_t)info & (W - 1);
+        if (__builtin_expect(hi != W || lo != 0, 0)) {
+#pragma unroll
+            for (int e = 0; e < P; ++e)
+                put_pair_in<KIND, NT>(p + 2u * e * B, z[2 * e], z[2 * e + 1], 2u * (e * B + l),
+                                      lo, hi);
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e)
+        put<NT>(reinterpret_cast<global_ptr<u64x2>>(p + 2u * e * B),
+                pair_bits<VarFP64, KIND>(z[2 * e], z[2 * e + 1]));
+}
+
+// The states of lane l's outputs of the row whose element 0 has state `z0`.
+template <int P>
+__device__ __forceinline__ void row_states(double (&z)[2 * P], double z0, const Mult (&m)[2 * P]) {
+#pragma unroll
+    for (int e = 0; e < 2 * P; ++e) z[e] = VarFP64::mul(z0, m[e]);
+}
+
+// Lane k's 64-bit value, read by every lane (k uniform).  readlane yields
+// a signed int: each half goes through uint32_t so it is not sign-extended.
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, uint32_t k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
+    return (uint64_t)hi << 32 | lo;
+}
+
+// Lane k's record, read by every lane.
+__device__ __forceinline__ u64x2 lane_rec(u64x2 v, uint32_t k) {
+    u64x2 r;
+    r.x = lane_u64(v.x, k);
+    r.y = lane_u64(v.y, k);
+    return r;
+}
+
+// 64 rows whose records lane k of `mine` holds (row k): IL rows in flight,
+// each row stored IL rows after its multiplications.  CHECK: some of the
+// rows may be partial.
+template <int KIND, bool NT, bool CHECK, int P, int IL>
+__device__ __forceinline__ void rows64(global_ptr<uint64_t> out, u64x2 mine,
+                                       const Mult (&m)[2 * P], uint32_t l, uint32_t B) {
+    static_assert(64 % IL == 0, "rows in flight divide 64");
+    double z[IL][2 * P];
+    uint64_t info[IL];
+#pragma unroll
+    for (int j = 0; j < IL; ++j) {
+        const u64x2 R = lane_rec(mine, j);
+        row_states<P>(z[j], __builtin_bit_cast(double, R.x), m);
+        info[j] = R.y;
+    }
+    for (uint32_t k = IL; k < 64; k += IL) {
+#pragma unroll
+        for (int j = 0; j < IL; ++j) {
+            store_rec<KIND, NT, CHECK, P>(out, info[j], z[j], l, B);
+            const u64x2 R = lane_rec(mine, k + j);
+            row_states<P>(z[j], __builtin_bit_cast(double, R.x), m);
+            info[j] = R.y;
+            // keeps the products here: with CHECK the compiler would sink
+            // them to the branch of their store, IL rows on
+#pragma unroll
+            for (int e = 0; e < 2 * P; ++e) asm volatile("" ::"v"(z[j][e]));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < IL; ++j) store_rec<KIND, NT, CHECK, P>(out, info[j], z[j], l, B);
+}
+
+// Interleaved kernel: workgroup w takes rows w, w + G, ... (rows of
+// 2 P block outputs); a row's states come from its record and the lane's
+// fixed multipliers (2^53)^k for its outputs k, so rows depend on nothing
+// before them.  The records are staged in LDS kRecChunk at a time (all
+// loads of a chunk issued before one wait); the first chunk's length
+// differs between workgroups so that they do not all stop for their next
+// chunk at the same moment.  Lane j of each wavefront then holds the record
+// of row 64 g + j of group g, which every lane reads by readlane: groups of
+// 64 whole rows run branch-free.
+template <int KIND, bool NT, int P, int IL>
+__global__ __launch_bounds__(256) void k_batch_rows(BatchArgs a) {
+    constexpr uint32_t kLoads = 16;  // record loads per thread and round
+    __shared__ u64x2 s_rec[kRecChunk];
     const const_ptr<BatchHeader> hdr = as_const(a.ws);
     const uint64_t n_rows = hdr->n_rows;
     const global_ptr<uint64_t> out = as_global(hdr->out);
-    const const_ptr<BatchDesc> desc = reinterpret_cast<const_ptr<BatchDesc>>(hdr + 1);
-    const const_ptr<uint32_t> row_desc = as_const(a.row_desc);
-    const uint32_t B = blockDim.x;
     const uint32_t l = threadIdx.x;
+    const uint32_t B = blockDim.x;
+    const uint32_t W = 2u * P * B;
     const uint64_t G = gridDim.x;
-    uint32_t d_prev = 0xffffffffu;
-    BatchDesc D;
-    double za = 1.0, zb = 1.0;
-    for (uint64_t r = blockIdx.x; r < n_rows; r += G) {
-        const uint32_t d = row_desc[r];
-        const bool same = d == d_prev;
-        if (!same) D = load_desc(desc + d);
-        const uint32_t s = (uint32_t)(D.out_off & 1u);
-        const uint64_t xb = 2ull * ((r - D.row_start) * B + l) + 1 - s;
-        if (same) {
-            za = mm_fp64(za, a.JG.v, a.JG.qh, a.JG.ql);
-            zb = mm_fp64(zb, a.JG.v, a.JG.qh, a.JG.ql);
-        } else {
-            uint64_t src;
-            if constexpr (INDEXED)
-                src = as_const(hdr->states)[D.src];
-            else
-                src = D.src;
-            zb = skip8(src, D.pos + xb + 1, t8);
-            za = mm_fp64(zb, a.Minv.v, a.Minv.qh, a.Minv.ql);
-            d_prev = d;
+    const uint64_t w = blockIdx.x;
+    if (w >= n_rows) return;
+    const uint64_t per = (n_rows + G - 1) / G;
+    const uint64_t n_w = (n_rows - w + G - 1) / G;  // this workgroup's rows
+    const u64x2* __restrict__ rec = reinterpret_cast<const u64x2*>(a.rec) + w * per;
+    Mult m[2 * P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        m[2 * e] = a.t_lo[2u * (e * B + l)];
+        m[2 * e + 1] = a.t_lo[2u * (e * B + l) + 1];
+    }
+    uint32_t chunk = kRecChunk - (uint32_t)((w * 1543u) % (kRecChunk / 2));
+    for (uint64_t k0 = 0; k0 < n_w; k0 += chunk, chunk = kRecChunk) {
+        const uint32_t n = n_w - k0 < chunk ? (uint32_t)(n_w - k0) : chunk;
+        __syncthreads();  // every wave is done with the previous chunk
+        for (uint32_t base = 0; base < n; base += kLoads * B) {
+            u64x2 v[kLoads];
+#pragma unroll
+            for (uint32_t t = 0; t < kLoads; ++t) {
+                const uint32_t i = base + t * B + l;
+                v[t] = rec[k0 + (i < n ? i : 0)];
+            }
+#pragma unroll
+            for (uint32_t t = 0; t < kLoads; ++t) {
+                const uint32_t i = base + t * B + l;
+                if (i < n) s_rec[i] = v[t];
+            }
         }
-        const uint64_t jr = r - D.row_start;
-        const bool full = (jr > 0 || s == 0) && 2ull * (jr + 1) * B - s <= D.len;
-        store_pair<VarFP64, KIND, NT>(out, D, xb, za, zb, full);
+        __syncthreads();
+        for (uint32_t i0 = 0; i0 < n; i0 += 64) {
+            const u64x2 mine = s_rec[(i0 + (l & 63u)) & (kRecChunk - 1)];
+            const uint32_t g = n - i0 < 64 ? n - i0 : 64;
+            if (g == 64) {
+                const bool full =
+                    (uint32_t)(mine.y >> kRecHiShift) == W && (mine.y & (W - 1)) == 0;
+                if (__ballot(!full) == 0)
+                    rows64<KIND, NT, false, P, IL>(out, mine, m, l, B);
+                else
+                    rows64<KIND, NT, true, P, IL>(out, mine, m, l, B);
+                continue;
+            }
+            for (uint32_t k = 0; k < g; ++k) {
+                const u64x2 R = lane_rec(mine, k);
+                double z[2 * P];
+                row_states<P>(z, __builtin_bit_cast(double, R.x), m);
+                store_rec<KIND, NT, true, P>(out, R.y, z, l, B);
+            }
+        }
     }
 }
 
@@ -387,17 +532,18 @@ hipError_t launch_queue(int kind, uint32_t grid, uint32_t block, hipStream_t s,
     return hipGetLastError();
 }
 
-const void* batch_map_kernel() { return reinterpret_cast<const void*>(&k_batch_map); }
-
-template <int KIND, bool NT>
-static const void* il_kn(bool indexed) {
-    return indexed ? reinterpret_cast<const void*>(&k_batch_il<KIND, NT, true>)
-                   : reinterpret_cast<const void*>(&k_batch_il<KIND, NT, false>);
+const void* batch_rec_kernel(bool indexed) {
+    return indexed ? reinterpret_cast<const void*>(&k_batch_rec<true>)
+                   : reinterpret_cast<const void*>(&k_batch_rec<false>);
 }
 
-const void* batch_il_kernel(int kind, bool nt, bool indexed) {
-    if (kind == 0) return nt ? il_kn<0, true>(indexed) : il_kn<0, false>(indexed);
-    return nt ? il_kn<1, true>(indexed) : il_kn<1, false>(indexed);
+const void* batch_rows_kernel(int kind, bool nt) {
+    constexpr int P = kIlPairs, IL = kIlRows;
+    if (kind == 0)
+        return nt ? reinterpret_cast<const void*>(&k_batch_rows<0, true, P, IL>)
+                  : reinterpret_cast<const void*>(&k_batch_rows<0, false, P, IL>);
+    return nt ? reinterpret_cast<const void*>(&k_batch_rows<1, true, P, IL>)
+              : reinterpret_cast<const void*>(&k_batch_rows<1, false, P, IL>);
 }
 
 template <class V, int KIND, bool NT>

@@ -48,13 +48,36 @@ constexpr uint32_t kSkipBits = 13;
 constexpr uint32_t kSkipSize = 1u << kSkipBits;
 constexpr uint32_t kSkipLevels = 4;
 
-// Interleaved kernel (FP64 reduction): skip tables of 8 bits per level held
-// in LDS, t8[lvl][j] = (2^53)^(j * 2^(8 lvl)), lvl < 7 (2^56 > the period),
-// three doubles (v, qh, ql) per entry.
+// The device-side API's skip tables (nn_dev_skip_table): 8 bits per level,
+// t8[lvl][j] = (2^53)^(j * 2^(8 lvl)), lvl < 7 (2^56 > the period), three
+// doubles (v, qh, ql) per entry.
 constexpr uint32_t kSkip8Levels = NN_DEV_SKIP_LEVELS;
 constexpr uint32_t kSkip8Size = NN_DEV_SKIP_SIZE;
 static_assert(kSkip8Levels == 7 && kSkip8Size == 256, "8-bit levels covering 2^56");
 static_assert(sizeof(nn_dev_mult) == 3 * sizeof(double), "t8 entries are nn_dev_mult");
+
+// Interleaved kernel: rows of 2*kIlPairs*block outputs, lane l owning the
+// pairs 2 (e block + l), 2 (e block + l) + 1, e < kIlPairs (each store of
+// a wavefront is 1 KiB contiguous), kIlRows rows in flight per lane.
+constexpr uint32_t kIlPairs = 1;
+constexpr uint32_t kIlRows = 4;
+// One record per batch row, written by a pre-pass.
+// Element k of a row (k < W = 2*kIlPairs*block) has
+// the state z * (2^53)^k and goes to output index g + k, and it belongs to
+// the row's window iff lo <= k < hi.  Rows are aligned to the output (g is
+// a multiple of W), so lo < W fits below g.
+struct RowRec {
+    double z;       // state of the row's element 0
+    uint64_t info;  // g | lo | hi << 52
+};
+static_assert(sizeof(RowRec) == 16, "one 16-byte record per row");
+constexpr uint64_t kRecIndexMask = (1ull << 52) - 1;  // g | lo
+constexpr uint32_t kRecHiShift = 52;
+// Records are stored workgroup-major: row r at (r % grid) * per + r / grid
+// with per = ceil(n_rows / grid), so the workgroup that writes rows r = w,
+// w + grid, ... reads its records as one contiguous run, kRecChunk at a time
+// through LDS.
+constexpr uint32_t kRecChunk = 4096;
 
 // Kernel arguments (fixed for the life of a plan).
 struct BatchArgs {
@@ -67,16 +90,18 @@ struct BatchArgs {
     const Mult* t_hi;
     const Mult* t_sk;       // kSkipLevels * kSkipSize entries
     // Interleaved kernel only:
-    Mult JG;                // (2^53)^(2*block*grid): the same lane G rows later
-    const double* t8;       // kSkip8Levels * kSkip8Size * 3 doubles
-    uint32_t* row_desc;     // per batch row: its window (device workspace)
+    RowRec* rec;            // row records (device workspace)
+    Mult JR;                // (2^53)^(row_outs*256): a pre-pass thread's next row
+    uint32_t grid;          // workgroups of the row kernel
+    uint32_t block;         // threads per workgroup of the row kernel
+    uint32_t row_outs;      // outputs per row (2*kIlPairs*block, a power of two)
 };
 
-// Interleaved kernels: row_desc[r] = the window of batch row r (pre-pass),
-// then workgroup w takes rows w, w + grid, ... (one write front, as the
-// plain row layout).  FP64 reduction only.
-const void* batch_map_kernel();
-const void* batch_il_kernel(int kind, bool nontemporal, bool indexed);
+// Interleaved kernels (FP64 reduction, block <= 256): the pre-pass writes
+// every row's record, then workgroup w of the row kernel takes rows w,
+// w + grid, ... (one write front, as the plain row layout).
+const void* batch_rec_kernel(bool indexed);
+const void* batch_rows_kernel(int kind, bool nontemporal);
 
 // The kernel entry for (mulmod, kind, nontemporal, indexed); its single
 // parameter is a BatchArgs passed by value.

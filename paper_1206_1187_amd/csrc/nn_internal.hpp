@@ -43,14 +43,14 @@ constexpr uint32_t kDefaultBlock = 256;
 
 // A batch plan: two slots, each a device workspace, a pinned staging copy
 // of it and a graph of the batch kernel (with the interleaved kernel's
-// row-map pre-pass before it).  Batches alternate between the slots, so the
+// row-record pre-pass before it).  Batches alternate between the slots, so the
 // host prepares batch i+1 while batch i runs; a slot is reused only after
 // the batch that last used it has finished.
 struct nn_batch_slot {
     size_t ws_bytes = 0;
     void* ws_dev = nullptr;
     void* ws_host = nullptr;      // pinned staging, same layout as ws_dev
-    uint32_t* row_map = nullptr;  // device, cap_rows entries (interleaved kernel)
+    nn::RowRec* rec = nullptr;    // device, cap_rows + grid row records (interleaved)
     hipEvent_t done = nullptr;
     bool pending = false;
     hipGraph_t graph = nullptr;

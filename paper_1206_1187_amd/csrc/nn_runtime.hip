@@ -189,7 +189,7 @@ void plan_release(nn_batch_plan* p) {
         if (q.exec) (void)hipGraphExecDestroy(q.exec);
         if (q.graph) (void)hipGraphDestroy(q.graph);
         if (q.ws_dev) (void)hipFree(q.ws_dev);
-        if (q.row_map) (void)hipFree(q.row_map);
+        if (q.rec) (void)hipFree(q.rec);
         if (q.ws_host) (void)hipHostFree(q.ws_host);
     }
     delete p;
@@ -202,8 +202,8 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
                 const uint64_t* states) {
     q.ws_bytes = sizeof(BatchHeader) + (size_t)p->cap_desc * sizeof(BatchDesc);
     hipError_t e = hipMalloc(&q.ws_dev, q.ws_bytes);
-    if (e == hipSuccess && p->interleaved)
-        e = hipMalloc((void**)&q.row_map, p->cap_rows * sizeof(uint32_t));
+    if (e == hipSuccess && p->interleaved)  // records are padded to grid * ceil(rows / grid)
+        e = hipMalloc((void**)&q.rec, (p->cap_rows + p->grid) * sizeof(RowRec));
     if (e != hipSuccess)
         return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", q.ws_bytes, hipGetErrorString(e));
     e = hipHostMalloc(&q.ws_host, q.ws_bytes, hipHostMallocDefault);
@@ -223,9 +223,11 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     q.args.t_lo = d.t_lo;
     q.args.t_hi = d.t_hi;
     q.args.t_sk = d.t_sk;
-    q.args.JG = make_mult(MultPowers::get().pow(2ull * block * p->grid));
-    q.args.t8 = d.t8;
-    q.args.row_desc = q.row_map;
+    q.args.rec = q.rec;
+    q.args.row_outs = 2u * kIlPairs * block;
+    q.args.JR = make_mult(MultPowers::get().pow((uint64_t)q.args.row_outs * 256));
+    q.args.grid = p->grid;
+    q.args.block = block;
     if (!p->use_graph) return NN_OK;
     // The graph holds the kernels; the descriptor upload before each replay
     // is an ordinary async copy on the same stream (a copy node from pinned
@@ -236,7 +238,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     if (e == hipSuccess && p->interleaved) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
-        kp.func = const_cast<void*>(batch_map_kernel());
+        kp.func = const_cast<void*>(batch_rec_kernel(p->indexed));
         kp.gridDim = dim3(p->map_grid);
         kp.blockDim = dim3(256);
         kp.kernelParams = params;
@@ -246,7 +248,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
         kp.func = p->interleaved
-                      ? const_cast<void*>(batch_il_kernel(p->kind, p->nontemporal, p->indexed))
+                      ? const_cast<void*>(batch_rows_kernel(p->kind, p->nontemporal))
                       : const_cast<void*>(
                             batch_kernel((int)p->mulmod, p->kind, p->nontemporal, p->indexed));
         kp.gridDim = dim3(p->grid);
@@ -309,10 +311,12 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
     p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
     p->interleaved = (c.flags & NN_BATCH_INTERLEAVED) != 0;
-    if (p->interleaved && (mulmod != NN_MULMOD_FP64 || block > 256 || cluster != 1)) {
+    if (p->interleaved &&
+        (mulmod != NN_MULMOD_FP64 || (block & (block - 1)) || block > 256 ||
+         cluster != 1)) {
         plan_release(p);
         return fail(NN_EINVAL, "the interleaved batch kernel needs the FP64 reduction, "
-                    "block <= 256 and cluster 1");
+                    "block 64, 128 or 256 and cluster 1");
     }
     p->cluster = cluster;
     p->cap_rows = max_outputs / (2ull * block) + 2 * cap_desc;
@@ -355,13 +359,19 @@ bool plan_idle(nn_batch_plan* p) {
 
 int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t stream) {
     nn_batch_slot& q = p->slot[p->next];
-    const uint64_t row = 2ull * p->block;
+    const uint64_t row = (p->interleaved ? 2ull * kIlPairs : 2ull) * p->block;
     BatchHeader* hdr = (BatchHeader*)q.ws_host;
     BatchDesc* dd = plan_staged_descs(p);
     uint64_t rows = 0;
     for (uint32_t k = 0; k < nd; ++k) {
         dd[k].row_start = rows;
-        rows += (dd[k].len + (dd[k].out_off & 1u) + row - 1) / row;
+        // rows aligned to output pairs (blocked kernel) or to whole rows
+        // of the output (interleaved kernel)
+        const uint64_t s = dd[k].out_off & (p->interleaved ? row - 1 : 1u);
+        rows += (dd[k].len + s + row - 1) / row;
+        // row records hold output indices in 52 bits
+        if (p->interleaved && dd[k].out_off + dd[k].len > (1ull << 51))
+            return fail(NN_ERANGE, "interleaved batches take output indices below 2^51");
     }
     if (p->interleaved && rows > p->cap_rows)
         return fail(NN_ERANGE, "batch of %llu rows, plan holds %llu", (unsigned long long)rows,
@@ -392,11 +402,11 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         BatchArgs copy = q.args;
         void* params[] = {&copy};
         if (p->interleaved) {
-            e = hipLaunchKernel(batch_map_kernel(), dim3(p->map_grid), dim3(256), params, 0,
-                                stream);
+            e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(p->map_grid), dim3(256),
+                                params, 0, stream);
             if (e == hipSuccess)
-                e = hipLaunchKernel(batch_il_kernel(p->kind, p->nontemporal, p->indexed),
-                                    dim3(p->grid), dim3(p->block), params, 0, stream);
+                e = hipLaunchKernel(batch_rows_kernel(p->kind, p->nontemporal), dim3(p->grid),
+                                    dim3(p->block), params, 0, stream);
         } else {
             e = launch_batch((int)p->mulmod, p->kind, p->nontemporal, p->indexed, p->grid,
                              p->block, stream, q.args);

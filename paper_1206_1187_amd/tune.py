@@ -134,6 +134,8 @@ def tune_batch(kind, reps=5, log=print, workload=None):
     shapes = [dict(mulmod=m, block=b, cluster=k, temporal=t) for m in ("fp64", "shoup")
               for b in (256, 512) for k in (1, 4, 8, 16) for t in (False, True)]
     shapes += [dict(mulmod=m, block=256, cluster=8) for m in ("barrett", "montgomery")]
+    shapes += [dict(mulmod="fp64", block=b, cluster=1, temporal=t, interleaved=True)
+               for b in (128, 256) for t in (False, True)]
     for shape, grid in itertools.product(shapes, grids):
         if grid % shape["cluster"]:
             continue

@@ -1,5 +1,6 @@
 """GPU parity of the batched form (nn_generate_batch) against the oracle,
 and against the plain path stream by stream.  Bit-exact throughout."""
+import ctypes
 import sys
 
 import numpy as np
@@ -79,8 +80,8 @@ def test_batch_bit_exact_mixed_lengths(kind, mulmod, interleaved):
     for block, grid, cluster, graph in [(256, 0, 0, True), (64, 3, 1, False), (1024, 7, 1, True),
                                         (128, 1, 1, True), (64, 1000, 8, True),
                                         (256, 4096, 4, True), (128, 12, 3, True),
-                                        (256, 64, 64, False)]:
-        if interleaved and (block > 256 or cluster > 1):
+                                        (256, 64, 64, False), (512, 5, 1, True)]:
+        if interleaved and (block not in (64, 128, 256) or cluster > 1):
             continue
         _say("batch", kind, mulmod, interleaved, block, grid, cluster, graph)
         buf = _sentinel(total)
@@ -196,17 +197,18 @@ def test_skip_stress_full_as_one_batch():
         assert np.array_equal(got[i], ref.view(np.uint64)), (i, o)
 
 
-def test_batched_workload_full_size_sampled():
-    """Config 4 at full size (10,000 streams, 2.7e9 outputs) in the bench's
-    plan configuration: every stream's first and last 64 outputs, and 400
-    whole streams, against the oracle."""
+@pytest.mark.parametrize("interleaved", [False, True])
+def test_batched_workload_full_size_sampled(interleaved):
+    """Config 4 at full size (10,000 streams, 2.7e9 outputs), both batch
+    kernels at their default shapes: every stream's first and last 64
+    outputs, and 400 whole streams, against the oracle."""
     case = wl.batched()
     states = np.array([orc.seed(int(a)) for a in case.indices], dtype=np.uint64)
     lengths = case.lengths
     offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
     total = int(lengths.sum())
     out = torch.empty(total, dtype=torch.float64, device="cuda")
-    with nn.BatchPlan("f64", len(states), total) as plan:
+    with nn.BatchPlan("f64", len(states), total, interleaved=interleaved) as plan:
         _say("batched full", plan.cfg().as_dict(), total)
         fin = plan.generate(states, lengths, offsets, out, final_states=True)
     torch.cuda.synchronize()
@@ -293,8 +295,9 @@ def test_batch_offsets_beyond_32_bit_indexing():
     total = offsets[2] + lengths[2] + 16
     states = [orc.seed(wl.INDEX_MIN + 31 * i) for i in range(4)]
     out = torch.empty(total, dtype=torch.uint64, device="cuda")
-    for graph in (True, False):
-        with nn.BatchPlan("u64", 32, total, graph=graph) as plan:
+    for graph, il in ((True, False), (False, False), (True, True)):
+        _say("beyond 2^32", "graph" if graph else "direct", "interleaved" if il else "blocked")
+        with nn.BatchPlan("u64", 32, total, graph=graph, interleaved=il) as plan:
             plan.generate(states, lengths, offsets, out)
             torch.cuda.synchronize()
         flat = out.view(torch.int64)
@@ -307,7 +310,7 @@ def test_batch_offsets_beyond_32_bit_indexing():
         st2 = states * 5
         ln2 = [64] * 20
         of2 = [base + 128 * i + (i & 1) for i in range(20)]
-        with nn.BatchPlan("u64", 32, total, graph=graph) as plan:
+        with nn.BatchPlan("u64", 32, total, graph=graph, interleaved=il) as plan:
             plan.generate(st2, ln2, of2, out)
             torch.cuda.synchronize()
         for s, o in zip(st2, of2):
@@ -316,3 +319,43 @@ def test_batch_offsets_beyond_32_bit_indexing():
             assert np.array_equal(got, ref), o
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("grid", [1, 3])
+def test_interleaved_record_chunks(grid):
+    """The interleaved kernel stages row records in LDS 4096 at a time (the
+    first chunk shorter on most workgroups): workgroups with well over 4096
+    rows, windows at both offset parities, against the oracle."""
+    rng = np.random.default_rng(40 + grid)
+    lengths = [int(x) for x in rng.integers(1, 100_000, 90)] + [300_001]
+    states, lengths, offsets, total = _mixed_batch(41 + grid, lengths)
+    buf = _sentinel(total)
+    with nn.BatchPlan("f64", 128, total, block=64, grid=grid, interleaved=True) as plan:
+        rows = sum((int(n) + (int(o) % 128) + 127) // 128 for n, o in zip(lengths, offsets))
+        _say("interleaved chunks", grid, "rows", rows)
+        assert rows // grid > 2 * 4096
+        plan.generate(states, lengths, offsets, buf.view(torch.float64))
+        torch.cuda.synchronize()
+    _check_batch(_bits(buf), states, lengths, offsets, "f64")
+
+
+def test_interleaved_output_index_limit():
+    """The interleaved kernel's shapes (FP64, block 64, 128 or 256, no clusters),
+    and its row records' 52-bit output indices: windows reaching past 2^51
+    elements are refused before anything is enqueued."""
+    good = orc.seed(wl.INDEX_MIN)
+    out = _sentinel(64)
+    from paper_1206_1187_amd import _native
+    for bad in (dict(block=192), dict(block=512), dict(mulmod="shoup"), dict(cluster=2)):
+        with pytest.raises(nn.NNError):
+            nn.BatchPlan("f64", 2, 1 << 20, interleaved=True, **bad)
+    with nn.BatchPlan("f64", 2, 1 << 20, interleaved=True) as plan:
+        # through the C ABI: the binding already refuses windows past its tensor
+        descs = (_native.StreamDesc * 2)((good, 10, 0), (good, 10, (1 << 51) - 5))
+        rc = _native.lib().nn_generate_batch(plan._h, ctypes.cast(descs, ctypes.c_void_p), 2,
+                                             ctypes.c_void_p(out.data_ptr()), None, None)
+        assert rc == _native.NN_ERANGE
+        plan.generate([good], [64], [0], out.view(torch.float64))
+        torch.cuda.synchronize()
+    ref, _ = orc.gen(good, 64, "f64")
+    assert np.array_equal(_bits(out), ref.view(np.uint64))

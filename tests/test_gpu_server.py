@@ -37,13 +37,18 @@ def _device():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("kind", ["f64", "u64"])
-def test_served_requests_equal_oracle_and_plain_alone(kind):
+@pytest.mark.parametrize("kind,interleaved", [("f64", False), ("u64", False), ("f64", True),
+                                              ("u64", True)])
+def test_served_requests_equal_oracle_and_plain_alone(kind, interleaved):
+    """Both batch kernels in the server's indexed mode (states read from the
+    device table)."""
+    _say("served", kind, "interleaved" if interleaved else "blocked")
     states = _states(8, 21)
     rng = np.random.default_rng(22)
     reqs = [(int(rng.integers(0, 8)), int(np.floor(np.exp(rng.uniform(0, np.log(1 << 18))))))
             for _ in range(300)] + [(3, 0), (5, 1), (5, (1 << 20) + 3)]
-    with serve.Server(states, 1 << 28, kind=kind, lanes=3, max_batch_requests=32) as srv:
+    with serve.Server(states, 1 << 28, kind=kind, lanes=3, max_batch_requests=32,
+                      interleaved=interleaved, **({"block": 128} if interleaved else {})) as srv:
         tickets = [srv.submit(s, n) for s, n in reqs]
         done = {}
         while len(done) < len(reqs):
