@@ -102,6 +102,12 @@ def batched_leg(nn, torch):
         for _ in range(3):
             plan.generate(states, lengths, offsets, out)
         direct_s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 10, torch)
+    # the interleaved kernel (per-row records, one write front) beside it
+    with nn.BatchPlan("f64", len(states), total, block=256, grid=128, interleaved=True) as plan:
+        for _ in range(3):
+            plan.generate(states, lengths, offsets, out)
+        res["interleaved_ms"] = _timed_kernel(
+            lambda: plan.generate(states, lengths, offsets, out), 10, torch) * 1e3
     res["graph_ms"] = graph_s * 1e3
     res["no_graph_ms"] = direct_s * 1e3
     res["variates_per_s"] = total / graph_s
@@ -341,6 +347,23 @@ def main():
         extras["f64_frac_of_write_ceiling"] = achieved / ceiling
         # Paper's Table 2: generation time net of the store time.
         extras["net_generation_ms"] = (f64_s - min(fill_s, flat_s)) * 1e3
+        # Paper's Table 1, execution vs including setup: the host seeding of
+        # Eq. 2 (a 106-bit power modulo 3^33 from the index), the launch
+        # constants and the launch, then the kernel, timed on the host clock
+        # from the index to the synchronised result.
+        t_seed = time.perf_counter()
+        for _ in range(10000):
+            nn.seed(case.index)
+        extras["seed_host_us"] = (time.perf_counter() - t_seed) / 10000 * 1e6
+        walls = []
+        for _ in range(10):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nn.generate_into(nn.seed(case.index), out_f)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        extras["f64_kernel_ms"] = f64_s * 1e3
+        extras["f64_including_setup_ms"] = sorted(walls)[len(walls) // 2] * 1e3
         # Fused consumer: the same generation summed in registers (no stores),
         # the analogue of the paper's Table 2 net generation rate.
         res = torch.zeros(1, dtype=torch.int64, device="cuda")
