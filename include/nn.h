@@ -240,7 +240,8 @@ typedef struct nn_stream_desc {
  * its members take every cluster-th row of it (cluster 1: each workgroup a
  * contiguous range).
  * block: threads per workgroup (a multiple of 64 in [64,1024]); grid:
- * workgroups (a multiple of cluster); cluster: 1..64; mulmod: an
+ * workgroups (a multiple of cluster); cluster: 1..64 (interleaved: up to
+ * grid; 0 = grid); mulmod: an
  * nn_mulmod; flags: NN_CFG_TEMPORAL_STORES, NN_BATCH_NO_GRAPH (enqueue a
  * copy and a kernel launch instead of replaying the plan's graph),
  * NN_BATCH_INTERLEAVED. */
@@ -252,14 +253,16 @@ typedef struct nn_batch_cfg {
     uint32_t flags;
 } nn_batch_cfg;
 #define NN_BATCH_NO_GRAPH 8u
-/* Interleave rows over all workgroups: a pre-pass writes one record per
- * row of 2*block outputs (its first state and output index; rows aligned to
- * the output), then workgroup w writes rows w, w + grid, ..., so all
- * workgroups write one region of the output at a time, as the plain
- * generator does.  Needs the FP64 reduction, block 64, 128 or 256, cluster
- * 1, and output indices below 2^51 (NN_ERANGE otherwise).  Measured on
- * MI355X: ahead of the default on batches of few long streams, 3-4 %
- * behind it on 10,000 streams of mixed lengths. */
+/* Interleaved kernel: a pre-pass writes one record per row of 2*block
+ * outputs (its first state and output index; rows aligned to the output),
+ * so a workgroup enters a stream at no cost and rows can be dealt out
+ * freely: clusters of `cluster` consecutive workgroups take contiguous
+ * ranges of rows and interleave them (cluster 0: one range for all, i.e.
+ * workgroup w writes rows w, w + grid, ..., one region of the output at a
+ * time, as the plain generator does).  Needs the FP64 reduction, block 64,
+ * 128 or 256, a grid that cluster divides, and output indices below 2^51
+ * (NN_ERANGE otherwise).  Batches of at most 16 windows travel in the
+ * kernel arguments and run the blocked kernel in either case. */
 #define NN_BATCH_INTERLEAVED 16u
 
 /* Opaque batch plan: device workspace, pinned staging and a hipGraph of

@@ -198,7 +198,8 @@ __global__ __launch_bounds__(1024) void k_batch_inline(BatchArgs a, BatchInline 
     batch_body<V, KIND, NT, INDEXED>(a, as_const(&in.hdr));
 }
 
-// Pre-pass of the interleaved kernel: every row's record.  Its rows are
+// Pre-pass of the interleaved kernel: every row's record, stored where its
+// workgroup of the row kernel reads it.  Its rows are
 // aligned to the output: row j of a window at output offset o covers
 // outputs [W (floor(o / W) + j), W (floor(o / W) + j + 1)), W = 2*kIlPairs*block,
 // which are its elements W j - s + k, k < W, with s = o mod W.  (Adjacent
@@ -212,8 +213,10 @@ __global__ __launch_bounds__(256) void k_batch_rec(BatchArgs a) {
     const uint32_t n_desc = hdr->n_desc;
     const uint64_t n_rows = hdr->n_rows;
     const const_ptr<BatchDesc> desc = reinterpret_cast<const_ptr<BatchDesc>>(hdr + 1);
-    const uint64_t G = a.grid;
-    const uint64_t per = (n_rows + G - 1) / G;
+    // row r -> cluster c = r / Rc, member (r - c Rc) mod K, its row (r - c Rc) / K
+    const uint64_t K = a.cluster, C = a.grid / a.cluster;
+    const uint64_t Rc = (n_rows + C - 1) / C;
+    const uint64_t per = (Rc + K - 1) / K;
     const uint64_t W = a.row_outs;  // outputs per row, a power of two
     const global_ptr<u64x2> rec = reinterpret_cast<global_ptr<u64x2>>(as_global(a.rec));
     for (uint32_t d = blockIdx.x; d < n_desc; d += gridDim.x) {
@@ -239,7 +242,8 @@ __global__ __launch_bounds__(256) void k_batch_rec(BatchArgs a) {
             u64x2 R;  // a RowRec
             R.x = __builtin_bit_cast(uint64_t, z);
             R.y = (D.out_off - s + first) | (j == 0 ? s : 0) | (hi << kRecHiShift);
-            rec[(r % G) * per + r / G] = R;
+            const uint64_t c = r / Rc, o = r - c * Rc;
+            rec[(c * K + o % K) * per + o / K] = R;
             z = VarFP64::mul(z, a.JR);
         }
     }
@@ -343,8 +347,10 @@ __device__ __forceinline__ void rows64(global_ptr<uint64_t> out, u64x2 mine,
     for (int j = 0; j < IL; ++j) store_rec<KIND, NT, CHECK, P>(out, info[j], z[j], l, B);
 }
 
-// Interleaved kernel: workgroup w takes rows w, w + G, ... (rows of
-// 2 P block outputs); a row's states come from its record and the lane's
+// Interleaved kernel: clusters of K = cluster consecutive workgroups take
+// contiguous ranges of rows (of 2 P block outputs), and member i of a
+// cluster takes rows i, i + K, ... of its range (K = grid: workgroup w takes
+// rows w, w + grid, ...).  A row's states come from its record and the lane's
 // fixed multipliers (2^53)^k for its outputs k, so rows depend on nothing
 // before them.  The records are staged in LDS kRecChunk at a time (all
 // loads of a chunk issued before one wait); the first chunk's length
@@ -362,11 +368,16 @@ __global__ __launch_bounds__(256) void k_batch_rows(BatchArgs a) {
     const uint32_t l = threadIdx.x;
     const uint32_t B = blockDim.x;
     const uint32_t W = 2u * P * B;
-    const uint64_t G = gridDim.x;
     const uint64_t w = blockIdx.x;
-    if (w >= n_rows) return;
-    const uint64_t per = (n_rows + G - 1) / G;
-    const uint64_t n_w = (n_rows - w + G - 1) / G;  // this workgroup's rows
+    // member w mod K of cluster w / K: rows r0 + i, r0 + i + K, ... of the
+    // cluster's range [r0, r_end)
+    const uint64_t K = a.cluster, C = gridDim.x / a.cluster;
+    const uint64_t Rc = (n_rows + C - 1) / C;
+    const uint64_t per = (Rc + K - 1) / K;
+    const uint64_t r0 = (w / K) * Rc, i = w % K;
+    const uint64_t r_end = r0 + Rc < n_rows ? r0 + Rc : n_rows;
+    if (r0 + i >= r_end) return;
+    const uint64_t n_w = (r_end - r0 - i + K - 1) / K;  // this workgroup's rows
     const u64x2* __restrict__ rec = reinterpret_cast<const u64x2*>(a.rec) + w * per;
     Mult m[2 * P];
 #pragma unroll

@@ -73,16 +73,16 @@ struct RowRec {
 static_assert(sizeof(RowRec) == 16, "one 16-byte record per row");
 constexpr uint64_t kRecIndexMask = (1ull << 52) - 1;  // g | lo
 constexpr uint32_t kRecHiShift = 52;
-// Records are stored workgroup-major: row r at (r % grid) * per + r / grid
-// with per = ceil(n_rows / grid), so the workgroup that writes rows r = w,
-// w + grid, ... reads its records as one contiguous run, kRecChunk at a time
+// Records are stored workgroup-major: each workgroup of the row kernel reads
+// the records of its rows as one contiguous run (per = ceil(ceil(n_rows / C)
+// / K) of them, C = grid / K clusters of K workgroups), kRecChunk at a time
 // through LDS.
 constexpr uint32_t kRecChunk = 4096;
 
 // Kernel arguments (fixed for the life of a plan).
 struct BatchArgs {
     const BatchHeader* ws;  // device workspace
-    uint32_t cluster;       // workgroups sharing a row range (blocked kernel)
+    uint32_t cluster;       // workgroups sharing a row range
     Mult JB;                // (2^53)^(2*block*cluster): the next row of a lane
     Mult JB2;               // (2^53)^(4*block*cluster): two such rows
     Mult Minv;              // (2^53)^-1

@@ -202,8 +202,8 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
                 const uint64_t* states) {
     q.ws_bytes = sizeof(BatchHeader) + (size_t)p->cap_desc * sizeof(BatchDesc);
     hipError_t e = hipMalloc(&q.ws_dev, q.ws_bytes);
-    if (e == hipSuccess && p->interleaved)  // records are padded to grid * ceil(rows / grid)
-        e = hipMalloc((void**)&q.rec, (p->cap_rows + p->grid) * sizeof(RowRec));
+    if (e == hipSuccess && p->interleaved)  // grid * per <= rows + clusters + grid records
+        e = hipMalloc((void**)&q.rec, (p->cap_rows + 2ull * p->grid) * sizeof(RowRec));
     if (e != hipSuccess)
         return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", q.ws_bytes, hipGetErrorString(e));
     e = hipHostMalloc(&q.ws_host, q.ws_bytes, hipHostMallocDefault);
@@ -282,8 +282,9 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     const uint32_t block = c.block ? c.block : kDefaultBlock;
     if (block < 64 || block > 1024 || block % 64)
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
-    const uint32_t cluster = c.cluster ? c.cluster : 1;
-    if (cluster > 64) return fail(NN_EINVAL, "cluster %u: at most 64", cluster);
+    const bool interleaved = (c.flags & NN_BATCH_INTERLEAVED) != 0;
+    uint32_t cluster = c.cluster ? c.cluster : 1;
+    if (cluster > 64 && !interleaved) return fail(NN_EINVAL, "cluster %u: at most 64", cluster);
     const uint32_t mulmod = c.mulmod ? c.mulmod : kd.mulmod;
     if (mulmod > NN_MULMOD_MONTGOMERY)
         return fail(NN_EINVAL, "mulmod %u: batches take FP64, Barrett, Shoup or Montgomery",
@@ -294,6 +295,7 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
         if (!grid) grid = 1;
     }
     if (!c.grid) grid = (grid + cluster - 1) / cluster * cluster;
+    if (interleaved && !c.cluster) cluster = grid;  // one range: all workgroups interleave
     if (grid > (1u << 20)) return fail(NN_EINVAL, "grid %u too large", grid);
     if (grid % cluster) return fail(NN_EINVAL, "grid %u is not a multiple of cluster %u", grid, cluster);
     // Direct batches split streams into pieces of at most kBatchMaxLen.
@@ -312,11 +314,10 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
     p->interleaved = (c.flags & NN_BATCH_INTERLEAVED) != 0;
     if (p->interleaved &&
-        (mulmod != NN_MULMOD_FP64 || (block & (block - 1)) || block > 256 ||
-         cluster != 1)) {
+        (mulmod != NN_MULMOD_FP64 || (block & (block - 1)) || block > 256)) {
         plan_release(p);
-        return fail(NN_EINVAL, "the interleaved batch kernel needs the FP64 reduction, "
-                    "block 64, 128 or 256 and cluster 1");
+        return fail(NN_EINVAL, "the interleaved batch kernel needs the FP64 reduction and "
+                    "block 64, 128 or 256");
     }
     p->cluster = cluster;
     p->cap_rows = max_outputs / (2ull * block) + 2 * cap_desc;
@@ -359,7 +360,12 @@ bool plan_idle(nn_batch_plan* p) {
 
 int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t stream) {
     nn_batch_slot& q = p->slot[p->next];
-    const uint64_t row = (p->interleaved ? 2ull * kIlPairs : 2ull) * p->block;
+    // A small batch travels in the kernel arguments (no upload to wait for)
+    // and runs the blocked kernel whichever kernel the plan has; larger ones
+    // of an interleaved plan run its pre-pass and row kernel.
+    const bool in_args = nd <= kInlineDescs;
+    const bool il = p->interleaved && !in_args;
+    const uint64_t row = (il ? 2ull * kIlPairs : 2ull) * p->block;
     BatchHeader* hdr = (BatchHeader*)q.ws_host;
     BatchDesc* dd = plan_staged_descs(p);
     uint64_t rows = 0;
@@ -367,13 +373,13 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         dd[k].row_start = rows;
         // rows aligned to output pairs (blocked kernel) or to whole rows
         // of the output (interleaved kernel)
-        const uint64_t s = dd[k].out_off & (p->interleaved ? row - 1 : 1u);
+        const uint64_t s = dd[k].out_off & (il ? row - 1 : 1u);
         rows += (dd[k].len + s + row - 1) / row;
         // row records hold output indices in 52 bits
-        if (p->interleaved && dd[k].out_off + dd[k].len > (1ull << 51))
+        if (il && dd[k].out_off + dd[k].len > (1ull << 51))
             return fail(NN_ERANGE, "interleaved batches take output indices below 2^51");
     }
-    if (p->interleaved && rows > p->cap_rows)
+    if (il && rows > p->cap_rows)
         return fail(NN_ERANGE, "batch of %llu rows, plan holds %llu", (unsigned long long)rows,
                     (unsigned long long)p->cap_rows);
     hdr->out = (uint64_t*)out;
@@ -381,8 +387,7 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     hdr->n_rows = rows;
     const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc);
     hipError_t e;
-    if (nd <= kInlineDescs && !p->interleaved) {
-        // A small batch travels in the kernel arguments: no upload to wait for.
+    if (in_args) {
         BatchInline in;
         memset(&in, 0, sizeof in);
         memcpy(&in, q.ws_host, bytes);

@@ -130,14 +130,15 @@ def tune_batch(kind, reps=5, log=print, workload=None):
     dt = torch.float64 if kind == "f64" else torch.uint64
     out = torch.empty(total, dtype=dt, device="cuda")
     results = []
-    grids = sorted({max(1, cus * k // 8) for k in (2, 3, 4, 5, 6, 8, 12, 16)})
+    grids = sorted({max(1, cus * k // 16) for k in (4, 6, 8, 9, 10, 12, 16, 24, 32)})
     shapes = [dict(mulmod=m, block=b, cluster=k, temporal=t) for m in ("fp64", "shoup")
               for b in (256, 512) for k in (1, 4, 8, 16) for t in (False, True)]
     shapes += [dict(mulmod=m, block=256, cluster=8) for m in ("barrett", "montgomery")]
-    shapes += [dict(mulmod="fp64", block=b, cluster=1, temporal=t, interleaved=True)
-               for b in (128, 256) for t in (False, True)]
+    # interleaved kernel: cluster 0 = all workgroups interleave over one range
+    shapes += [dict(mulmod="fp64", block=256, cluster=k, temporal=t, interleaved=True)
+               for k in (0, 8, 16, 32) for t in (False, True)]
     for shape, grid in itertools.product(shapes, grids):
-        if grid % shape["cluster"]:
+        if shape["cluster"] and grid % shape["cluster"]:
             continue
         kw = dict(shape, grid=grid)
         with nn.BatchPlan(kind, len(states), total, **kw) as plan:

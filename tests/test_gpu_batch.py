@@ -81,7 +81,7 @@ def test_batch_bit_exact_mixed_lengths(kind, mulmod, interleaved):
                                         (128, 1, 1, True), (64, 1000, 8, True),
                                         (256, 4096, 4, True), (128, 12, 3, True),
                                         (256, 64, 64, False), (512, 5, 1, True)]:
-        if interleaved and (block not in (64, 128, 256) or cluster > 1):
+        if interleaved and block not in (64, 128, 256):
             continue
         _say("batch", kind, mulmod, interleaved, block, grid, cluster, graph)
         buf = _sentinel(total)
@@ -254,18 +254,23 @@ def test_slots_alternate_across_streams():
 
 
 @pytest.mark.parametrize("kind", ["u64", "f64"])
-@pytest.mark.parametrize("mulmod", ["fp64", "shoup", "barrett", "montgomery"])
-def test_small_batches_in_kernel_arguments(kind, mulmod):
+@pytest.mark.parametrize("mulmod,interleaved", [("fp64", False), ("shoup", False),
+                                                ("barrett", False), ("montgomery", False),
+                                                ("fp64", True)])
+def test_small_batches_in_kernel_arguments(kind, mulmod, interleaved):
     """Batches of up to 16 windows travel in the kernel arguments (no
-    upload); 1, 2, 15, 16 and 17 windows (17 takes the workspace path), odd
-    offsets, ragged lengths, one window long enough to be split in pieces."""
+    upload) and run the blocked kernel, also in an interleaved plan (whose
+    workgroups then form one cluster); 1, 2, 15, 16 and 17 windows (17 takes
+    the workspace path), odd offsets, ragged lengths, one window long enough
+    to be split in pieces."""
     dt = torch.float64 if kind == "f64" else torch.uint64
     lengths_all = [1, 511, 512, 513, 70_001, 3, 1024, 8193, 2, 65, 100_003, 17, 4096, 9, 300, 1025,
                    33]
-    with nn.BatchPlan(kind, 32, 1 << 26, mulmod=mulmod, block=128, grid=9) as plan:
+    with nn.BatchPlan(kind, 32, 1 << 26, mulmod=mulmod, block=128, grid=9,
+                      interleaved=interleaved) as plan:
         for nwin in (1, 2, 15, 16, 17):
             states, lengths, offsets, total = _mixed_batch(400 + nwin, lengths_all[:nwin])
-            _say("inline", kind, mulmod, nwin)
+            _say("inline", kind, mulmod, "interleaved" if interleaved else "blocked", nwin)
             buf = _sentinel(total)
             fin = plan.generate(states, lengths, offsets, buf.view(dt), final_states=True)
             torch.cuda.synchronize()
@@ -340,21 +345,27 @@ def test_interleaved_record_chunks(grid):
 
 
 def test_interleaved_output_index_limit():
-    """The interleaved kernel's shapes (FP64, block 64, 128 or 256, no clusters),
+    """The interleaved kernel's shapes (FP64, block 64, 128 or 256, clusters dividing the grid),
     and its row records' 52-bit output indices: windows reaching past 2^51
     elements are refused before anything is enqueued."""
     good = orc.seed(wl.INDEX_MIN)
     out = _sentinel(64)
     from paper_1206_1187_amd import _native
-    for bad in (dict(block=192), dict(block=512), dict(mulmod="shoup"), dict(cluster=2)):
+    for bad in (dict(block=192), dict(block=512), dict(mulmod="shoup"), dict(grid=128, cluster=3)):
         with pytest.raises(nn.NNError):
             nn.BatchPlan("f64", 2, 1 << 20, interleaved=True, **bad)
-    with nn.BatchPlan("f64", 2, 1 << 20, interleaved=True) as plan:
-        # through the C ABI: the binding already refuses windows past its tensor
-        descs = (_native.StreamDesc * 2)((good, 10, 0), (good, 10, (1 << 51) - 5))
-        rc = _native.lib().nn_generate_batch(plan._h, ctypes.cast(descs, ctypes.c_void_p), 2,
+    with nn.BatchPlan("f64", 32, 1 << 20, interleaved=True) as plan:
+        # through the C ABI (the binding already refuses windows past its
+        # tensor), with more windows than travel in the kernel arguments, so
+        # the batch goes to the interleaved kernel, which refuses it before
+        # anything is enqueued
+        n = 18
+        descs = (_native.StreamDesc * n)(*([(good, 2, 2 * i) for i in range(n - 1)] +
+                                           [(good, 10, (1 << 51) - 5)]))
+        rc = _native.lib().nn_generate_batch(plan._h, ctypes.cast(descs, ctypes.c_void_p), n,
                                              ctypes.c_void_p(out.data_ptr()), None, None)
         assert rc == _native.NN_ERANGE
+        assert b"2^51" in _native.lib().nn_last_error()
         plan.generate([good], [64], [0], out.view(torch.float64))
         torch.cuda.synchronize()
     ref, _ = orc.gen(good, 64, "f64")
