@@ -236,6 +236,14 @@ void harvest(nn_server* s) {
     }
 }
 
+// True when no batch is running or waiting for a lane.
+bool batches_idle(const nn_server* s) {
+    if (!s->pending.empty()) return false;
+    for (const Lane& l : s->lanes)
+        if (l.busy) return false;
+    return true;
+}
+
 // Admits from the head of the queue; returns true if anything was admitted.
 bool admit(nn_server* s) {
     bool any = false;
@@ -243,11 +251,14 @@ bool admit(nn_server* s) {
     while (!s->queue.empty()) {
         Request& r = s->reqs[s->queue.front()];
         if (s->slots_used >= s->cfg.max_slots) break;
-        // Small requests take the device queue while it keeps up (at most two
-        // entries in flight per queue workgroup); under heavier load the
-        // batch lanes, which spread each batch over the whole device.
+        // Small requests take the device queue while the server is lightly
+        // loaded: no batch running or waiting, and at most two entries in
+        // flight per queue workgroup.  Under load the batch lanes take
+        // everything (each batch spreads over the whole device), and the
+        // queue kernel, left idle, exits and frees its compute units.
         const bool small = s->dq && r.count && r.count <= s->cfg.queue_max_outputs &&
-                           s->qflight.size() < 2ull * s->cfg.queue_workgroups;
+                           s->qflight.size() < 2ull * s->cfg.queue_workgroups &&
+                           batches_idle(s);
         if (!small) {
             if (s->pending.size() >= s->cfg.max_batch_requests) break;
             if (s->pending_outputs + r.count > s->cfg.max_batch_outputs) break;
