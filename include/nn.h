@@ -464,13 +464,17 @@ int nn_e40_generate(uint64_t *state, uint64_t count, void *out_dev, int kind, vo
  * out[i] = a[i] * b[i] mod 3^33, with b[i] taking the role of the fixed
  * multiplier.  Every a[i] and b[i] must be a valid state;
  * NN_MULMOD_MODBARRETT multiplies by 2^53 itself and needs every b[i] to be
- * 2^53 mod 3^33.  For testing the arithmetic on a CPU; host pointers. */
+ * 2^53 mod 3^33.  NN_DEBUG_DEVICE_MULMOD selects the public device header's
+ * nn_dev_mulmod (include/nn_device.h), the FP64 reduction without the
+ * two-product of q 3^33 that the library's storing kernels use.  For testing
+ * the arithmetic on a CPU; host pointers. */
+#define NN_DEBUG_DEVICE_MULMOD 100
+int nn_debug_mulmod(int mulmod, const uint64_t *a, const uint64_t *b, uint64_t n,
+                    uint64_t *out);
+
 /* nn_e40_debug_mulmod -- the host build of the 3^40 step's reduction:
  * out[i] = a[i] * b[i] mod 3^40 for units a[i], b[i]; host pointers. */
 int nn_e40_debug_mulmod(const uint64_t *a, const uint64_t *b, uint64_t n, uint64_t *out);
-
-int nn_debug_mulmod(int mulmod, const uint64_t *a, const uint64_t *b, uint64_t n,
-                    uint64_t *out);
 
 #ifdef __cplusplus
 }

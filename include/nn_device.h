@@ -31,25 +31,24 @@
 /* v * z mod 3^33 for a state z and a multiplier m (nn_dev_mult_pow), exact.
  *
  * r = v z - q 3^33 with q = rint(z (qh + ql)), where qh + ql is v / 3^33 as
- * a double-double.  All values are integers below 2^106 and 3^33 < 2^53 <
- * 2 * 3^33:
- *  - ph + pl == v z and sh + sl == q 3^33 exactly (FMA two-product);
- *  - |q - v z / 3^33| <= 0.75 + 2^-52, because fl(z qh + fl(z ql)) is within
- *    one rounding of v z / 3^33 and rint adds at most 0.5 (0.5 in total once
- *    the estimate reaches 2^52, where its ulp is already 1); so |r| < 3^33;
- *  - ph - sh is exact (the operands are within a factor of two, Sterbenz, or
- *    the difference is an integer below 2^53), pl - sl is an integer below
- *    2^53 in magnitude, and r itself is an integer below 3^33;
- * so a single conditional add of 3^33 lands r in [1, 3^33). */
+ * a double-double.  With m = 3^33 (2^52 < m < 2^53) and v, z in [1, m):
+ *  - ph + pl == v z exactly (FMA two-product); v z < 2^105, so ph's ulp is
+ *    at most 2^52 and |pl| <= 2^51;
+ *  - |q - v z / m| <= 0.75 + 2^-52, because fl(z qh + fl(z ql)) is within
+ *    one rounding of v z / m and rint adds at most 0.5 (0.5 in total once
+ *    the estimate reaches 2^52, where its ulp is already 1); so r = v z - q m
+ *    is an integer with |r| <= 0.76 m < 2^52;
+ *  - t = fma(-q, m, ph) rounds the exact ph - q m = r - pl once; that is an
+ *    integer of magnitude below 0.76 m + 2^51 < 2^53, so t is exact, and so
+ *    is t + pl = r, an integer below 2^52;
+ * so a single conditional add of m lands r in [1, m). */
 __host__ __device__ __forceinline__ double nn_dev_mulmod(double z, nn_dev_mult m) {
     const double mod = 5559060566555523.0; /* 3^33 */
     const double ph = m.v * z;
     const double pl = __builtin_fma(m.v, z, -ph);
     const double e = __builtin_fma(z, m.qh, z * m.ql);
     const double q = __builtin_rint(e);
-    const double sh = q * mod;
-    const double sl = __builtin_fma(q, mod, -sh);
-    const double r = (ph - sh) + (pl - sl);
+    const double r = __builtin_fma(-q, mod, ph) + pl;
     return r < 0.0 ? r + mod : r;
 }
 

@@ -221,13 +221,15 @@ def dev_skip_table():
 
 
 def debug_mulmod(variant, a, b):
-    """Host build of a step-loop reduction: a[i]*b[i] mod 3^33 (numpy uint64)."""
+    """Host build of a step-loop reduction: a[i]*b[i] mod 3^33 (numpy uint64).
+    ``variant``: a reduction name, or "device" for include/nn_device.h's
+    nn_dev_mulmod."""
     import numpy as np
     a = np.ascontiguousarray(a, dtype=np.uint64)
     b = np.ascontiguousarray(b, dtype=np.uint64)
     out = np.empty_like(a)
     if isinstance(variant, str):
-        variant = MULMOD_NAMES[variant]
+        variant = _native.NN_DEBUG_DEVICE_MULMOD if variant == "device" else MULMOD_NAMES[variant]
     p = ctypes.POINTER(ctypes.c_uint64)
     _native.check(_native.lib().nn_debug_mulmod(
         int(variant), a.ctypes.data_as(p), b.ctypes.data_as(p), a.size, out.ctypes.data_as(p)))

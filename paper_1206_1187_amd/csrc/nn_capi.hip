@@ -535,7 +535,8 @@ const char* nn_version(void) { return "nn-alpha23 0.1.0 (gfx950)"; }
 
 int nn_debug_mulmod(int mulmod, const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t* out) {
     if (n && (!a || !b || !out)) return fail(NN_EINVAL, "NULL array");
-    if (mulmod < NN_MULMOD_DEFAULT || mulmod > NN_MULMOD_MODBARRETT)
+    if ((mulmod < NN_MULMOD_DEFAULT || mulmod > NN_MULMOD_MODBARRETT) &&
+        mulmod != NN_DEBUG_DEVICE_MULMOD)
         return fail(NN_EINVAL, "mulmod %d unknown", mulmod);
     for (uint64_t i = 0; i < n; ++i)
         if (!valid_state(a[i]) || !valid_state(b[i]))
@@ -553,6 +554,9 @@ int nn_debug_mulmod(int mulmod, const uint64_t* a, const uint64_t* b, uint64_t n
         switch (mulmod) {
             case NN_MULMOD_DEFAULT:
             case NN_MULMOD_FP64: out[i] = VarFP64::to_u64(VarFP64::mul(VarFP64::load(a[i]), f)); break;
+            case NN_DEBUG_DEVICE_MULMOD:
+                out[i] = (uint64_t)nn_dev_mulmod((double)a[i], nn_dev_mult{f.v, f.qh, f.ql});
+                break;
             case NN_MULMOD_BARRETT: out[i] = VarBarrett::mul(a[i], f); break;
             case NN_MULMOD_SHOUP: out[i] = VarShoup::mul(a[i], f); break;
             default: out[i] = VarMontgomery::mul(a[i], f); break;

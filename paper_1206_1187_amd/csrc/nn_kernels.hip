@@ -218,7 +218,7 @@ static hipError_t consume_v(int kind, uint32_t grid, uint32_t block, hipStream_t
 hipError_t launch_consume(int mulmod, int kind, uint32_t grid, uint32_t block, hipStream_t s,
                           const GenArgs& a, void* result) {
     switch (mulmod) {
-        case 1: return consume_v<VarFP64>(kind, grid, block, s, a, result);
+        case 1: return consume_v<VarFP64Fused>(kind, grid, block, s, a, result);
         case 2: return consume_v<VarBarrett>(kind, grid, block, s, a, result);
         case 3: return consume_v<VarShoup>(kind, grid, block, s, a, result);
         case 4: return consume_v<VarMontgomery>(kind, grid, block, s, a, result);

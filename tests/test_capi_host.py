@@ -123,8 +123,10 @@ def _adversarial_pairs(rng, n):
     return a, b
 
 
-@pytest.mark.parametrize("variant", ["fp64", "barrett", "shoup", "montgomery"])
+@pytest.mark.parametrize("variant", ["fp64", "barrett", "shoup", "montgomery", "device"])
 def test_host_build_of_reductions_is_exact(variant):
+    """Every reduction, and the public device header's nn_dev_mulmod
+    ("device"), on random and adversarial pairs against Python integers."""
     rng = random.Random(hash(variant) & 0xffff)
     a, b = _adversarial_pairs(rng, 20000)
     r = np.random.default_rng(7)
