@@ -48,6 +48,27 @@ def _timed_kernel(fn, reps, torch):
     return sum(ms) / len(ms) / 1e3
 
 
+def pick_grid(nn, torch, cfg, out, state, deltas, rounds=3, reps=5):
+    """The launch shape `cfg` with the grid that runs fastest on this device
+    among the tuned grid and its neighbours (grid + d for d in deltas): the
+    best grid differs between boxes by up to one such step.  Each candidate
+    is timed `rounds` times (reps launches each, one untimed before); the
+    best round counts.  Returns (cfg, {grid: ms})."""
+    cands = []
+    for d in deltas:
+        c = type(cfg)(*[getattr(cfg, f) for f, _ in cfg._fields_])
+        c.grid = max(16, cfg.grid + d)
+        cands.append(c)
+    best = {c.grid: float("inf") for c in cands}
+    for _ in range(rounds):
+        for c in cands:
+            nn.generate_into(state, out, cfg=c)
+            s = _timed_kernel(lambda: nn.generate_into(state, out, cfg=c), reps, torch)
+            best[c.grid] = min(best[c.grid], s * 1e3)
+    chosen = min(cands, key=lambda c: best[c.grid])
+    return chosen, best
+
+
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -227,6 +248,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fill ceiling and reduction comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form replay")
+    ap.add_argument("--no-shape-pick", action="store_true",
+                    help="use the tuned launch shapes as they are (no per-device grid choice)")
     ap.add_argument("--only", choices=["batched", "served"],
                     help="run only this leg and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -266,16 +289,23 @@ def main():
     out_u = torch.empty(case.count_u64, dtype=torch.uint64, device="cuda")
     cfg_f = nn.default_cfg("f64", case.count_f64)
     cfg_u = nn.default_cfg("u64", case.count_u64)
+    picked = None
+    if not args.no_shape_pick:
+        s0 = nn.seed(case.index)
+        cfg_f, pf = pick_grid(nn, torch, cfg_f, out_f, s0, (0, -16, 16))
+        cfg_u, pu = pick_grid(nn, torch, cfg_u, out_u, s0, (0, -32, 32))
+        picked = {"f64_grid_ms": pf, "u64_grid_ms": pu}
+        log("grid choice", json.dumps(picked))
     log("workload", case, "cfg f64", cfg_f.as_dict(), "cfg u64", cfg_u.as_dict())
 
     def step(ev=None):
         s = nn.seed(case.index)
         if ev is not None:
             ev[0].record()
-        nn.generate_into(s, out_f)
+        nn.generate_into(s, out_f, cfg=cfg_f)
         if ev is not None:
             ev[1].record()
-        nn.generate_into(s, out_u)
+        nn.generate_into(s, out_u, cfg=cfg_u)
 
     for _ in range(args.warmup):
         step()
@@ -317,6 +347,7 @@ def main():
             "count_u64": case.count_u64,
             "launch_f64": cfg_f.as_dict(),
             "launch_u64": cfg_u.as_dict(),
+            "grid_choice_ms": picked,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -334,7 +365,8 @@ def main():
     if not args.no_extras:
         extras = {}
         reps = 20
-        u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u), reps, torch)
+        u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u, cfg=cfg_u), reps,
+                            torch)
         extras["generate_u64_GBps"] = 8.0 * case.count_u64 / u_s / 1e9
         # The paper's "Constant" kernel (Section 4.2) with the generator's own
         # store pattern, and with the fastest pattern measured (flat).
@@ -362,7 +394,7 @@ def main():
         for _ in range(10):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            nn.generate_into(nn.seed(case.index), out_f)
+            nn.generate_into(nn.seed(case.index), out_f, cfg=cfg_f)
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t0)
         extras["f64_kernel_ms"] = f64_s * 1e3
