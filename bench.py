@@ -99,7 +99,7 @@ def traffic_from_profile():
         return None
 
 
-def batched_leg(nn, torch):
+def batched_leg(nn, torch, pick=True):
     """Config 4: 10,000 streams (lengths log-uniform in [1, 2^22]) as one
     batched launch replayed from the plan's hipGraph, against the same
     streams with one nn_generate launch each on the same stream."""
@@ -114,6 +114,22 @@ def batched_leg(nn, torch):
     res = {"workload": "batched: 10,000 seed indices (numpy default_rng(3)), lengths "
                        "log-uniform in [1, 2^22], f64, windows packed back to back",
            "streams": len(states), "variates": total}
+    if kw.get("grid") and pick:
+        # the tuned shape with its grid or a neighbour (cluster kept), as for
+        # the plain form: two rounds of three replays each, the best counting
+        step = max(16, int(kw.get("cluster") or 16))
+        times = {}
+        for _ in range(2):
+            for g in (kw["grid"], kw["grid"] - step, kw["grid"] + step):
+                if g <= 0 or (kw.get("cluster") and g % kw["cluster"]):
+                    continue
+                with nn.BatchPlan("f64", len(states), total, **dict(kw, grid=g)) as plan:
+                    for _ in range(2):
+                        plan.generate(states, lengths, offsets, out)
+                    s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 3, torch)
+                times[g] = min(times.get(g, float("inf")), s * 1e3)
+        kw = dict(kw, grid=min(times, key=times.get))
+        res["grid_choice_ms"] = times
     with nn.BatchPlan("f64", len(states), total, **kw) as plan:
         res["cfg"] = plan.cfg().as_dict()
         for _ in range(8):  # warm-up: first touch of the output (several launches), first replay
@@ -281,7 +297,8 @@ def main():
         return
     nn.init(0)
     if args.only:
-        leg = batched_leg(nn, torch) if args.only == "batched" else served_leg(nn, torch)
+        leg = (batched_leg(nn, torch, pick=not args.no_shape_pick) if args.only == "batched"
+               else served_leg(nn, torch))
         print(json.dumps({args.only: leg}), flush=True)
         return
     case = wl.plain_bulk()
@@ -440,7 +457,7 @@ def main():
     del out_f, out_u
     torch.cuda.empty_cache()
     if not args.no_extras:
-        result["batched"] = batched_leg(nn, torch)
+        result["batched"] = batched_leg(nn, torch, pick=not args.no_shape_pick)
         log("batched", json.dumps(result["batched"]))
         if not args.no_served:
             result["served"] = served_leg(nn, torch)
