@@ -114,27 +114,38 @@ def batched_leg(nn, torch, pick=True):
     res = {"workload": "batched: 10,000 seed indices (numpy default_rng(3)), lengths "
                        "log-uniform in [1, 2^22], f64, windows packed back to back",
            "streams": len(states), "variates": total}
-    if kw.get("grid") and pick:
-        # the tuned shape with its grid or a neighbour (cluster kept), as for
-        # the plain form: two rounds of three replays each, the best counting
-        step = max(16, int(kw.get("cluster") or 16))
-        times = {}
-        for _ in range(2):
-            for g in (kw["grid"], kw["grid"] - step, kw["grid"] + step):
-                if g <= 0 or (kw.get("cluster") and g % kw["cluster"]):
-                    continue
-                with nn.BatchPlan("f64", len(states), total, **dict(kw, grid=g)) as plan:
+    # The tuned shape with its grid or a neighbour (cluster kept), as for the
+    # plain form: two rounds of three replays per candidate, the best
+    # counting.  The candidates' plans stay alive and the chosen one is
+    # timed, so no plan is freed or allocated just before the measurement.
+    plans = {}
+    try:
+        if kw.get("grid") and pick:
+            step = max(16, int(kw.get("cluster") or 16))
+            grids = [g for g in (kw["grid"], kw["grid"] - step, kw["grid"] + step)
+                     if g > 0 and not (kw.get("cluster") and g % kw["cluster"])]
+            for g in grids:
+                plans[g] = nn.BatchPlan("f64", len(states), total, **dict(kw, grid=g))
+            times = {}
+            for _ in range(2):
+                for g in grids:
                     for _ in range(2):
-                        plan.generate(states, lengths, offsets, out)
-                    s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 3, torch)
-                times[g] = min(times.get(g, float("inf")), s * 1e3)
-        kw = dict(kw, grid=min(times, key=times.get))
-        res["grid_choice_ms"] = times
-    with nn.BatchPlan("f64", len(states), total, **kw) as plan:
+                        plans[g].generate(states, lengths, offsets, out)
+                    t = _timed_kernel(lambda: plans[g].generate(states, lengths, offsets, out),
+                                      3, torch)
+                    times[g] = min(times.get(g, float("inf")), t * 1e3)
+            kw = dict(kw, grid=min(times, key=times.get))
+            res["grid_choice_ms"] = times
+        plan = plans.get(kw.get("grid"))
+        if plan is None:
+            plan = plans[None] = nn.BatchPlan("f64", len(states), total, **kw)
         res["cfg"] = plan.cfg().as_dict()
         for _ in range(8):  # warm-up: first touch of the output (several launches), first replay
             plan.generate(states, lengths, offsets, out)
         graph_s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 10, torch)
+    finally:
+        for p in plans.values():
+            p.close()
     with nn.BatchPlan("f64", len(states), total, graph=False, **kw) as plan:
         for _ in range(3):
             plan.generate(states, lengths, offsets, out)

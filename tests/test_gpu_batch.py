@@ -197,19 +197,29 @@ def test_skip_stress_full_as_one_batch():
         assert np.array_equal(got[i], ref.view(np.uint64)), (i, o)
 
 
-@pytest.mark.parametrize("interleaved", [False, True])
-def test_batched_workload_full_size_sampled(interleaved):
-    """Config 4 at full size (10,000 streams, 2.7e9 outputs), both batch
-    kernels at their default shapes: every stream's first and last 64
-    outputs, and 400 whole streams, against the oracle."""
+@pytest.mark.parametrize("shape", ["blocked", "interleaved", "tuned", "tuned-", "tuned+"])
+def test_batched_workload_full_size_sampled(shape):
+    """Config 4 at full size (10,000 streams, 2.7e9 outputs): both batch
+    kernels at their default shapes, and the tuned shape the benchmark runs
+    with the neighbouring grids it may pick instead (cluster kept): every
+    stream's first and last 64 outputs, and 400 whole streams, against the
+    oracle."""
+    from paper_1206_1187_amd import tune
     case = wl.batched()
     states = np.array([orc.seed(int(a)) for a in case.indices], dtype=np.uint64)
     lengths = case.lengths
     offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
     total = int(lengths.sum())
     out = torch.empty(total, dtype=torch.float64, device="cuda")
-    with nn.BatchPlan("f64", len(states), total, interleaved=interleaved) as plan:
-        _say("batched full", plan.cfg().as_dict(), total)
+    if shape in ("blocked", "interleaved"):
+        kw = dict(interleaved=shape == "interleaved")
+    else:
+        kw = tune.best_batch_cfg("f64", total)
+        if shape != "tuned" and kw.get("grid"):
+            step = max(16, int(kw.get("cluster") or 16))
+            kw = dict(kw, grid=kw["grid"] + (step if shape == "tuned+" else -step))
+    with nn.BatchPlan("f64", len(states), total, **kw) as plan:
+        _say("batched full", shape, plan.cfg().as_dict(), total)
         fin = plan.generate(states, lengths, offsets, out, final_states=True)
     torch.cuda.synchronize()
     flat = out.view(torch.int64)

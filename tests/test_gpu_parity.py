@@ -256,6 +256,37 @@ def test_plain_bulk_full_size_bit_exact():
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("kind,deltas", [("f64", (-16, 16)), ("u64", (-32, 32))])
+def test_plain_bulk_full_size_bench_grids_sampled(kind, deltas):
+    """The benchmark picks its grid on the device among the tuned one and
+    its neighbours; the neighbours at full size, sampled chunks (the start,
+    the ragged end, and random offsets) against the oracle."""
+    case = wl.plain_bulk()
+    z0 = nn.seed(case.index)
+    count = case.count_f64 if kind == "f64" else case.count_u64
+    base = nn.default_cfg(kind, count)
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    out = torch.empty(count, dtype=dt, device="cuda")
+    rng = np.random.default_rng(5)
+    n = 1 << 16
+    starts = [0, count - n] + [int(x) for x in rng.integers(0, count - n, 14)]
+    for d in deltas:
+        cfg = nn.LaunchCfg(*[getattr(base, f) for f, _ in base._fields_])
+        cfg.grid = base.grid + d
+        _say("bench grid", kind, cfg.as_dict())
+        out.fill_(0)
+        zn = nn.generate_into(z0, out, cfg=cfg)
+        torch.cuda.synchronize()
+        assert zn == orc.skip(z0, count)
+        flat = out.view(torch.int64)
+        for st in starts:
+            ref, _ = orc.gen(orc.skip(z0, st), n, kind)
+            got = flat[st:st + n].cpu().numpy().view(np.uint64)
+            assert np.array_equal(got, ref.view(np.uint64)), (kind, d, st)
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_flat_chunk_boundary_beyond_one_launch():
     """Counts above one flat launch (2^30 outputs) are split into several
     launches; check the outputs on both sides of every split and the tail."""
