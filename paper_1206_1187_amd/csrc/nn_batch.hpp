@@ -82,7 +82,7 @@ constexpr uint32_t kRecChunk = 4096;
 // Kernel arguments (fixed for the life of a plan).
 struct BatchArgs {
     const BatchHeader* ws;  // device workspace
-    uint32_t cluster;       // workgroups sharing a row range
+    uint32_t cluster;       // workgroups sharing a row range (both batch kernels)
     Mult JB;                // (2^53)^(2*block*cluster): the next row of a lane
     Mult JB2;               // (2^53)^(4*block*cluster): two such rows
     Mult Minv;              // (2^53)^-1
@@ -97,9 +97,11 @@ struct BatchArgs {
     uint32_t row_outs;      // outputs per row (2*kIlPairs*block, a power of two)
 };
 
-// Interleaved kernels (FP64 reduction, block <= 256): the pre-pass writes
-// every row's record, then workgroup w of the row kernel takes rows w,
-// w + grid, ... (one write front, as the plain row layout).
+// Interleaved kernels (FP64 reduction, block 64, 128 or 256): the pre-pass
+// writes every row's record, then the row kernel's clusters of `cluster`
+// workgroups each take a contiguous range of rows and interleave them
+// (cluster = grid: workgroup w takes rows w, w + grid, ..., one write front
+// as in the plain row layout).
 const void* batch_rec_kernel(bool indexed);
 const void* batch_rows_kernel(int kind, bool nontemporal);
 
