@@ -255,6 +255,20 @@ def cpu_baseline(case):
     t1 = time.perf_counter()
     orc.gen_into(z0, one, threads=1)
     wall1 = time.perf_counter() - t1
+    # the paper's own serial CPU loop (Section 3.1's Modified Barrett step,
+    # the comparator kept in the oracle), one thread, the same prefix
+    t2 = time.perf_counter()
+    orc.gen_f64_modbarrett(z0, one.size)
+    wall2 = time.perf_counter() - t2
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": total / wall,
         "unit": "variates/s",
@@ -263,6 +277,8 @@ def cpu_baseline(case):
         "sample": "one full step (2^30 f64 + 2^28 u64 from the same seed index) in 2^25-element "
                   "chunks, OpenMP skip-ahead partition over %d threads; %.2f s wall" % (threads, wall),
         "single_thread_value": float(one.size / wall1),
+        "single_thread_modified_barrett_value": float(one.size / wall2),
+        "cpu_model": model,
     }
 
 
