@@ -48,27 +48,6 @@ def _timed_kernel(fn, reps, torch):
     return sum(ms) / len(ms) / 1e3
 
 
-def pick_grid(nn, torch, cfg, out, state, deltas, rounds=3, reps=5):
-    """The launch shape `cfg` with the grid that runs fastest on this device
-    among the tuned grid and its neighbours (grid + d for d in deltas): the
-    best grid differs between boxes by up to one such step.  Each candidate
-    is timed `rounds` times (reps launches each, one untimed before); the
-    best round counts.  Returns (cfg, {grid: ms})."""
-    cands = []
-    for d in deltas:
-        c = type(cfg)(*[getattr(cfg, f) for f, _ in cfg._fields_])
-        c.grid = max(16, cfg.grid + d)
-        cands.append(c)
-    best = {c.grid: float("inf") for c in cands}
-    for _ in range(rounds):
-        for c in cands:
-            nn.generate_into(state, out, cfg=c)
-            s = _timed_kernel(lambda: nn.generate_into(state, out, cfg=c), reps, torch)
-            best[c.grid] = min(best[c.grid], s * 1e3)
-    chosen = min(cands, key=lambda c: best[c.grid])
-    return chosen, best
-
-
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -115,27 +94,14 @@ def batched_leg(nn, torch, pick=True):
                        "log-uniform in [1, 2^22], f64, windows packed back to back",
            "streams": len(states), "variates": total}
     # The tuned shape with its grid or a neighbour (cluster kept), as for the
-    # plain form: two rounds of three replays per candidate, the best
-    # counting.  The candidates' plans stay alive and the chosen one is
+    # plain form.  The candidates' plans stay alive and the chosen one is
     # timed, so no plan is freed or allocated just before the measurement.
     plans = {}
     try:
-        if kw.get("grid") and pick:
-            step = max(16, int(kw.get("cluster") or 16))
-            grids = [g for g in (kw["grid"], kw["grid"] - step, kw["grid"] + step)
-                     if g > 0 and not (kw.get("cluster") and g % kw["cluster"])]
-            for g in grids:
-                plans[g] = nn.BatchPlan("f64", len(states), total, **dict(kw, grid=g))
-            times = {}
-            for _ in range(2):
-                for g in grids:
-                    for _ in range(2):
-                        plans[g].generate(states, lengths, offsets, out)
-                    t = _timed_kernel(lambda: plans[g].generate(states, lengths, offsets, out),
-                                      3, torch)
-                    times[g] = min(times.get(g, float("inf")), t * 1e3)
-            kw = dict(kw, grid=min(times, key=times.get))
-            res["grid_choice_ms"] = times
+        if pick:
+            kw, times, plans = tune.pick_batch_grid(kw, "f64", states, lengths, offsets, out)
+            if times:
+                res["grid_choice_ms"] = times
         plan = plans.get(kw.get("grid"))
         if plan is None:
             plan = plans[None] = nn.BatchPlan("f64", len(states), total, **kw)
@@ -335,9 +301,10 @@ def main():
     cfg_u = nn.default_cfg("u64", case.count_u64)
     picked = None
     if not args.no_shape_pick:
+        from paper_1206_1187_amd import tune
         s0 = nn.seed(case.index)
-        cfg_f, pf = pick_grid(nn, torch, cfg_f, out_f, s0, (0, -16, 16))
-        cfg_u, pu = pick_grid(nn, torch, cfg_u, out_u, s0, (0, -32, 32))
+        cfg_f, pf = tune.pick_plain_grid(cfg_f, out_f, s0, (0, -16, 16))
+        cfg_u, pu = tune.pick_plain_grid(cfg_u, out_u, s0, (0, -32, 32))
         picked = {"f64_grid_ms": pf, "u64_grid_ms": pu}
         log("grid choice", json.dumps(picked))
     log("workload", case, "cfg f64", cfg_f.as_dict(), "cfg u64", cfg_u.as_dict())

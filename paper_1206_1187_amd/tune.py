@@ -85,6 +85,73 @@ def _median_ms(fn, reps, warm=2):
     return ms[len(ms) // 2]
 
 
+def _min_ms(fn, reps, rounds):
+    """Best over `rounds` of the mean duration of `reps` launches of fn()
+    (one untimed launch before each round), in ms."""
+    import torch
+    best = float("inf")
+    for _ in range(rounds):
+        fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        best = min(best, sum(a.elapsed_time(b) for a, b in evs) / reps)
+    return best
+
+
+def pick_plain_grid(cfg, out, state, deltas, rounds=3, reps=5):
+    """The launch shape `cfg` (an nn_launch_cfg) with the grid that runs
+    fastest on the current device among cfg.grid + d, d in `deltas`: the best
+    grid of a tuned shape differs between MI355X boxes by about one such
+    step.  Times generate_into(state, out) for each candidate, interleaving
+    the candidates over `rounds` rounds.  Returns (cfg, {grid: ms})."""
+    import paper_1206_1187_amd as nn
+    cands = []
+    for d in deltas:
+        c = type(cfg)(*[getattr(cfg, f) for f, _ in cfg._fields_])
+        c.grid = max(16, cfg.grid + d)
+        cands.append(c)
+    times = {c.grid: float("inf") for c in cands}
+    for _ in range(rounds):
+        for c in cands:
+            times[c.grid] = min(times[c.grid],
+                                _min_ms(lambda: nn.generate_into(state, out, cfg=c), reps, 1))
+    return min(cands, key=lambda c: times[c.grid]), times
+
+
+def pick_batch_grid(kw, kind, states, lengths, offsets, out, rounds=2, reps=3):
+    """BatchPlan keyword arguments `kw` with the grid (or a neighbour one
+    cluster away, the cluster kept) that replays fastest on the current
+    device.  Returns (kw, {grid: ms}, {grid: plan}); the caller owns the
+    candidates' plans and closes them (reusing the chosen one avoids freeing
+    and allocating workspaces just before its own measurement)."""
+    import paper_1206_1187_amd as nn
+    if not kw.get("grid"):
+        return dict(kw), {}, {}
+    step = max(16, int(kw.get("cluster") or 16))
+    grids = [g for g in (kw["grid"], kw["grid"] - step, kw["grid"] + step)
+             if g > 0 and not (kw.get("cluster") and g % kw["cluster"])]
+    total = int(sum(int(n) for n in lengths))
+    plans = {}
+    try:
+        for g in grids:
+            plans[g] = nn.BatchPlan(kind, len(states), total, **dict(kw, grid=g))
+        times = {}
+        for _ in range(rounds):
+            for g in grids:
+                times[g] = min(times.get(g, float("inf")), _min_ms(
+                    lambda: plans[g].generate(states, lengths, offsets, out), reps, 1))
+    except BaseException:
+        for p in plans.values():
+            p.close()
+        raise
+    return dict(kw, grid=min(times, key=times.get)), times, plans
+
+
 def tune_plain(kind, count, reps=9, log=print):
     import torch
 
