@@ -336,18 +336,20 @@ def test_batch_offsets_beyond_32_bit_indexing():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("grid", [1, 3])
-def test_interleaved_record_chunks(grid):
+@pytest.mark.parametrize("grid,temporal", [(1, False), (3, False), (3, True)])
+def test_interleaved_record_chunks(grid, temporal):
     """The interleaved kernel stages row records in LDS 4096 at a time (the
     first chunk shorter on most workgroups): workgroups with well over 4096
-    rows, windows at both offset parities, against the oracle."""
+    rows, windows at both offset parities, against the oracle; non-temporal
+    and temporal stores."""
     rng = np.random.default_rng(40 + grid)
     lengths = [int(x) for x in rng.integers(1, 100_000, 90)] + [300_001]
     states, lengths, offsets, total = _mixed_batch(41 + grid, lengths)
     buf = _sentinel(total)
-    with nn.BatchPlan("f64", 128, total, block=64, grid=grid, interleaved=True) as plan:
+    with nn.BatchPlan("f64", 128, total, block=64, grid=grid, interleaved=True,
+                      temporal=temporal) as plan:
         rows = sum((int(n) + (int(o) % 128) + 127) // 128 for n, o in zip(lengths, offsets))
-        _say("interleaved chunks", grid, "rows", rows)
+        _say("interleaved chunks", grid, "temporal" if temporal else "nt", "rows", rows)
         assert rows // grid > 2 * 4096
         plan.generate(states, lengths, offsets, buf.view(torch.float64))
         torch.cuda.synchronize()
