@@ -314,7 +314,7 @@ typedef struct nn_server_cfg {
                                     current device, 256-byte aligned), or NULL for
                                     one owned by the server */
     uint64_t pool_bytes;         /* output pool size in bytes, > 0 */
-    uint64_t max_batch_outputs;  /* outputs per batch and per request; 0 = 2^26 */
+    uint64_t max_batch_outputs;  /* outputs per batch and per request; 0 = 2^27 */
     uint32_t max_batch_requests; /* requests per batch; 0 = 4096 */
     uint32_t max_slots;          /* admitted, unreleased requests; 0 = 65536 */
     uint32_t lanes;              /* concurrent batches; 0 = 2, at most 64 */

@@ -156,7 +156,7 @@ struct nn_server {
 
 namespace {
 
-constexpr uint64_t kDefaultBatchOutputs = 1ull << 26;
+constexpr uint64_t kDefaultBatchOutputs = 1ull << 27;
 constexpr uint32_t kDefaultBatchRequests = 4096;
 constexpr uint32_t kDefaultSlots = 65536;
 constexpr uint32_t kDefaultLanes = 2;
