@@ -1,0 +1,101 @@
+// host_driver.cpp -- the library's host-side arithmetic (csrc/nn_host.hpp,
+// csrc/nn_arith.hpp, csrc/nn_e40.hpp and the device header's
+// nn_dev_mulmod, all of which also compile for the host) under
+// AddressSanitizer and UndefinedBehaviorSanitizer, checked against the
+// oracle on edge and random inputs.  Built by tests/test_oracle_sanitized.py
+// with a host compiler only; test infrastructure.
+#include <stdint.h>
+#include <stdio.h>
+
+#include "nn_e40.hpp"
+#include "nn_host.hpp"
+
+extern "C" {
+#include "nn_oracle.h"
+}
+
+static int fails = 0;
+#define CHECK(c)                                                                  \
+    do {                                                                          \
+        if (!(c)) {                                                               \
+            if (fails < 20) fprintf(stderr, "FAIL %s:%d: %s\n", __FILE__, __LINE__, #c); \
+            ++fails;                                                              \
+        }                                                                         \
+    } while (0)
+
+static uint64_t rng = 0xD1B54A32D192ED03ULL;
+static uint64_t next64() {  // xorshift64*
+    rng ^= rng >> 12;
+    rng ^= rng << 25;
+    rng ^= rng >> 27;
+    return rng * 0x2545F4914F6CDD1DULL;
+}
+
+static uint64_t unit(uint64_t m) {  // a random unit modulo a power of 3
+    for (;;) {
+        const uint64_t z = 1 + next64() % (m - 1);
+        if (z % 3) return z;
+    }
+}
+
+static void check_mult(uint64_t v, uint64_t z) {
+    const nn::Mult f = nn::make_mult(v);
+    const uint64_t want = orc_mulmod(z, v, ORC_MOD);
+    CHECK((uint64_t)nn::mm_fp64((double)z, f.v, f.qh, f.ql) == want);
+    CHECK((uint64_t)nn_dev_mulmod((double)z, nn_dev_mult{f.v, f.qh, f.ql}) == want);
+    CHECK(nn::mm_barrett(z, v) == want);
+    CHECK(nn::mm_shoup(z, v, f.shoup) == want);
+    CHECK(nn::mm_montgomery(z, f.mont) == want);
+}
+
+int main() {
+    const uint64_t m = ORC_MOD;
+    CHECK(nn::kMod == m && nn::e40::kMod == ORC_E40_MOD);
+    // the four reductions at the ends of the unit range and at random
+    const uint64_t edge[] = {1, 2, 4, m - 1, m - 2, m - 4, nn::kMult, nn::kHalf, nn::kHalf + 1};
+    for (uint64_t v : edge)
+        for (uint64_t z : edge) check_mult(v, z);
+    for (int i = 0; i < 200000; ++i) check_mult(unit(m), unit(m));
+    // the step multiplier and its powers, as the kernels take them
+    for (int i = 0; i < 2000; ++i) {
+        const uint64_t k = next64() >> (next64() % 64);
+        check_mult(nn::MultPowers::get().pow(k), unit(m));
+        const uint64_t s = unit(m);
+        CHECK(nn::h_skip(s, k) == orc_skip(s, k));
+        CHECK(nn::mm_modbarrett_step(s) == orc_step(s));
+    }
+    CHECK(nn::h_skip(1, 0) == 1);
+    CHECK(nn::h_skip(1, nn::kPeriod) == 1);
+    CHECK(nn::h_skip(7, UINT64_MAX) == orc_skip(7, UINT64_MAX));
+    // seeding (Eq. 2) at the ends of the index range and at random
+    uint64_t z = 0;
+    const uint64_t idx[] = {ORC_INDEX_MIN, ORC_INDEX_MIN + 1, ORC_INDEX_MAX - 1, ORC_INDEX_MAX};
+    for (uint64_t a : idx) CHECK(orc_seed(a, &z) == 0 && nn::h_seed(a) == z);
+    for (int i = 0; i < 2000; ++i) {
+        const uint64_t a = ORC_INDEX_MIN + next64() % (ORC_INDEX_MAX - ORC_INDEX_MIN);
+        CHECK(orc_seed(a, &z) == 0 && nn::h_seed(a) == z && nn::valid_state(z));
+    }
+    CHECK(!nn::valid_state(0) && !nn::valid_state(m) && !nn::valid_state(3));
+    // variates: RN(z RN(3^-33)) on both sides
+    for (int i = 0; i < 10000; ++i) {
+        const uint64_t s = unit(m);
+        CHECK(nn::VarFP64::to_f64((double)s) == orc_to_f64(s));
+        CHECK(nn::VarBarrett::to_f64(s) == orc_to_f64(s));
+    }
+    // 3^40: Montgomery step against the oracle's
+    const uint64_t m40 = ORC_E40_MOD;
+    const uint64_t mont = (uint64_t)(((nn::u128)nn::e40::kMult << 64) % m40);
+    const uint64_t e40_edge[] = {1, 2, m40 - 1, m40 - 2, nn::e40::kHalf, 1ULL << 63};
+    for (uint64_t s : e40_edge) CHECK(nn::e40::mm40(s, mont) == orc_e40_step(s));
+    for (int i = 0; i < 200000; ++i) {
+        const uint64_t s = unit(m40);
+        CHECK(nn::e40::mm40(s, mont) == orc_e40_step(s));
+        CHECK(nn::e40::to_f64(s) == orc_e40_to_f64(s));
+    }
+    if (fails) {
+        fprintf(stderr, "%d check(s) failed\n", fails);
+        return 1;
+    }
+    printf("host driver ok\n");
+    return 0;
+}
