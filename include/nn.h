@@ -450,9 +450,13 @@ int nn_e40_skip(uint64_t state, uint64_t k, uint64_t *state_out);
  * (device memory, 8-byte aligned, count*8 bytes, owned by the caller) as
  * uint64 or binary64 and sets *state to z_count; asynchronous on `stream`.
  * cfg (NULL for the defaults) may set block, grid, unroll (1, 2, 4), ilp
- * (1, 2, 4) and NN_CFG_TEMPORAL_STORES (defaults: 256 threads, 2 workgroups
- * per CU, ilp 2, unroll 1); the reduction is Montgomery's (R = 2^64), the
- * layout the row layout with 16-byte stores.  Errors as nn_generate_ex. */
+ * (1, 2, 4), NN_CFG_TEMPORAL_STORES and mulmod: NN_MULMOD_FP64 (the
+ * default: states as two base-3^20 limbs, since 3^40 = (3^20)^2 the step is
+ * three exact FP64 products modulo 3^20; defaults 256 threads, one
+ * workgroup per CU, ilp 2, unroll 1) or NN_MULMOD_MONTGOMERY (64-bit
+ * states, R = 2^64; defaults 256 threads, three workgroups per CU, ilp 4,
+ * unroll 2).  The layout is the row layout with 16-byte stores.  Both
+ * reductions give the same bits.  Errors as nn_generate_ex. */
 int nn_e40_generate_ex(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream,
                        const nn_launch_cfg *cfg);
 int nn_e40_generate(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream);
@@ -472,9 +476,14 @@ int nn_e40_generate(uint64_t *state, uint64_t count, void *out_dev, int kind, vo
 int nn_debug_mulmod(int mulmod, const uint64_t *a, const uint64_t *b, uint64_t n,
                     uint64_t *out);
 
-/* nn_e40_debug_mulmod -- the host build of the 3^40 step's reduction:
- * out[i] = a[i] * b[i] mod 3^40 for units a[i], b[i]; host pointers. */
+/* nn_e40_debug_mulmod -- the host build of the 3^40 step's Montgomery
+ * reduction: out[i] = a[i] * b[i] mod 3^40 for units a[i], b[i]; host
+ * pointers.  nn_e40_debug_mulmod_ex selects the reduction: NN_MULMOD_FP64
+ * (or NN_MULMOD_DEFAULT; the base-3^20 limb step) or NN_MULMOD_MONTGOMERY;
+ * NN_EINVAL for any other, a NULL array or a non-unit operand. */
 int nn_e40_debug_mulmod(const uint64_t *a, const uint64_t *b, uint64_t n, uint64_t *out);
+int nn_e40_debug_mulmod_ex(int mulmod, const uint64_t *a, const uint64_t *b, uint64_t n,
+                           uint64_t *out);
 
 #ifdef __cplusplus
 }

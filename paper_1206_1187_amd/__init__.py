@@ -192,15 +192,17 @@ def e40_generate_into(state, out, stream=None, cfg=None):
     return st.value
 
 
-def e40_debug_mulmod(a, b):
-    """Host build of the 3^40 reduction: a[i]*b[i] mod 3^40 (numpy uint64)."""
+def e40_debug_mulmod(a, b, mulmod="montgomery"):
+    """Host build of a 3^40 reduction ("montgomery" or "fp64", the limb
+    step): a[i]*b[i] mod 3^40 (numpy uint64)."""
     import numpy as np
     a = np.ascontiguousarray(a, dtype=np.uint64)
     b = np.ascontiguousarray(b, dtype=np.uint64)
     out = np.empty_like(a)
     p = ctypes.POINTER(ctypes.c_uint64)
-    _native.check(_native.lib().nn_e40_debug_mulmod(a.ctypes.data_as(p), b.ctypes.data_as(p),
-                                                    a.size, out.ctypes.data_as(p)))
+    _native.check(_native.lib().nn_e40_debug_mulmod_ex(
+        MULMOD_NAMES[mulmod], a.ctypes.data_as(p), b.ctypes.data_as(p), a.size,
+        out.ctypes.data_as(p)))
     return out
 
 

@@ -158,6 +158,7 @@ SIGNATURES = {
     "nn_e40_generate": (_int, [_pu64, _u64, _vp, _int, _vp]),
     "nn_e40_generate_ex": (_int, [_pu64, _u64, _vp, _int, _vp, ctypes.POINTER(LaunchCfg)]),
     "nn_e40_debug_mulmod": (_int, [_pu64, _pu64, _u64, _pu64]),
+    "nn_e40_debug_mulmod_ex": (_int, [_int, _pu64, _pu64, _u64, _pu64]),
     "nn_dev_skip_table": (_int, [ctypes.POINTER(ctypes.c_void_p)]),
     "nn_strerror": (ctypes.c_char_p, [_int]),
     "nn_last_error": (ctypes.c_char_p, []),

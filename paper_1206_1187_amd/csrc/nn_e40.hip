@@ -127,36 +127,69 @@ struct E40Args {
     Mult40 J;       // (2^53)^(2T)
     Mult40 M1;      // 2^53
     Mult40 JI;      // J^IL
+    Mult40L JL, M1L, JIL;  // the same multipliers as base-B limbs
     const Mult40* t_lo;
     const Mult40* t_hi;
     uint64_t* head;       // 8-byte aligned output's first element, or null
     uint64_t head_state;  // its state
 };
 
-template <int KIND>
-__device__ __forceinline__ uint64_t bits40(uint64_t z) {
-    if constexpr (KIND == 0)
-        return z;
-    else
-        return (uint64_t)__double_as_longlong(to_f64(z));
-}
+// The two step reductions: MM 0 = Montgomery on 64-bit states, MM 1 = FP64
+// on base-B limbs.
+template <int MM>
+struct Step;
+template <>
+struct Step<0> {
+    typedef uint64_t S;
+    static __device__ __forceinline__ S from(uint64_t z) { return z; }
+    static __device__ __forceinline__ S mul(S z, const Mult40& v, const Mult40L&) {
+        return mm40(z, v.mont);
+    }
+    template <int KIND>
+    static __device__ __forceinline__ uint64_t bits(S z) {
+        if constexpr (KIND == 0)
+            return z;
+        else
+            return (uint64_t)__double_as_longlong(to_f64(z));
+    }
+};
+template <>
+struct Step<1> {
+    typedef L2 S;
+    static __device__ __forceinline__ S from(uint64_t z) { return limbs(z); }
+    static __device__ __forceinline__ S mul(S z, const Mult40&, const Mult40L& v) {
+        return mul40l(z, v);
+    }
+    template <int KIND>
+    static __device__ __forceinline__ uint64_t bits(S z) {
+        if constexpr (KIND == 0)
+            return to_u64(z);
+        else
+            return (uint64_t)__double_as_longlong(to_f64(z));
+    }
+};
 
-template <int KIND, int IL, int UNROLL, bool NT>
+template <int KIND, int MM, int IL, int UNROLL, bool NT>
 __global__ __launch_bounds__(1024) void k_e40(E40Args a) {
+    typedef Step<MM> St;
+    typedef typename St::S S;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0 && a.head) put<NT>(as_global(a.head), bits40<KIND>(a.head_state));
+    if (t == 0 && a.head) put<NT>(as_global(a.head), St::template bits<KIND>(St::from(a.head_state)));
     const uint32_t rem_pairs = a.rem >> 1;
     const bool extra_pair = t < rem_pairs;
     const bool extra_one = (a.rem & 1u) && t == rem_pairs;
     if (a.e_full == 0 && !extra_pair && !extra_one) return;
     const uint64_t k = 2ull * t;  // < 2^25
-    uint64_t za[IL], zb[IL];
-    za[0] = mm40(mm40(a.base, a.t_hi[k >> 10].mont), a.t_lo[k & (kLo - 1)].mont);
-    zb[0] = mm40(za[0], a.M1.mont);
+    // The thread's first pair by two table multiplications (Montgomery),
+    // then the step's own representation.
+    const uint64_t z0 = mm40(mm40(a.base, a.t_hi[k >> 10].mont), a.t_lo[k & (kLo - 1)].mont);
+    S za[IL], zb[IL];
+    za[0] = St::from(z0);
+    zb[0] = St::from(mm40(z0, a.M1.mont));
 #pragma unroll
     for (int r = 1; r < IL; ++r) {
-        za[r] = mm40(za[r - 1], a.J.mont);
-        zb[r] = mm40(zb[r - 1], a.J.mont);
+        za[r] = St::mul(za[r - 1], a.J, a.JL);
+        zb[r] = St::mul(zb[r - 1], a.J, a.JL);
     }
     const global_ptr<u64x2> out = reinterpret_cast<global_ptr<u64x2>>(as_global(a.out));
     global_ptr<u64x2> row = out;
@@ -164,28 +197,29 @@ __global__ __launch_bounds__(1024) void k_e40(E40Args a) {
     uint64_t i = 0;
 #pragma unroll UNROLL
     for (; i + IL <= a.e_full; i += IL) {
+        // each row: its store, then its two multiplications, kept in that
+        // order so stores leave the wave evenly spaced
 #pragma unroll
         for (int r = 0; r < IL; ++r) {
             u64x2 v;
-            v.x = bits40<KIND>(za[r]);
-            v.y = bits40<KIND>(zb[r]);
+            v.x = St::template bits<KIND>(za[r]);
+            v.y = St::template bits<KIND>(zb[r]);
             put<NT>(row + r * T + t, v);
+            za[r] = St::mul(za[r], a.JI, a.JIL);
+            zb[r] = St::mul(zb[r], a.JI, a.JIL);
+            __builtin_amdgcn_sched_barrier(0);
         }
         row += IL * T;
-#pragma unroll
-        for (int r = 0; r < IL; ++r) {
-            za[r] = mm40(za[r], a.JI.mont);
-            zb[r] = mm40(zb[r], a.JI.mont);
-        }
     }
+    // Rows left over (fewer than IL): the states before the last advance.
     const uint32_t left = (uint32_t)(a.e_full - i);
-    uint64_t pa = za[0], pb = zb[0];
+    S pa = za[0], pb = zb[0];
 #pragma unroll
     for (int r = 0; r < IL; ++r) {
         if ((uint32_t)r < left) {
             u64x2 v;
-            v.x = bits40<KIND>(za[r]);
-            v.y = bits40<KIND>(zb[r]);
+            v.x = St::template bits<KIND>(za[r]);
+            v.y = St::template bits<KIND>(zb[r]);
             put<NT>(row + r * T + t, v);
         }
         if ((uint32_t)r == left) {
@@ -196,48 +230,55 @@ __global__ __launch_bounds__(1024) void k_e40(E40Args a) {
     row += left * T;
     if (extra_pair) {
         u64x2 v;
-        v.x = bits40<KIND>(pa);
-        v.y = bits40<KIND>(pb);
+        v.x = St::template bits<KIND>(pa);
+        v.y = St::template bits<KIND>(pb);
         put<NT>(row + t, v);
     } else if (extra_one) {
-        put<NT>(reinterpret_cast<global_ptr<uint64_t>>(row + t), bits40<KIND>(pa));
+        put<NT>(reinterpret_cast<global_ptr<uint64_t>>(row + t), St::template bits<KIND>(pa));
     }
 }
 
-template <int KIND, int IL, int U, bool NT>
+template <int KIND, int MM, int IL, int U, bool NT>
 hipError_t launch_one(uint32_t grid, uint32_t block, hipStream_t s, const E40Args& a) {
-    k_e40<KIND, IL, U, NT><<<grid, block, 0, s>>>(a);
+    k_e40<KIND, MM, IL, U, NT><<<grid, block, 0, s>>>(a);
     return hipGetLastError();
 }
 
-template <int KIND, int IL, bool NT>
+template <int KIND, int MM, int IL, bool NT>
 hipError_t launch_u(int unroll, uint32_t grid, uint32_t block, hipStream_t s, const E40Args& a) {
     switch (unroll) {
-        case 1: return launch_one<KIND, IL, 1, NT>(grid, block, s, a);
-        case 2: return launch_one<KIND, IL, 2, NT>(grid, block, s, a);
-        case 4: return launch_one<KIND, IL, 4, NT>(grid, block, s, a);
+        case 1: return launch_one<KIND, MM, IL, 1, NT>(grid, block, s, a);
+        case 2: return launch_one<KIND, MM, IL, 2, NT>(grid, block, s, a);
+        case 4: return launch_one<KIND, MM, IL, 4, NT>(grid, block, s, a);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int KIND, bool NT>
+template <int KIND, int MM, bool NT>
 hipError_t launch_il(int ilp, int unroll, uint32_t grid, uint32_t block, hipStream_t s,
                      const E40Args& a) {
     switch (ilp) {
-        case 1: return launch_u<KIND, 1, NT>(unroll, grid, block, s, a);
-        case 2: return launch_u<KIND, 2, NT>(unroll, grid, block, s, a);
-        case 4: return launch_u<KIND, 4, NT>(unroll, grid, block, s, a);
+        case 1: return launch_u<KIND, MM, 1, NT>(unroll, grid, block, s, a);
+        case 2: return launch_u<KIND, MM, 2, NT>(unroll, grid, block, s, a);
+        case 4: return launch_u<KIND, MM, 4, NT>(unroll, grid, block, s, a);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch(int kind, int ilp, int unroll, bool nt, uint32_t grid, uint32_t block,
+template <int KIND, int MM>
+hipError_t launch_nt(int ilp, int unroll, bool nt, uint32_t grid, uint32_t block, hipStream_t s,
+                     const E40Args& a) {
+    return nt ? launch_il<KIND, MM, true>(ilp, unroll, grid, block, s, a)
+              : launch_il<KIND, MM, false>(ilp, unroll, grid, block, s, a);
+}
+
+hipError_t launch(int kind, int mm, int ilp, int unroll, bool nt, uint32_t grid, uint32_t block,
                   hipStream_t s, const E40Args& a) {
     if (kind == 0)
-        return nt ? launch_il<0, true>(ilp, unroll, grid, block, s, a)
-                  : launch_il<0, false>(ilp, unroll, grid, block, s, a);
-    return nt ? launch_il<1, true>(ilp, unroll, grid, block, s, a)
-              : launch_il<1, false>(ilp, unroll, grid, block, s, a);
+        return mm ? launch_nt<0, 1>(ilp, unroll, nt, grid, block, s, a)
+                  : launch_nt<0, 0>(ilp, unroll, nt, grid, block, s, a);
+    return mm ? launch_nt<1, 1>(ilp, unroll, nt, grid, block, s, a)
+              : launch_nt<1, 0>(ilp, unroll, nt, grid, block, s, a);
 }
 
 }  // namespace
@@ -280,19 +321,27 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
     nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
     if ((c.flags & ~(uint32_t)(NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS)) || c.occupancy ||
-        (c.width && c.width != 2) || (c.mulmod && c.mulmod != NN_MULMOD_MONTGOMERY))
-        return fail(NN_EINVAL, "the 3^40 generator takes block, grid, unroll, ilp and "
-                               "NN_CFG_TEMPORAL_STORES (rows, 16-byte stores, Montgomery)");
+        (c.width && c.width != 2) ||
+        (c.mulmod && c.mulmod != NN_MULMOD_MONTGOMERY && c.mulmod != NN_MULMOD_FP64))
+        return fail(NN_EINVAL, "the 3^40 generator takes block, grid, unroll, ilp, mulmod "
+                               "(NN_MULMOD_FP64 or NN_MULMOD_MONTGOMERY) and "
+                               "NN_CFG_TEMPORAL_STORES (rows, 16-byte stores)");
+    const int mm = c.mulmod == NN_MULMOD_MONTGOMERY ? 0 : 1;
     const uint32_t block = c.block ? c.block : 256u;
     if (block < 64 || block > 1024 || block % 64)
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
-    // Defaults from a sweep on MI355X (2^30 f64 outputs): 256 threads, two
-    // workgroups per CU, two rows in flight, no unrolling (4.8 TB/s; the
-    // Montgomery step makes this kernel compute-bound, unlike the 3^33 one).
-    const uint32_t unroll = c.unroll ? c.unroll : 1u;
+    // Defaults from sweeps on MI355X (2^30 f64 outputs, 256 threads):
+    //  * FP64 limb step: one workgroup per CU, two rows in flight, no
+    //    unrolling: 6.1-6.3 TB/s on two boxes (ilp 4 within 2 %).  Grids that
+    //    are not a multiple of the CU count lose badly (272 workgroups: 3.9
+    //    TB/s), since every workgroup carries the same number of rows;
+    //  * Montgomery: three workgroups per CU, four rows in flight, unroll 2:
+    //    5.6 TB/s (it needs more waves to hide its 64-bit multiplies).
+    const bool limb_step = mm == 1;
+    const uint32_t unroll = c.unroll ? c.unroll : (limb_step ? 1u : 2u);
     if (unroll != 1 && unroll != 2 && unroll != 4)
         return fail(NN_EINVAL, "unroll %u: must be 1, 2 or 4", unroll);
-    const uint32_t ilp = c.ilp ? c.ilp : 2u;
+    const uint32_t ilp = c.ilp ? c.ilp : (limb_step ? 2u : 4u);
     if (ilp != 1 && ilp != 2 && ilp != 4) return fail(NN_EINVAL, "ilp %u: must be 1, 2 or 4", ilp);
     const e40::Mult40* tab = nullptr;
     int st = e40::device_tables(&tab);
@@ -306,7 +355,7 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
     uint32_t grid = c.grid;
     if (!grid) {
         const uint64_t need = (n + 2ull * block - 1) / (2ull * block);
-        const uint64_t cap = (uint64_t)(d->cus > 0 ? d->cus : 1) * 2;
+        const uint64_t cap = (uint64_t)(d->cus > 0 ? d->cus : 1) * (limb_step ? 1 : 3);
         grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
     }
     if ((uint64_t)grid * block > e40::kMaxThreads)
@@ -324,9 +373,12 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
     a.J = e40::make_mult40(e40::Powers::get().pow(row));
     a.M1 = e40::make_mult40(e40::kMult);
     a.JI = e40::make_mult40(e40::Powers::get().pow(row * ilp));
+    a.JL = e40::make_mult40l(a.J.v);
+    a.M1L = e40::make_mult40l(a.M1.v);
+    a.JIL = e40::make_mult40l(a.JI.v);
     a.t_lo = tab;
     a.t_hi = tab + e40::kLo;
-    hipError_t e = e40::launch(kind, (int)ilp, (int)unroll, !(c.flags & NN_CFG_TEMPORAL_STORES),
+    hipError_t e = e40::launch(kind, mm, (int)ilp, (int)unroll, !(c.flags & NN_CFG_TEMPORAL_STORES),
                                grid, block, (hipStream_t)stream, a);
     if (e != hipSuccess) return fail(NN_EHIP, "e40 launch: %s", hipGetErrorString(e));
     *state = e40::h_mul(s, e40::Powers::get().pow(count));
@@ -337,14 +389,26 @@ int nn_e40_generate(uint64_t* state, uint64_t count, void* out_dev, int kind, vo
     return nn_e40_generate_ex(state, count, out_dev, kind, stream, nullptr);
 }
 
-int nn_e40_debug_mulmod(const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t* out) {
+int nn_e40_debug_mulmod_ex(int mulmod, const uint64_t* a, const uint64_t* b, uint64_t n,
+                           uint64_t* out) {
+    if (mulmod != NN_MULMOD_DEFAULT && mulmod != NN_MULMOD_FP64 && mulmod != NN_MULMOD_MONTGOMERY)
+        return fail(NN_EINVAL, "mulmod %d: the 3^40 step is NN_MULMOD_FP64 or NN_MULMOD_MONTGOMERY",
+                    mulmod);
     if (n && (!a || !b || !out)) return fail(NN_EINVAL, "NULL array");
     for (uint64_t i = 0; i < n; ++i)
         if (!e40::valid_state(a[i]) || !e40::valid_state(b[i]))
             return fail(NN_EINVAL, "pair %llu is not a pair of units modulo 3^40",
                         (unsigned long long)i);
-    for (uint64_t i = 0; i < n; ++i) out[i] = e40::mm40(a[i], e40::make_mult40(b[i]).mont);
+    if (mulmod == NN_MULMOD_MONTGOMERY)
+        for (uint64_t i = 0; i < n; ++i) out[i] = e40::mm40(a[i], e40::make_mult40(b[i]).mont);
+    else
+        for (uint64_t i = 0; i < n; ++i)
+            out[i] = e40::to_u64(e40::mul40l(e40::limbs(a[i]), e40::make_mult40l(b[i])));
     return ok();
+}
+
+int nn_e40_debug_mulmod(const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t* out) {
+    return nn_e40_debug_mulmod_ex(NN_MULMOD_MONTGOMERY, a, b, n, out);
 }
 
 }  // extern "C"

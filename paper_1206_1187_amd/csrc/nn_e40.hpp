@@ -51,5 +51,78 @@ NN_HD uint64_t mm40(uint64_t z, uint64_t vmont) {
 
 NN_HD double to_f64(uint64_t z) { return (double)z * kRecip; }
 
+// The FP64 step: base-B limbs, B = 3^20 < 2^32, m = B^2.  For a state
+// z = x1 B + x0 and a multiplier v = j1 B + j0 the term x1 j1 B^2 is a
+// multiple of m, so
+//     v z = (x1 j0 + x0 j1 + c) B + r   (mod m),   x0 j0 = c B + r,
+// three products of integers below 2^33, each reduced modulo B exactly in
+// FP64: the product as ph + pl (two-product, exact), a quotient rounded
+// from ph/B (off by at most one from the nearest), the remainder formed by
+// one FMA and one add, both exact because it is an integer below 2^34.
+// States stay redundant between steps: x0 = r in about [-B/2, B/2] and
+// x1 the unreduced sum, below 2.01 B in magnitude; canon() reduces both
+// limbs to [0, B) for output.  Multipliers are canonical: 0 <= j0, j1 < B.
+constexpr uint64_t kLimb = 3486784401ULL;  // 3^20
+constexpr double kB = 3486784401.0;
+constexpr double kRB = 1.0 / 3486784401.0;      // RN(1/B)
+constexpr double kHalfRB = 0.5 / 3486784401.0;  // RN(1/(2B)) = RN(1/B)/2
+static_assert(kLimb * kLimb == kMod, "3^40 = (3^20)^2");
+
+struct L2 {
+    double lo;  // x0
+    double hi;  // x1
+};
+
+struct Mult40L {
+    double j0;  // v mod B
+    double j1;  // v div B
+};
+
+// x j - q B for q the rounded quotient: x j mod B up to one B either way.
+NN_HD double rem_b(double x, double j, double* q_out) {
+    const double ph = x * j;
+    const double pl = __builtin_fma(x, j, -ph);
+    const double q = __builtin_rint(ph * kRB);
+    *q_out = q;
+    return __builtin_fma(-q, kB, ph) + pl;
+}
+
+NN_HD L2 mul40l(L2 z, Mult40L v) {
+    double c, qa, qb;
+    const double r = rem_b(z.lo, v.j0, &c);
+    const double ta = rem_b(z.hi, v.j0, &qa);
+    const double tb = rem_b(z.lo, v.j1, &qb);
+    return L2{r, ta + tb + c};
+}
+
+NN_HD L2 limbs(uint64_t z) { return L2{(double)(z % kLimb), (double)(z / kLimb)}; }
+
+// The canonical limbs (z = hi B + lo, 0 <= lo, hi < B) of a redundant state.
+// g = floor(x0 / B) is -1 or 0 (x0 is a nonzero integer in (-B, B)); the
+// quotient floor((y + 1/2) / B) of the carried x1 is at least 1/(2B) away
+// from an integer, far beyond its rounding error, so its floor is exact.
+NN_HD void canon(L2 z, double* hi, double* lo) {
+    const double g = __builtin_floor(z.lo * kRB);
+    *lo = __builtin_fma(-g, kB, z.lo);
+    const double y = z.hi + g;
+    const double f = __builtin_floor(__builtin_fma(y, kRB, kHalfRB));
+    *hi = __builtin_fma(-f, kB, y);
+}
+
+NN_HD uint64_t to_u64(L2 z) {
+    double hi, lo;
+    canon(z, &hi, &lo);
+    return (uint64_t)(uint32_t)hi * kLimb + (uint32_t)lo;
+}
+
+// RN(z) = RN(hi B + lo) is one FMA: the exact sum rounded once.
+NN_HD double to_f64(L2 z) {
+    double hi, lo;
+    canon(z, &hi, &lo);
+    return __builtin_fma(hi, kB, lo) * kRecip;
+}
+
+inline Mult40L make_mult40l(uint64_t v) { return Mult40L{(double)(v % kLimb), (double)(v / kLimb)}; }
+
 }  // namespace e40
 }  // namespace nn

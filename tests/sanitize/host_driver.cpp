@@ -5,6 +5,7 @@
 // oracle on edge and random inputs.  Built by tests/test_oracle_sanitized.py
 // with a host compiler only; test infrastructure.
 #include <stdint.h>
+#include <math.h>
 #include <stdio.h>
 
 #include "nn_e40.hpp"
@@ -91,6 +92,44 @@ int main() {
         const uint64_t s = unit(m40);
         CHECK(nn::e40::mm40(s, mont) == orc_e40_step(s));
         CHECK(nn::e40::to_f64(s) == orc_e40_to_f64(s));
+    }
+    // 3^40, the FP64 limb step: single products from canonical limbs, and
+    // long chains through the redundant form (the bounds the step relies
+    // on), against the oracle's exact products
+    const uint64_t l_edge[] = {1,           2,           nn::e40::kLimb - 1, nn::e40::kLimb + 1,
+                               m40 - 1,     m40 - 2,     nn::e40::kHalf,     nn::e40::kMult,
+                               m40 - nn::e40::kLimb + 1, (nn::e40::kLimb - 1) * nn::e40::kLimb + 1};
+    for (uint64_t v : l_edge)
+        for (uint64_t s : l_edge) {
+            const nn::e40::L2 r = nn::e40::mul40l(nn::e40::limbs(s), nn::e40::make_mult40l(v));
+            const uint64_t want = (uint64_t)(((nn::u128)s * v) % m40);
+            CHECK(nn::e40::to_u64(r) == want);
+            CHECK(nn::e40::to_f64(r) == orc_e40_to_f64(want));
+        }
+    for (int c = 0; c < 200; ++c) {
+        const uint64_t v = c < 100 ? unit(m40) : (c < 150 ? m40 - 1 - (uint64_t)c : orc_e40_skip(1, next64()));
+        const nn::e40::Mult40L mv = nn::e40::make_mult40l(v);
+        uint64_t want = unit(m40);
+        nn::e40::L2 s = nn::e40::limbs(want);
+        for (int k = 0; k < 5000; ++k) {
+            s = nn::e40::mul40l(s, mv);
+            want = (uint64_t)(((nn::u128)want * v) % m40);
+            CHECK(nn::e40::to_u64(s) == want);
+            CHECK(fabs(s.hi) < 2.01 * nn::e40::kB && fabs(s.lo) <= 0.5001 * nn::e40::kB);
+        }
+        CHECK(nn::e40::to_f64(s) == orc_e40_to_f64(want));
+    }
+    // the generator's own multiplier, stepped, against the oracle's steps
+    {
+        uint64_t z = 0;
+        CHECK(orc_e40_seed(ORC_E40_INDEX_MIN + 4242, &z) == 0);
+        nn::e40::L2 s = nn::e40::limbs(z);
+        const nn::e40::Mult40L m1 = nn::e40::make_mult40l(nn::e40::kMult);
+        for (int k = 0; k < 100000; ++k) {
+            s = nn::e40::mul40l(s, m1);
+            z = orc_e40_step(z);
+            CHECK(nn::e40::to_u64(s) == z && nn::e40::to_f64(s) == orc_e40_to_f64(z));
+        }
     }
     if (fails) {
         fprintf(stderr, "%d check(s) failed\n", fails);

@@ -62,12 +62,31 @@ def test_e40_host_build_of_montgomery_step_is_exact():
         for y in fixed:
             a.append(x)
             b.append(y)
-    got = nn.e40_debug_mulmod(a, b)
     want = np.array([x * y % M for x, y in zip(a, b)], dtype=np.uint64)
-    bad = np.nonzero(got != want)[0]
-    assert bad.size == 0, [(a[i], b[i], int(got[i])) for i in bad[:5]]
+    for mulmod in ("montgomery", "fp64"):
+        got = nn.e40_debug_mulmod(a, b, mulmod)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, [(mulmod, a[i], b[i], int(got[i])) for i in bad[:5]]
+        with pytest.raises(nn.NNError):
+            nn.e40_debug_mulmod([3], [5], mulmod)
     with pytest.raises(nn.NNError):
-        nn.e40_debug_mulmod([3], [5])
+        nn.e40_debug_mulmod([1], [1], "barrett")
+
+
+def test_e40_host_build_of_limb_step_at_limb_edges():
+    """The FP64 step splits operands into base-3^20 limbs: operands whose
+    limbs sit at 0, 1, B/2 and B - 1 (carries into and out of the high
+    limb), and multipliers of the generator itself (2^53 and its powers)."""
+    B = 3 ** 20
+    rng = random.Random(5)
+    limbs = [0, 1, 2, B // 2, B // 2 + 1, B - 2, B - 1]
+    vals = sorted({hi * B + lo for hi in limbs for lo in limbs if 0 < hi * B + lo < M})
+    vals = [v for v in vals if v % 3]
+    mults = vals + [pow(2 ** 53, k, M) for k in (1, 2, 3, 1024, 2 ** 25, rng.randrange(M))]
+    a = [x for x in vals for _ in mults]
+    b = [y for _ in vals for y in mults]
+    want = np.array([x * y % M for x, y in zip(a, b)], dtype=np.uint64)
+    assert np.array_equal(nn.e40_debug_mulmod(a, b, "fp64"), want)
 
 
 def test_e40_generate_validation_before_device():

@@ -50,7 +50,9 @@ def test_e40_bit_exact_shapes_and_tails():
     ref_u, _ = orc.e40_gen(z0, 300_000, "u64")
     ref_f, _ = orc.e40_gen(z0, 300_000, "f64")
     shapes = [dict(), dict(block=64, grid=3, ilp=1, unroll=1), dict(block=1024, grid=7, ilp=4, unroll=4),
-              dict(block=512, grid=129, ilp=2, unroll=2), dict(block=256, grid=1, ilp=4, unroll=1)]
+              dict(block=512, grid=129, ilp=2, unroll=2), dict(block=256, grid=1, ilp=4, unroll=1),
+              dict(mulmod="montgomery"), dict(mulmod="montgomery", block=64, grid=5, ilp=4, unroll=2),
+              dict(mulmod="fp64", block=128, grid=33, ilp=1, unroll=4)]
     for kw in shapes:
         cfg = nn.make_cfg(**kw)
         for count in (1, 2, 3, 511, 512, 513, 4097, 99_991, 300_000):
@@ -64,27 +66,35 @@ def test_e40_bit_exact_shapes_and_tails():
     assert np.array_equal(got, ref_f.view(np.uint64)[:99_991])
 
 
-def test_e40_chained_and_extreme_states():
-    for s in (1, 2, M - 1, M - 2, 2 ** 63 + 1, orc.e40_seed(orc.E40_INDEX_MAX)):
+@pytest.mark.parametrize("mulmod", ["fp64", "montgomery"])
+def test_e40_chained_and_extreme_states(mulmod):
+    cfg = nn.make_cfg(mulmod=mulmod)
+    B = 3 ** 20
+    # states at the ends of the range and with limbs at their ends
+    for s in (1, 2, M - 1, M - 2, 2 ** 63 + 1, orc.e40_seed(orc.E40_INDEX_MAX),
+              B - 1, B + 1, (B - 1) * B + 1, (B - 1) * B + B - 1):
         if s % 3 == 0:
             continue
         ref, zr = orc.e40_gen(s, 70_001, "u64")
         out = torch.empty(70_001, dtype=torch.uint64, device="cuda")
         z = s
         for lo, hi in ((0, 1), (1, 1000), (1000, 1001), (1001, 70_001)):
-            z = nn.e40_generate_into(z, out[lo:hi])
+            _say("e40 chained", mulmod, s, lo, hi)
+            z = nn.e40_generate_into(z, out[lo:hi], cfg=cfg)
         torch.cuda.synchronize()
         assert np.array_equal(_bits(out), ref), s
         assert z == zr
 
 
-def test_e40_large_sampled():
+@pytest.mark.parametrize("mulmod", ["fp64", "montgomery"])
+def test_e40_large_sampled(mulmod):
     """2^26 outputs in the default shape; windows of the output compared
     with the oracle started there by skip-ahead."""
     n = 1 << 26
     z0 = orc.e40_seed(orc.E40_INDEX_MIN + 987654321)
     out = torch.empty(n, dtype=torch.float64, device="cuda")
-    zn = nn.e40_generate_into(z0, out)
+    _say("e40 large", mulmod)
+    zn = nn.e40_generate_into(z0, out, cfg=nn.make_cfg(mulmod=mulmod))
     torch.cuda.synchronize()
     assert zn == orc.e40_skip(z0, n)
     flat = out.view(torch.int64)
@@ -100,7 +110,8 @@ def test_e40_large_sampled():
 def test_e40_config_validation():
     z0 = orc.e40_seed(orc.E40_INDEX_MIN)
     out = torch.empty(4096, dtype=torch.float64, device="cuda")
-    for cfg in [nn.make_cfg(layout="flat"), nn.make_cfg(width=1), nn.make_cfg(mulmod="fp64"),
+    for cfg in [nn.make_cfg(layout="flat"), nn.make_cfg(width=1), nn.make_cfg(mulmod="barrett"),
+                nn.make_cfg(mulmod="shoup"),
                 nn.make_cfg(unroll=8), nn.make_cfg(ilp=3), nn.make_cfg(block=100),
                 nn.make_cfg(occupancy=3), nn.make_cfg(grid=1 << 20, block=1024)]:
         with pytest.raises(nn.NNError):
