@@ -370,7 +370,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic_from_profile(),
-            "kernel": "k_generate f64 (%s)" % ["", "fp64", "barrett", "shoup", "montgomery"][cfg_f.mulmod],
+            "kernel": "k_generate2_ilp f64 (%s)" % ["", "fp64", "barrett", "shoup", "montgomery"][cfg_f.mulmod],
             "algorithmic_bytes_per_launch": 8 * case.count_f64,
         },
     }
@@ -381,6 +381,13 @@ def main():
         u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u, cfg=cfg_u), reps,
                             torch)
         extras["generate_u64_GBps"] = 8.0 * case.count_u64 / u_s / 1e9
+        # The flat layout at its defaults (chunks of four 512-output rows per
+        # workgroup, temporal stores, residency cap 4), same workload.
+        for kind, out in (("f64", out_f), ("u64", out_u)):
+            fl_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out,
+                                                          cfg=nn.make_cfg(layout="flat")), reps,
+                                 torch)
+            extras["flat_layout_%s_GBps" % kind] = 8.0 * out.numel() / fl_s / 1e9
         # The paper's "Constant" kernel (Section 4.2) with the generator's own
         # store pattern, and with the fastest pattern measured (flat).
         fill_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000), reps, torch)

@@ -74,9 +74,10 @@ typedef enum nn_mulmod {
  * Three layouts write the same values (serial order in memory):
  *  - rows (default): grid*block threads loop over rows of
  *    width*grid*block outputs, stepping by a jump multiplier;
- *  - flat (NN_CFG_FLAT): every 256-thread workgroup writes 512 consecutive
- *    outputs, two per lane in one 16-byte store, and exits (needs a 16-byte
- *    aligned output);
+ *  - flat (NN_CFG_FLAT): every 256-thread workgroup writes `unroll` rows of
+ *    512 consecutive outputs (one contiguous chunk), two per lane in one
+ *    16-byte store per row, and exits; workgroups are dispatched in address
+ *    order (needs a 16-byte aligned output);
  *  - consecutive (NN_CFG_CONSECUTIVE): the paper's per-thread loop (Section
  *    3.2): each thread makes `unroll` consecutive outputs with Eq. 3's own
  *    multiplier 2^53 and Section 3.1's Modified Barrett reduction; the
@@ -92,13 +93,17 @@ typedef enum nn_mulmod {
  * consecutive layout (0 selects it there).
  * unroll: 1, 2, 4 or 8 iterations of the step loop per trip (rows); outputs
  * per thread and tile, 2, 4, 8, 16 or 32 (consecutive, default 4 with 512
- * threads per workgroup).
- * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable (default:
- * non-temporal streaming stores); NN_CFG_ROWS / NN_CFG_FLAT force a layout.
+ * threads per workgroup); rows per workgroup, 1, 2, 4, 8 or 16 (flat,
+ * default 4).
+ * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable and
+ * NN_CFG_NONTEMPORAL_STORES makes them non-temporal streaming stores (at
+ * most one of the two; default: non-temporal, except temporal for the flat
+ * layout); NN_CFG_ROWS / NN_CFG_FLAT force a layout.
  * width: outputs per lane and store, 1 (8-byte stores) or 2 (16-byte
  * stores, needs a 16-byte aligned output) (rows; flat is always 2).
  * occupancy: 0, or a cap in [2,16] on resident workgroups per compute unit
- * (flat), enforced through unused dynamic LDS.
+ * (flat; 0 there means 4 for nn_generate, no cap for nn_fill), enforced
+ * through unused dynamic LDS.
  * Consecutive: width 2 (16-byte stores) on a 16-byte aligned output, else 1. 
  * ilp: rows each thread keeps in flight, 1, 2 or 4 (rows with width 2):
  * 2*ilp independent multiplication chains per lane. */
@@ -124,6 +129,7 @@ typedef struct nn_launch_cfg {
  * out[t + i*T] = z_(t*E + i + 1), not in serial order.  mulmod 0 or
  * NN_MULMOD_MODBARRETT; grid, width, ilp and occupancy must be 0. */
 #define NN_CFG_PAPER_STRIDED 16u
+#define NN_CFG_NONTEMPORAL_STORES 32u
 
 /* ---------------------------------------------------------------- host -- */
 

@@ -52,14 +52,17 @@ def init(device=0):
     _native.check(_native.lib().nn_init(int(device)))
 
 
-def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=False, width=0, layout=None,
+def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=None, width=0, layout=None,
              occupancy=0, ilp=0):
     """Launch configuration (include/nn.h, nn_launch_cfg); ``layout`` is
     None (library default), "flat", "rows", "consecutive" or "paper_strided"
-    (the paper's transposed order: out[t + i*T] = element t*E + i)."""
+    (the paper's transposed order: out[t + i*T] = element t*E + i).
+    ``temporal``: None keeps the layout's default store policy, True asks for
+    temporal stores, False for non-temporal ones."""
     if isinstance(mulmod, str):
         mulmod = MULMOD_NAMES[mulmod]
-    flags = _native.NN_CFG_TEMPORAL_STORES if temporal else 0
+    flags = {None: 0, True: _native.NN_CFG_TEMPORAL_STORES,
+             False: _native.NN_CFG_NONTEMPORAL_STORES}[temporal]
     if layout == "flat":
         flags |= _native.NN_CFG_FLAT
     elif layout == "rows":

@@ -33,16 +33,21 @@ struct Resolved {
 
 
 // `out` may be NULL (query of the defaults): it is then taken as aligned.
+// `fill`: nn_fill's resolution (its flat layout keeps one row per workgroup,
+// non-temporal stores and no residency cap unless asked).
 int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const DeviceTables& d,
-                const void* out, Resolved* r) {
+                const void* out, Resolved* r, bool fill = false) {
     const int cus = d.cus;
     const KindDefaults& kd = kind_defaults(kind);
     nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
     const bool aligned16 = ((uintptr_t)out % 16) == 0;
     const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE |
-                           NN_CFG_PAPER_STRIDED;
+                           NN_CFG_PAPER_STRIDED | NN_CFG_NONTEMPORAL_STORES;
     if (c.flags & ~known) return fail(NN_EINVAL, "unknown flags 0x%x", c.flags);
+    const uint32_t store_flags = c.flags & (NN_CFG_TEMPORAL_STORES | NN_CFG_NONTEMPORAL_STORES);
+    if (store_flags == (NN_CFG_TEMPORAL_STORES | NN_CFG_NONTEMPORAL_STORES))
+        return fail(NN_EINVAL, "NN_CFG_TEMPORAL_STORES and NN_CFG_NONTEMPORAL_STORES are exclusive");
     const uint32_t layouts =
         c.flags & (NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE | NN_CFG_PAPER_STRIDED);
     if (layouts & (layouts - 1)) return fail(NN_EINVAL, "the layout flags are exclusive");
@@ -123,7 +128,8 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     if (r->mulmod == NN_MULMOD_MODBARRETT)
         return fail(NN_EINVAL, "NN_MULMOD_MODBARRETT steps by 2^53 only: consecutive layout");
     if (r->mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", r->mulmod);
-    r->occupancy = c.occupancy;
+    r->flat = (c.flags & NN_CFG_FLAT) != 0;
+    r->occupancy = c.occupancy ? c.occupancy : (r->flat && !fill ? kFlatDefaultOccupancy : 0u);
     r->lds = 0;
     if (r->occupancy) {
         if (r->occupancy < 2 || r->occupancy > 16)
@@ -133,21 +139,30 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
         if (r->lds > d.lds_per_block || (uint64_t)r->lds * r->occupancy > d.lds_per_cu)
             return fail(NN_EINVAL, "occupancy %u not expressible on this device", r->occupancy);
     }
-    // The row layout is the default: its step loop hides the multiplication
-    // latency that bounds the flat layout (measured on MI355X).
-    r->flat = (c.flags & NN_CFG_FLAT) != 0;
     if (r->flat) {
         if (!aligned16)
             return fail(NN_EINVAL, "the flat layout needs a 16-byte aligned output (got %p)", out);
-        if ((c.block && c.block != kFlatBlock) || c.grid || c.unroll || (c.width && c.width != 2))
+        if ((c.block && c.block != kFlatBlock) || c.grid || (c.width && c.width != 2))
             return fail(NN_EINVAL, "the flat layout has a fixed shape (block 256, width 2)");
         if (c.ilp > 1) return fail(NN_EINVAL, "ilp applies to the row layout only");
         r->block = kFlatBlock;
         r->width = 2;
-        r->unroll = 1;
         r->ilp = 1;
+        if (fill) {
+            if (c.unroll) return fail(NN_EINVAL, "nn_fill's flat layout writes one row per workgroup");
+            r->unroll = 1;
+        } else {
+            // rows per workgroup, and temporal stores unless asked otherwise
+            // (the measured best, see kFlatDefaultRows)
+            r->unroll = c.unroll ? c.unroll : kFlatDefaultRows;
+            if (r->unroll == 0 || r->unroll > kFlatMaxRows || (r->unroll & (r->unroll - 1)))
+                return fail(NN_EINVAL, "unroll %u: the flat layout writes 1, 2, 4, 8 or 16 rows "
+                                       "per workgroup", r->unroll);
+            if (!store_flags) r->nontemporal = false;
+        }
         const uint64_t chunk = count < kFlatMaxCount ? count : kFlatMaxCount;
-        r->grid = (uint32_t)((chunk + kFlatPerBlock - 1) / kFlatPerBlock);
+        const uint64_t per = (uint64_t)kFlatPerBlock * r->unroll;
+        r->grid = (uint32_t)((chunk + per - 1) / per);
         if (!r->grid) r->grid = 1;
         return NN_OK;
     }
@@ -307,15 +322,17 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
     if (r.flat) {
         FlatArgs f;
         f.M1 = make_mult(kMult);
-        f.t_blk = d->t_blk;
-        f.t_lo = d->t_lo;
+        f.J = make_mult(MultPowers::get().pow(kFlatPerBlock));
+        f.tabs = d->t_lo;
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
             f.out = (uint64_t*)out_dev + off;
             f.count = n;
             f.base = h_skip(s, off + 1);  // the first output of this chunk
-            hipError_t e = launch_generate_flat((int)r.mulmod, kind, r.nontemporal, r.lds,
-                                                (hipStream_t)stream, f);
+            const uint64_t per = (uint64_t)kFlatPerBlock * r.unroll;
+            f.tail_base = h_skip(f.base, n / per * per);
+            hipError_t e = launch_generate_flat((int)r.mulmod, kind, r.nontemporal, (int)r.unroll,
+                                                r.lds, (hipStream_t)stream, f);
             if (e != hipSuccess)
                 return fail(NN_EHIP, "generate launch: %s", hipGetErrorString(e));
         }
@@ -410,7 +427,7 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r);
+    st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r, true);
     if (st) return st;
     if (r.consec || r.strided) return fail(NN_EINVAL, "nn_fill has no consecutive layout");
     if (r.flat) {

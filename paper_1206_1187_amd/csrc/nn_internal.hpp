@@ -23,7 +23,8 @@ struct DeviceTables {
     Mult* t_hi = nullptr;       // kHiSize entries
     Mult* t_sk = nullptr;       // kSkipLevels * kSkipSize entries
     double* t8 = nullptr;       // kSkip8Levels * kSkip8Size * 3 doubles
-    uint64_t* t_blk = nullptr;  // kFlatMaxBlocks entries (flat layout)
+    Mult* t_flo = nullptr;      // kFlatLoSize entries (flat layout)
+    Mult* t_fhi = nullptr;      // kFlatHiSize entries (flat layout)
     int cus = 0;
     uint32_t lds_per_cu = 0;
     uint32_t lds_per_block = 0;

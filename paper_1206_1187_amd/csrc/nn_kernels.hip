@@ -256,31 +256,79 @@ __global__ __launch_bounds__(1024) void k_fill(uint64_t* __restrict__ out, uint6
     }
 }
 
-// Flat layout (see launch_generate_flat).  The workgroup's start state
-// depends only on uniform values, so its integer product runs on the scalar
-// unit; each lane then needs one multiplication per output.
-template <class V, int KIND, bool NT>
-__global__ __launch_bounds__(kFlatBlock) void k_generate_flat(uint64_t* __restrict__ out,
-                                                              uint64_t count, uint64_t base,
-                                                              Mult M1,
-                                                              const uint64_t* __restrict__ t_blk,
-                                                              const Mult* __restrict__ t_lo) {
+// Flat layout (see launch_generate_flat).  Workgroup b writes the R rows of
+// kFlatPerBlock outputs from element kFlatPerBlock*R*b on, lane l the pair
+// 2l of each row, and exits.  Its start is two multiplications by uniform
+// table entries (scalar loads that hit L2), then one by the lane's offset;
+// after that one multiplication per output.  Each row: its store, then the
+// two multiplications to the next.
+//
+// A workgroup lives a few microseconds, so its start must not wait on more
+// round trips of scalar-load latency than needed: the table allocation and
+// the base lead the arguments (one scalar load fetches both), the whole-chunk
+// kernel takes no count and tests nothing, and the table indices are in
+// range for every lane.  A ragged last chunk goes to k_generate_flat_tail.
+template <class V>
+__device__ __forceinline__ void flat_start(uint64_t b, uint32_t l, int R, uint64_t base,
+                                           const Mult* __restrict__ tabs, const Mult& M1,
+                                           typename V::S& za, typename V::S& zb) {
+    const uint64_t u = b * (uint64_t)R;  // rows before the chunk, < kFlatMaxRowsPerLaunch
+    const Mult hi = tabs[kFlatHiOffset + u / kFlatLoSize];
+    const Mult lo = tabs[kFlatLoOffset + u % kFlatLoSize];
+    const Mult lane = tabs[2u * l];  // t_lo: (2^53)^(2l)
+    za = V::mul(V::mul(V::mul(V::load(base), hi), lo), lane);
+    zb = V::mul(za, M1);
+}
+
+template <class V, int KIND, bool NT, int R>
+__global__ __launch_bounds__(kFlatBlock) void k_generate_flat(const Mult* __restrict__ tabs,
+                                                              uint64_t base,
+                                                              uint64_t* __restrict__ out,
+                                                              Mult M1, Mult J) {
     extern __shared__ char occupancy_cap[];  // dynamic LDS only limits residency
     (void)occupancy_cap;
     const uint64_t b = blockIdx.x;
-    const uint64_t z_blk = mm_barrett(base, t_blk[b]);
     const uint32_t l = threadIdx.x;
-    const uint64_t k = (uint64_t)kFlatPerBlock * b + 2u * l;
-    if (k >= count) return;
-    const typename V::S za = V::mul(V::load(z_blk), t_lo[2u * l]);
-    if (k + 1 < count) {
-        const typename V::S zb = V::mul(za, M1);
+    typename V::S za, zb;
+    flat_start<V>(b, l, R, base, tabs, M1, za, zb);
+    u64x2* p = reinterpret_cast<u64x2*>(out + (uint64_t)kFlatPerBlock * R * b + 2u * l);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
         u64x2 v;
         v.x = out_bits<V, KIND>(za);
         v.y = out_bits<V, KIND>(zb);
-        put<NT>(reinterpret_cast<u64x2*>(out + k), v);
-    } else {
-        put<NT>(out + k, out_bits<V, KIND>(za));
+        put<NT>(p + r * kFlatBlock, v);
+        if (r + 1 < R) {
+            za = V::mul(za, J);
+            zb = V::mul(zb, J);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The last, partial chunk: `count` < kFlatPerBlock*R outputs from `out`,
+// one workgroup (b = 0 relative to `base`).
+template <class V, int KIND, bool NT, int R>
+__global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(const Mult* __restrict__ tabs,
+                                                                   uint64_t base,
+                                                                   uint64_t* __restrict__ out,
+                                                                   Mult M1, Mult J,
+                                                                   uint64_t count) {
+    const uint32_t l = threadIdx.x;
+    typename V::S za, zb;
+    flat_start<V>(0, l, R, base, tabs, M1, za, zb);
+    uint64_t k = 2u * l;
+    for (int r = 0; r < R && k < count; ++r, k += kFlatPerBlock) {
+        if (k + 1 < count) {
+            u64x2 v;
+            v.x = out_bits<V, KIND>(za);
+            v.y = out_bits<V, KIND>(zb);
+            put<NT>(reinterpret_cast<u64x2*>(out + k), v);
+        } else {
+            put<NT>(out + k, out_bits<V, KIND>(za));
+        }
+        za = V::mul(za, J);
+        zb = V::mul(zb, J);
     }
 }
 
@@ -301,27 +349,53 @@ __global__ __launch_bounds__(kFlatBlock) void k_fill_flat(uint64_t* __restrict__
     }
 }
 
-template <class V, int KIND, bool NT>
+template <class V, int KIND, bool NT, int R>
 static hipError_t flat_one(uint32_t lds, hipStream_t s, const FlatArgs& a) {
-    const uint32_t grid = (uint32_t)((a.count + kFlatPerBlock - 1) / kFlatPerBlock);
-    hipLaunchKernelGGL((k_generate_flat<V, KIND, NT>), dim3(grid), dim3(kFlatBlock), lds, s,
-                       a.out, a.count, a.base, a.M1, a.t_blk, a.t_lo);
-    return hipGetLastError();
+    const uint64_t per = (uint64_t)kFlatPerBlock * R;
+    const uint64_t full = a.count / per;  // whole chunks
+    const uint64_t tail = a.count - full * per;
+    if (full) {
+        hipLaunchKernelGGL((k_generate_flat<V, KIND, NT, R>), dim3((uint32_t)full),
+                           dim3(kFlatBlock), lds, s, a.tabs, a.base, a.out, a.M1, a.J);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (tail) {
+        // the tail chunk starts full*R rows in: its own base, one workgroup
+        hipLaunchKernelGGL((k_generate_flat_tail<V, KIND, NT, R>), dim3(1), dim3(kFlatBlock), 0,
+                           s, a.tabs, a.tail_base, a.out + full * per, a.M1, a.J, tail);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <class V, int KIND, bool NT>
+static hipError_t flat_r(int rows, uint32_t lds, hipStream_t s, const FlatArgs& a) {
+    switch (rows) {
+        case 1: return flat_one<V, KIND, NT, 1>(lds, s, a);
+        case 2: return flat_one<V, KIND, NT, 2>(lds, s, a);
+        case 4: return flat_one<V, KIND, NT, 4>(lds, s, a);
+        case 8: return flat_one<V, KIND, NT, 8>(lds, s, a);
+        case 16: return flat_one<V, KIND, NT, 16>(lds, s, a);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <class V>
-static hipError_t flat_v(int kind, bool nt, uint32_t lds, hipStream_t s, const FlatArgs& a) {
-    if (kind == 0) return nt ? flat_one<V, 0, true>(lds, s, a) : flat_one<V, 0, false>(lds, s, a);
-    return nt ? flat_one<V, 1, true>(lds, s, a) : flat_one<V, 1, false>(lds, s, a);
+static hipError_t flat_v(int kind, bool nt, int rows, uint32_t lds, hipStream_t s,
+                         const FlatArgs& a) {
+    if (kind == 0)
+        return nt ? flat_r<V, 0, true>(rows, lds, s, a) : flat_r<V, 0, false>(rows, lds, s, a);
+    return nt ? flat_r<V, 1, true>(rows, lds, s, a) : flat_r<V, 1, false>(rows, lds, s, a);
 }
 
-hipError_t launch_generate_flat(int mulmod, int kind, bool nt, uint32_t lds, hipStream_t s,
-                                const FlatArgs& a) {
+hipError_t launch_generate_flat(int mulmod, int kind, bool nt, int rows, uint32_t lds,
+                                hipStream_t s, const FlatArgs& a) {
     switch (mulmod) {
-        case 1: return flat_v<VarFP64>(kind, nt, lds, s, a);
-        case 2: return flat_v<VarBarrett>(kind, nt, lds, s, a);
-        case 3: return flat_v<VarShoup>(kind, nt, lds, s, a);
-        case 4: return flat_v<VarMontgomery>(kind, nt, lds, s, a);
+        case 1: return flat_v<VarFP64>(kind, nt, rows, lds, s, a);
+        case 2: return flat_v<VarBarrett>(kind, nt, rows, lds, s, a);
+        case 3: return flat_v<VarShoup>(kind, nt, rows, lds, s, a);
+        case 4: return flat_v<VarMontgomery>(kind, nt, rows, lds, s, a);
         default: return hipErrorInvalidValue;
     }
 }

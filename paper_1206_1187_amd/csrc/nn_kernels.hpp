@@ -48,27 +48,50 @@ hipError_t launch_generate(int mulmod, int kind, int width, int unroll, int ilp,
 hipError_t launch_consume(int mulmod, int kind, uint32_t grid, uint32_t block, hipStream_t s,
                           const GenArgs& a, void* result);
 
-// Flat layout: workgroup b of 256 threads writes elements
-// [512 b, 512 b + 512) of the launch, two consecutive ones per lane in one
-// 16-byte store, and exits; every workgroup starts from
-// base * t_blk[b] with t_blk[b] = (2^53)^(512 b), b < kFlatMaxBlocks.
+// Flat layout: workgroup b of 256 threads writes R rows of 512 elements,
+// [512 R b, 512 R (b + 1)) of the launch, two consecutive ones per lane in
+// one 16-byte store per row, and exits.  Its chunk starts u = R b rows of
+// 512 in, from base * t_fhi[u >> 10] * t_flo[u & 1023] with
+// t_flo[j] = (2^53)^(512 j) and t_fhi[i] = (2^53)^(512 * 1024 i): two small
+// tables that stay in L2 (a workgroup lives a few microseconds, so its start
+// must not wait on DRAM).
 constexpr uint32_t kFlatBlock = 256;
 constexpr uint32_t kFlatPerBlock = 2 * kFlatBlock;
-constexpr uint64_t kFlatMaxBlocks = 1ull << 21;
-constexpr uint64_t kFlatMaxCount = kFlatMaxBlocks * kFlatPerBlock;  // 2^30 per launch
+constexpr uint32_t kFlatLoSize = 1024;
+constexpr uint32_t kFlatHiSize = 2048;
+constexpr uint64_t kFlatMaxRowsPerLaunch = (uint64_t)kFlatLoSize * kFlatHiSize;  // 2^21
+// The device tables are one allocation of Mult entries: t_lo (kLoSize),
+// t_hi (kHiSize), the four 8192-entry skip levels, then t_flo and t_fhi.
+// The flat kernels take the allocation's start and these fixed offsets, so
+// one kernel-argument load gives them every table.
+constexpr uint64_t kFlatLoOffset = (uint64_t)kLoSize + kHiSize + 4ull * 8192ull;
+constexpr uint64_t kFlatHiOffset = kFlatLoOffset + kFlatLoSize;
+constexpr uint64_t kFlatMaxCount = kFlatMaxRowsPerLaunch * kFlatPerBlock;  // 2^30 per launch
+
+// Rows per workgroup of the flat layout: 1, 2, 4, 8 or 16.  Defaults from
+// sweeps on MI355X (2^30 f64 outputs): four rows (16 KiB per workgroup) and
+// temporal stores, with the residency cap of occupancy 4 (33 280 bytes of
+// dynamic LDS per workgroup).  The rate has a cliff in the LDS per
+// workgroup: 6.2-6.35 TB/s at 31 744 bytes or less, 7.4-7.5 TB/s from
+// 32 256 to 40 960 bytes; non-temporal stores stay at 6.2-6.4 throughout.
+constexpr uint32_t kFlatMaxRows = 16;
+constexpr uint32_t kFlatDefaultRows = 4;
+constexpr uint32_t kFlatDefaultOccupancy = 4;
 
 struct FlatArgs {
     uint64_t* out;   // 16-byte aligned
     uint64_t count;  // <= kFlatMaxCount
-    uint64_t base;
-    Mult M1;
-    const uint64_t* t_blk;
-    const Mult* t_lo;
+    uint64_t base;   // state of out[0]
+    uint64_t tail_base;  // state of the first output of the partial last chunk, if any
+    Mult M1;         // 2^53
+    Mult J;          // (2^53)^kFlatPerBlock: the next row of a lane
+    const Mult* tabs;   // the device tables: t_lo at 0, t_flo and t_fhi at their offsets
 };
 
-// lds_bytes > 0 caps the resident workgroups per compute unit.
-hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, uint32_t lds_bytes,
-                                hipStream_t stream, const FlatArgs& a);
+// rows: rows per workgroup (1, 2, 4, 8, 16); lds_bytes > 0 caps the
+// resident workgroups per compute unit.
+hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, int rows,
+                                uint32_t lds_bytes, hipStream_t stream, const FlatArgs& a);
 hipError_t launch_fill_flat(bool nontemporal, uint32_t lds_bytes, hipStream_t stream,
                             uint64_t* out, uint64_t count, uint64_t value);
 

@@ -108,16 +108,18 @@ const std::vector<double>& host_skip8_table() {
     return tab;
 }
 
-// Host copy of the flat layout's workgroup multipliers (2^53)^(512 b).
-const std::vector<uint64_t>& host_block_table() {
-    static std::vector<uint64_t> tab = [] {
-        std::vector<uint64_t> t(kFlatMaxBlocks);
-        const uint64_t step = MultPowers::get().pow(kFlatPerBlock);
+// Host copy of the flat layout's chunk multipliers: (2^53)^(512 j) for
+// j < kFlatLoSize, then (2^53)^(512 kFlatLoSize i) for i < kFlatHiSize.
+const std::vector<Mult>& host_flat_tables() {
+    static std::vector<Mult> tab = [] {
+        std::vector<Mult> t(kFlatLoSize + kFlatHiSize);
+        const uint64_t row = MultPowers::get().pow(kFlatPerBlock);
         uint64_t p = 1;
-        for (uint64_t b = 0; b < kFlatMaxBlocks; ++b) {
-            t[b] = p;
-            p = h_mulmod(p, step);
-        }
+        for (uint32_t j = 0; j < kFlatLoSize; ++j, p = h_mulmod(p, row)) t[j] = make_mult(p);
+        const uint64_t big = p;  // (2^53)^(512 kFlatLoSize)
+        p = 1;
+        for (uint32_t i = 0; i < kFlatHiSize; ++i, p = h_mulmod(p, big))
+            t[kFlatLoSize + i] = make_mult(p);
         return t;
     }();
     return tab;
@@ -137,10 +139,10 @@ int ensure_device_current(int dev, DeviceTables** out) {
             return fail(NN_ENODEV, "device %d is %s, this library is built for gfx950", dev,
                         prop.gcnArchName);
         const std::vector<Mult>& h = host_mult_tables();
-        const std::vector<uint64_t>& hb = host_block_table();
+        const std::vector<Mult>& hb = host_flat_tables();
         const std::vector<double>& h8 = host_skip8_table();
         const size_t mult_bytes = h.size() * sizeof(Mult);
-        const size_t blk_bytes = hb.size() * sizeof(uint64_t);
+        const size_t blk_bytes = hb.size() * sizeof(Mult);
         const size_t t8_bytes = h8.size() * sizeof(double);
         void* mem = nullptr;
         e = hipMalloc(&mem, mult_bytes + blk_bytes + t8_bytes);
@@ -158,7 +160,10 @@ int ensure_device_current(int dev, DeviceTables** out) {
         d.t_lo = (Mult*)mem;
         d.t_hi = d.t_lo + kLoSize;
         d.t_sk = d.t_hi + kHiSize;
-        d.t_blk = (uint64_t*)((char*)mem + mult_bytes);
+        d.t_flo = (Mult*)((char*)mem + mult_bytes);
+        d.t_fhi = d.t_flo + kFlatLoSize;
+        static_assert(kFlatLoOffset == (uint64_t)kLoSize + kHiSize + kSkipLevels * kSkipSize,
+                      "the flat tables follow the skip tables");
         d.t8 = (double*)((char*)mem + mult_bytes + blk_bytes);
         d.cus = prop.multiProcessorCount;
         d.lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;

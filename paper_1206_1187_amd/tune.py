@@ -123,6 +123,24 @@ def pick_plain_grid(cfg, out, state, deltas, rounds=3, reps=5):
     return min(cands, key=lambda c: times[c.grid]), times
 
 
+def pick_plain_layout(cfg, out, state, rounds=3, reps=5):
+    """`cfg` (a row-layout nn_launch_cfg) or the flat layout at its library
+    defaults (fields 0: four 512-output rows per workgroup, temporal stores,
+    residency cap 4), whichever runs faster on the current device; the flat
+    layout needs a 16-byte aligned output, else `cfg` is kept.  Returns
+    (cfg, {"rows": ms, "flat": ms})."""
+    import paper_1206_1187_amd as nn
+    if out.data_ptr() % 16:
+        return cfg, {}
+    flat = nn.make_cfg(layout="flat", mulmod=int(cfg.mulmod))
+    cands = {"rows": cfg, "flat": flat}
+    times = {k: float("inf") for k in cands}
+    for _ in range(rounds):
+        for k, c in cands.items():
+            times[k] = min(times[k], _min_ms(lambda: nn.generate_into(state, out, cfg=c), reps, 1))
+    return cands[min(times, key=times.get)], times
+
+
 def pick_batch_grid(kw, kind, states, lengths, offsets, out, rounds=2, reps=3):
     """BatchPlan keyword arguments `kw` with the grid (or a neighbour one
     cluster away, the cluster kept) that replays fastest on the current

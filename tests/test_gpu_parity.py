@@ -135,22 +135,29 @@ def test_output_alignment():
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_flat_layout_bit_exact(variant):
-    """The flat layout (one 512-output workgroup each) for every reduction,
-    both kinds, ragged tails and residency caps."""
+    """The flat layout (workgroups of 1-16 rows of 512 outputs) for every
+    reduction, both kinds, ragged tails around the row and chunk sizes,
+    residency caps and both store policies."""
     z0 = orc.seed(wl.INDEX_MIN + 31337)
     ref_u, _ = orc.gen(z0, 300_000, "u64", threads=0)
     ref_f, _ = orc.gen(z0, 300_000, "f64", threads=0)
-    for count in (1, 2, 3, 511, 512, 513, 1023, 1024, 1025, 3 * 512 + 1, 99_991, 300_000):
-        for occ in (0, 3):
-            cfg = nn.make_cfg(mulmod=variant, layout="flat", occupancy=occ)
-            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
-                got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=512)
-                assert np.array_equal(got, ref.view(np.uint64)[:count]), (variant, count, occ, kind)
-                assert zn == orc.skip(z0, count)
-    # temporal stores write the same values
-    got, _ = _gen_guarded(z0, 99_991, "f64", cfg=nn.make_cfg(mulmod=variant, layout="flat",
-                                                            temporal=True))
-    assert np.array_equal(got, ref_f.view(np.uint64)[:99_991])
+    counts = (1, 2, 3, 511, 512, 513, 1023, 1024, 1025, 3 * 512 + 1, 2047, 2048, 2049, 8191,
+              8193, 99_991, 300_000)
+    for rows in (0, 1, 2, 4, 16):
+        for count in counts:
+            for occ in (0, 3):
+                cfg = nn.make_cfg(mulmod=variant, layout="flat", occupancy=occ, unroll=rows)
+                for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                    _say("flat", variant, rows, count, occ, kind)
+                    got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=512)
+                    assert np.array_equal(got, ref.view(np.uint64)[:count]), \
+                        (variant, rows, count, occ, kind)
+                    assert zn == orc.skip(z0, count)
+        # both store policies write the same values
+        for temporal in (True, False):
+            cfg = nn.make_cfg(mulmod=variant, layout="flat", unroll=rows, temporal=temporal)
+            got, _ = _gen_guarded(z0, 99_991, "f64", cfg=cfg)
+            assert np.array_equal(got, ref_f.view(np.uint64)[:99_991]), (rows, temporal)
 
 
 def test_config_validation():
@@ -161,10 +168,16 @@ def test_config_validation():
            nn.make_cfg(width=3), nn.make_cfg(occupancy=1), nn.make_cfg(occupancy=17),
            nn.make_cfg(layout="rows", occupancy=4), nn.make_cfg(mulmod=9),
            nn.make_cfg(ilp=3), nn.make_cfg(width=1, ilp=2), nn.make_cfg(layout="flat", ilp=2),
-           nn.make_cfg(grid=1 << 20, block=1024)]
+           nn.make_cfg(grid=1 << 20, block=1024), nn.make_cfg(layout="flat", unroll=3),
+           nn.make_cfg(layout="flat", unroll=32), nn.make_cfg(layout="flat", grid=4)]
+    both = nn.make_cfg(layout="flat", temporal=True)
+    both.flags |= nn._native.NN_CFG_NONTEMPORAL_STORES
+    bad.append(both)
     for cfg in bad:
         with pytest.raises(nn.NNError):
             nn.generate_into(z0, out, cfg=cfg)
+    with pytest.raises(nn.NNError):  # nn_fill's flat layout has one row per workgroup
+        nn.fill(out, 0, cfg=nn.make_cfg(layout="flat", unroll=4))
     with pytest.raises(nn.NNError):
         nn.generate_into(z0, out[1:].view(torch.float64), cfg=nn.make_cfg(layout="flat"))
     d = nn.default_cfg("f64", 1 << 30)
@@ -287,12 +300,16 @@ def test_plain_bulk_full_size_bench_grids_sampled(kind, deltas):
     torch.cuda.empty_cache()
 
 
-def test_flat_chunk_boundary_beyond_one_launch():
+@pytest.mark.parametrize("layout,rows", [(None, 0), ("flat", 4), ("flat", 16)])
+def test_flat_chunk_boundary_beyond_one_launch(layout, rows):
     """Counts above one flat launch (2^30 outputs) are split into several
-    launches; check the outputs on both sides of every split and the tail."""
+    launches; check the outputs on both sides of every split and the tail
+    (and the default layout at the same count)."""
     z0 = orc.seed(wl.plain_bulk().index + 5)
     count = (1 << 30) + 4099
-    out, zn = nn.generate(z0, count, "f64")
+    _say("beyond one launch", layout, rows)
+    out = torch.empty(count, dtype=torch.float64, device="cuda")
+    zn = nn.generate_into(z0, out, cfg=nn.make_cfg(layout=layout, unroll=rows))
     torch.cuda.synchronize()
     assert zn == orc.skip(z0, count)
     flat = out.view(torch.int64)
