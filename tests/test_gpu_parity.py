@@ -160,6 +160,25 @@ def test_flat_layout_bit_exact(variant):
             assert np.array_equal(got, ref_f.view(np.uint64)[:99_991]), (rows, temporal)
 
 
+def test_pick_plain_layout_returns_a_working_cfg():
+    """tune.pick_plain_layout times the row and flat layouts and returns the
+    faster; whichever it returns writes the oracle's values."""
+    from paper_1206_1187_amd import tune
+    z0 = orc.seed(wl.INDEX_MIN + 777)
+    n = 1 << 20
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    cfg, times = tune.pick_plain_layout(nn.default_cfg("f64", n), out, z0, rounds=1, reps=2)
+    assert set(times) == {"rows", "flat"} and all(t > 0 for t in times.values())
+    zn = nn.generate_into(z0, out, cfg=cfg)
+    torch.cuda.synchronize()
+    assert zn == orc.skip(z0, n)
+    ref, _ = orc.gen(z0, 8192, "f64", threads=0)
+    assert np.array_equal(_bits(out)[:8192], ref.view(np.uint64))
+    # an output that is only 8-byte aligned keeps the row layout
+    cfg2, times2 = tune.pick_plain_layout(nn.default_cfg("f64", n - 1), out[1:], z0)
+    assert times2 == {} and not (cfg2.flags & nn._native.NN_CFG_FLAT)
+
+
 def test_config_validation():
     z0 = orc.seed(wl.INDEX_MIN)
     out = torch.empty(4096, dtype=torch.float64, device="cuda")
