@@ -5,7 +5,7 @@ One step is the whole plain path over the bulk workload: seed a starting
 index (Eq. 2), generate 2^30 binary64 variates and then 2^28 raw uint64
 states from that seed (Eq. 3 with per-thread skip-ahead), with the outputs
 resident in HBM.  The JSON line reports whole-job variates/s, the
-roofline of the dominant kernel (the f64 generator) measured with HIP events
+roofline of the dominant kernel (the f64 generator, flat layout) measured with HIP events
 on the launch stream, the paper's "Constant" write ceiling for the same
 store pattern (Section 4.2), a comparison of the exact reductions, and the
 CPU oracle timed on the host cores.
@@ -23,7 +23,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 METRIC = "uniform variates/sec at 1 GPU and % of HBM write BW; batched/served vs plain"
 # Profile summary holding the HBM byte counters of the dominant kernel.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_generate2_ilp_fp64_f64.plain_bulk.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_generate_flat_fp64_f64.plain_bulk.md")
 # Every source the dominant kernel is compiled from: its counters are void
 # once any of them changes.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1206_1187_amd", "csrc", f)
@@ -299,15 +299,18 @@ def main():
     case = wl.plain_bulk()
     out_f = torch.empty(case.count_f64, dtype=torch.float64, device="cuda")
     out_u = torch.empty(case.count_u64, dtype=torch.uint64, device="cuda")
-    cfg_f = nn.default_cfg("f64", case.count_f64)
+    # f64: the flat layout (chunks of four 512-output rows per workgroup,
+    # temporal stores, residency cap 4), faster than the row kernel on every
+    # box measured; u64: the row kernel, with its grid chosen on the device.
+    cfg_f = nn.make_cfg(layout="flat", mulmod="fp64", unroll=4, occupancy=4)
+    cfg_rows_f = nn.default_cfg("f64", case.count_f64)
     cfg_u = nn.default_cfg("u64", case.count_u64)
     picked = None
     if not args.no_shape_pick:
         from paper_1206_1187_amd import tune
         s0 = nn.seed(case.index)
-        cfg_f, pf = tune.pick_plain_grid(cfg_f, out_f, s0, (0, -16, 16))
         cfg_u, pu = tune.pick_plain_grid(cfg_u, out_u, s0, (0, -32, 32))
-        picked = {"f64_grid_ms": pf, "u64_grid_ms": pu}
+        picked = {"u64_grid_ms": pu}
         log("grid choice", json.dumps(picked))
     log("workload", case, "cfg f64", cfg_f.as_dict(), "cfg u64", cfg_u.as_dict())
 
@@ -370,7 +373,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic_from_profile(),
-            "kernel": "k_generate2_ilp f64 (%s)" % ["", "fp64", "barrett", "shoup", "montgomery"][cfg_f.mulmod],
+            "kernel": "k_generate_flat f64 (fp64, 4 rows per workgroup)",
             "algorithmic_bytes_per_launch": 8 * case.count_f64,
         },
     }
@@ -381,13 +384,14 @@ def main():
         u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u, cfg=cfg_u), reps,
                             torch)
         extras["generate_u64_GBps"] = 8.0 * case.count_u64 / u_s / 1e9
-        # The flat layout at its defaults (chunks of four 512-output rows per
-        # workgroup, temporal stores, residency cap 4), same workload.
-        for kind, out in (("f64", out_f), ("u64", out_u)):
-            fl_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out,
-                                                          cfg=nn.make_cfg(layout="flat")), reps,
-                                 torch)
-            extras["flat_layout_%s_GBps" % kind] = 8.0 * out.numel() / fl_s / 1e9
+        # The other layout of each kind on the same workload: the row kernel
+        # (tuned shape) for f64, the flat layout for u64.
+        rows_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_f,
+                                                        cfg=cfg_rows_f), reps, torch)
+        extras["rows_layout_f64_GBps"] = 8.0 * case.count_f64 / rows_s / 1e9
+        fl_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u,
+                                                      cfg=nn.make_cfg(layout="flat")), reps, torch)
+        extras["flat_layout_u64_GBps"] = 8.0 * case.count_u64 / fl_s / 1e9
         # The paper's "Constant" kernel (Section 4.2) with the generator's own
         # store pattern, and with the fastest pattern measured (flat).
         fill_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000), reps, torch)
