@@ -397,15 +397,22 @@ def main():
         fill_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000), reps, torch)
         flat = nn.make_cfg(layout="flat", occupancy=3)
         flat_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000, cfg=flat), reps, torch)
+        # ... and with the f64 generator's own pattern (chunks of four rows
+        # per workgroup, temporal stores, residency cap 4)
+        chunk = nn.make_cfg(layout="flat", unroll=4, occupancy=4, temporal=True)
+        chunk_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000, cfg=chunk), reps,
+                                torch)
         fill_gbps = 8.0 * case.count_f64 / fill_s / 1e9
         flat_gbps = 8.0 * case.count_f64 / flat_s / 1e9
-        extras["fill_same_pattern_GBps"] = fill_gbps
+        chunk_gbps = 8.0 * case.count_f64 / chunk_s / 1e9
+        extras["fill_row_pattern_GBps"] = fill_gbps
         extras["fill_flat_GBps"] = flat_gbps
-        ceiling = max(fill_gbps, flat_gbps)
+        extras["fill_same_pattern_GBps"] = chunk_gbps
+        ceiling = max(fill_gbps, flat_gbps, chunk_gbps)
         extras["write_ceiling_GBps"] = ceiling
         extras["f64_frac_of_write_ceiling"] = achieved / ceiling
         # Paper's Table 2: generation time net of the store time.
-        extras["net_generation_ms"] = (f64_s - min(fill_s, flat_s)) * 1e3
+        extras["net_generation_ms"] = (f64_s - min(fill_s, flat_s, chunk_s)) * 1e3
         # Paper's Table 1, execution vs including setup: the host seeding of
         # Eq. 2 (a 106-bit power modulo 3^33 from the index), the launch
         # constants and the launch, then the kernel, timed on the host clock

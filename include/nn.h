@@ -221,8 +221,10 @@ int nn_dev_skip_table(const nn_dev_mult **table_out);
 /* nn_fill -- the paper's "Constant" measurement kernel (Section 4.2,
  * Table 1): writes `value` to out_dev[0..count) with exactly the store
  * pattern nn_generate_ex uses for the same cfg and NN_OUT_F64 (fields left
- * 0 resolve as for F64 output), giving the write-bandwidth ceiling of that
- * pattern.  Same pointer rules and errors as nn_generate. */
+ * 0 resolve as for F64 output, except in the flat layout, where they mean
+ * one row per workgroup, non-temporal stores and no residency cap), giving
+ * the write-bandwidth ceiling of that pattern.  Same pointer rules and
+ * errors as nn_generate. */
 int nn_fill(uint64_t count, void *out_dev, uint64_t value, void *stream,
             const nn_launch_cfg *cfg);
 

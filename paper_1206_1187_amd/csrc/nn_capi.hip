@@ -33,8 +33,8 @@ struct Resolved {
 
 
 // `out` may be NULL (query of the defaults): it is then taken as aligned.
-// `fill`: nn_fill's resolution (its flat layout keeps one row per workgroup,
-// non-temporal stores and no residency cap unless asked).
+// `fill`: nn_fill's resolution (its flat layout defaults to one row per
+// workgroup, non-temporal stores and no residency cap).
 int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const DeviceTables& d,
                 const void* out, Resolved* r, bool fill = false) {
     const int cus = d.cus;
@@ -148,18 +148,13 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
         r->block = kFlatBlock;
         r->width = 2;
         r->ilp = 1;
-        if (fill) {
-            if (c.unroll) return fail(NN_EINVAL, "nn_fill's flat layout writes one row per workgroup");
-            r->unroll = 1;
-        } else {
-            // rows per workgroup, and temporal stores unless asked otherwise
-            // (the measured best, see kFlatDefaultRows)
-            r->unroll = c.unroll ? c.unroll : kFlatDefaultRows;
-            if (r->unroll == 0 || r->unroll > kFlatMaxRows || (r->unroll & (r->unroll - 1)))
-                return fail(NN_EINVAL, "unroll %u: the flat layout writes 1, 2, 4, 8 or 16 rows "
-                                       "per workgroup", r->unroll);
-            if (!store_flags) r->nontemporal = false;
-        }
+        // rows per workgroup; nn_generate takes temporal stores unless asked
+        // otherwise (the measured best, see kFlatDefaultRows)
+        r->unroll = c.unroll ? c.unroll : (fill ? 1u : kFlatDefaultRows);
+        if (r->unroll == 0 || r->unroll > kFlatMaxRows || (r->unroll & (r->unroll - 1)))
+            return fail(NN_EINVAL, "unroll %u: the flat layout writes 1, 2, 4, 8 or 16 rows "
+                                   "per workgroup", r->unroll);
+        if (!fill && !store_flags) r->nontemporal = false;
         const uint64_t chunk = count < kFlatMaxCount ? count : kFlatMaxCount;
         const uint64_t per = (uint64_t)kFlatPerBlock * r->unroll;
         r->grid = (uint32_t)((chunk + per - 1) / per);
@@ -433,8 +428,9 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     if (r.flat) {
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
-            hipError_t e = launch_fill_flat(r.nontemporal, r.lds, (hipStream_t)stream,
-                                            (uint64_t*)out_dev + off, n, value);
+            hipError_t e = launch_fill_flat(r.nontemporal, (int)r.unroll, r.lds,
+                                            (hipStream_t)stream, (uint64_t*)out_dev + off, n,
+                                            value);
             if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
         }
         return ok();

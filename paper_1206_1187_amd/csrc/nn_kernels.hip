@@ -332,20 +332,23 @@ __global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(const Mult* _
     }
 }
 
-template <bool NT>
+// The flat layout's store pattern with a constant: workgroup b writes the R
+// rows of kFlatPerBlock outputs from element kFlatPerBlock*R*b on.
+template <bool NT, int R>
 __global__ __launch_bounds__(kFlatBlock) void k_fill_flat(uint64_t* __restrict__ out,
                                                           uint64_t count, uint64_t value) {
     extern __shared__ char occupancy_cap[];
     (void)occupancy_cap;
-    const uint64_t k = (uint64_t)kFlatPerBlock * blockIdx.x + 2u * threadIdx.x;
-    if (k >= count) return;
-    if (k + 1 < count) {
-        u64x2 v;
-        v.x = value;
-        v.y = value;
-        put<NT>(reinterpret_cast<u64x2*>(out + k), v);
-    } else {
-        put<NT>(out + k, value);
+    u64x2 v;
+    v.x = value;
+    v.y = value;
+    uint64_t k = (uint64_t)kFlatPerBlock * R * blockIdx.x + 2u * threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < R; ++r, k += kFlatPerBlock) {
+        if (k + 1 < count)
+            put<NT>(reinterpret_cast<u64x2*>(out + k), v);
+        else if (k < count)
+            put<NT>(out + k, value);
     }
 }
 
@@ -400,16 +403,33 @@ hipError_t launch_generate_flat(int mulmod, int kind, bool nt, int rows, uint32_
     }
 }
 
-hipError_t launch_fill_flat(bool nt, uint32_t lds, hipStream_t s, uint64_t* out, uint64_t count,
-                            uint64_t value) {
-    const uint32_t grid = (uint32_t)((count + kFlatPerBlock - 1) / kFlatPerBlock);
-    if (nt)
-        hipLaunchKernelGGL((k_fill_flat<true>), dim3(grid), dim3(kFlatBlock), lds, s, out, count,
-                           value);
-    else
-        hipLaunchKernelGGL((k_fill_flat<false>), dim3(grid), dim3(kFlatBlock), lds, s, out,
-                           count, value);
+template <bool NT, int R>
+static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, uint64_t* out, uint64_t count,
+                                uint64_t value) {
+    const uint64_t per = (uint64_t)kFlatPerBlock * R;
+    const uint32_t grid = (uint32_t)((count + per - 1) / per);
+    hipLaunchKernelGGL((k_fill_flat<NT, R>), dim3(grid), dim3(kFlatBlock), lds, s, out, count,
+                       value);
     return hipGetLastError();
+}
+
+template <bool NT>
+static hipError_t fill_flat_r(int rows, uint32_t lds, hipStream_t s, uint64_t* out,
+                              uint64_t count, uint64_t value) {
+    switch (rows) {
+        case 1: return fill_flat_one<NT, 1>(lds, s, out, count, value);
+        case 2: return fill_flat_one<NT, 2>(lds, s, out, count, value);
+        case 4: return fill_flat_one<NT, 4>(lds, s, out, count, value);
+        case 8: return fill_flat_one<NT, 8>(lds, s, out, count, value);
+        case 16: return fill_flat_one<NT, 16>(lds, s, out, count, value);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_flat(bool nt, int rows, uint32_t lds, hipStream_t s, uint64_t* out,
+                            uint64_t count, uint64_t value) {
+    return nt ? fill_flat_r<true>(rows, lds, s, out, count, value)
+              : fill_flat_r<false>(rows, lds, s, out, count, value);
 }
 
 // Kernel selector: W = 1, W = 2, or W = 2 with IL = 2 or 4 rows in flight.

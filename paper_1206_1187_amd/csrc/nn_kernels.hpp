@@ -92,7 +92,7 @@ struct FlatArgs {
 // resident workgroups per compute unit.
 hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, int rows,
                                 uint32_t lds_bytes, hipStream_t stream, const FlatArgs& a);
-hipError_t launch_fill_flat(bool nontemporal, uint32_t lds_bytes, hipStream_t stream,
+hipError_t launch_fill_flat(bool nontemporal, int rows, uint32_t lds_bytes, hipStream_t stream,
                             uint64_t* out, uint64_t count, uint64_t value);
 
 // Consecutive layout: the output is cut into tiles of block*E elements;

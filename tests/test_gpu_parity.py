@@ -4,6 +4,7 @@ Integer work, so the bar is bit-exactness for raw states and for the
 binary64 variates.  Inputs come from the seeded workload recipes; expected
 values only from the oracle.
 """
+import itertools
 import sys
 
 import numpy as np
@@ -195,8 +196,8 @@ def test_config_validation():
     for cfg in bad:
         with pytest.raises(nn.NNError):
             nn.generate_into(z0, out, cfg=cfg)
-    with pytest.raises(nn.NNError):  # nn_fill's flat layout has one row per workgroup
-        nn.fill(out, 0, cfg=nn.make_cfg(layout="flat", unroll=4))
+    with pytest.raises(nn.NNError):
+        nn.fill(out, 0, cfg=nn.make_cfg(layout="flat", unroll=3))
     with pytest.raises(nn.NNError):
         nn.generate_into(z0, out[1:].view(torch.float64), cfg=nn.make_cfg(layout="flat"))
     d = nn.default_cfg("f64", 1 << 30)
@@ -253,9 +254,11 @@ def test_skip_stress_sample():
 
 
 def test_fill_ceiling_kernel_pattern():
-    for block, grid, count, width in [(256, 2048, 1 << 20, 1), (64, 5, 100_003, 1),
-                                      (256, 256, 1 << 20, 2), (64, 5, 100_003, 2)]:
-        cfg = nn.make_cfg(block=block, grid=grid, width=width)
+    cfgs = [nn.make_cfg(block=block, grid=grid, width=width)
+            for block, grid, width in [(256, 2048, 1), (64, 5, 1), (256, 256, 2), (64, 5, 2)]]
+    cfgs += [nn.make_cfg(layout="flat", unroll=rows, occupancy=occ, temporal=t)
+             for rows, occ, t in [(0, 0, None), (1, 3, None), (4, 4, True), (16, 0, False)]]
+    for cfg, count in itertools.product(cfgs, (1 << 20, 100_003, 2049, 3)):
         buf = _sentinel_buffer(count + 512)
         nn.fill(buf[256:256 + count], 0x3FF0000000000001, cfg=cfg)
         torch.cuda.synchronize()
