@@ -50,6 +50,32 @@ def test_header_constants_match_paper():
     assert int(consts["NN_INDEX_MAX"]) == 2 ** 53
 
 
+def test_header_flags_match_binding():
+    """Every NN_CFG_* / NN_BATCH_* / NN_SERVER_* flag and the debug selector
+    the binding uses has the value include/nn.h gives it."""
+    text = open(os.path.join(ROOT, "include", "nn.h")).read()
+    flags = {k: int(v) for k, v in re.findall(r"#define\s+(NN_\w+)\s+(\d+)u?\b", text)}
+    names = [n for n in dir(_native) if n.startswith(("NN_CFG_", "NN_BATCH_", "NN_SERVER_",
+                                                       "NN_DEBUG_"))]
+    assert "NN_CFG_NONTEMPORAL_STORES" in names
+    for n in names:
+        assert n in flags and flags[n] == getattr(_native, n), n
+
+
+def test_make_cfg_store_policy_and_layout_flags():
+    """make_cfg's temporal argument: None keeps the layout default (no flag),
+    True and False set the explicit flags; the layout names set theirs."""
+    assert nn.make_cfg().flags == 0
+    assert nn.make_cfg(temporal=True).flags == _native.NN_CFG_TEMPORAL_STORES
+    assert nn.make_cfg(temporal=False).flags == _native.NN_CFG_NONTEMPORAL_STORES
+    c = nn.make_cfg(layout="flat", unroll=4, occupancy=4)
+    assert c.flags == _native.NN_CFG_FLAT and c.unroll == 4 and c.occupancy == 4
+    assert nn.make_cfg(layout="rows", temporal=False).flags == (
+        _native.NN_CFG_ROWS | _native.NN_CFG_NONTEMPORAL_STORES)
+    with pytest.raises(nn.NNError):
+        nn.make_cfg(layout="diagonal")
+
+
 def test_version_and_strerror():
     assert "gfx950" in nn.version()
     lib = _native.lib()
