@@ -102,8 +102,7 @@ typedef enum nn_mulmod {
  * width: outputs per lane and store, 1 (8-byte stores) or 2 (16-byte
  * stores, needs a 16-byte aligned output) (rows; flat is always 2).
  * occupancy: 0, or a cap in [2,16] on resident workgroups per compute unit
- * (flat; 0 there means 4 for nn_generate, no cap for nn_fill), enforced
- * through unused dynamic LDS.
+ * (flat; 0 there means 4), enforced through unused dynamic LDS.
  * Consecutive: width 2 (16-byte stores) on a 16-byte aligned output, else 1. 
  * ilp: rows each thread keeps in flight, 1, 2 or 4 (rows with width 2):
  * 2*ilp independent multiplication chains per lane. */
@@ -149,7 +148,8 @@ int nn_skip(uint64_t state, uint64_t k, uint64_t *state_out);
 /* --------------------------------------------------------------- device -- */
 
 /* nn_init -- set up the library on HIP device `device` (uploads the
- * immutable skip-ahead tables, ~0.8 MB, owned by the library until process
+ * immutable skip-ahead tables, about 3.4 MB: 69 632 48-byte multipliers
+ * and the 43 KB device-API table, owned by the library until process
  * exit).  Optional: the first generating call on a device does it.  The
  * caller's current device is left unchanged.  Thread-safe. */
 int nn_init(int device);
@@ -219,12 +219,12 @@ int nn_dev_mult_pow(uint64_t k, nn_dev_mult *out);
 int nn_dev_skip_table(const nn_dev_mult **table_out);
 
 /* nn_fill -- the paper's "Constant" measurement kernel (Section 4.2,
- * Table 1): writes `value` to out_dev[0..count) with exactly the store
- * pattern nn_generate_ex uses for the same cfg and NN_OUT_F64 (fields left
- * 0 resolve as for F64 output, except in the flat layout, where they mean
- * one row per workgroup, non-temporal stores and no residency cap), giving
- * the write-bandwidth ceiling of that pattern.  Same pointer rules and
- * errors as nn_generate. */
+ * Tables 1-2): writes `value` to out_dev[0..count) with exactly the store
+ * pattern nn_generate_ex uses for the same cfg and NN_OUT_F64 (the same
+ * layout, launch shape, rows per workgroup, store policy and residency cap,
+ * fields left 0 resolving as they do for F64 output), with the arithmetic
+ * taken out: the write-bandwidth ceiling of that pattern.  Same pointer
+ * rules and errors as nn_generate. */
 int nn_fill(uint64_t count, void *out_dev, uint64_t value, void *stream,
             const nn_launch_cfg *cfg);
 
@@ -272,6 +272,18 @@ typedef struct nn_batch_cfg {
  * (NN_ERANGE otherwise).  Batches of at most 16 windows travel in the
  * kernel arguments and run the blocked kernel in either case. */
 #define NN_BATCH_INTERLEAVED 16u
+/* Chunked kernel: the plain generator's flat layout over a batch.  The
+ * output is cut into aligned chunks of 2048 outputs (16 KiB); a pre-pass
+ * writes one record per chunk and window that meet (the state of the
+ * chunk's first element in that window, and the window's part of the
+ * chunk), and `grid` persistent 256-thread workgroups take the records
+ * round-robin, each writing its chunk as four rows of 512 outputs with one
+ * 16-byte store per lane and row.  Needs the FP64 reduction, block 0 or 256,
+ * cluster 0 or 1 and output indices below 2^51 (NN_ERANGE otherwise); grid
+ * 0 means four workgroups per compute unit.  Exclusive with
+ * NN_BATCH_INTERLEAVED.  Batches of at most 16 windows travel in the
+ * kernel arguments and run the blocked kernel. */
+#define NN_BATCH_CHUNKS 32u
 
 /* Opaque batch plan: device workspace, pinned staging and a hipGraph of
  * (staging -> workspace copy, persistent kernel) whose arguments never

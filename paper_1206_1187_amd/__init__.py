@@ -253,13 +253,15 @@ class BatchPlan:
     """
 
     def __init__(self, kind, max_streams, max_outputs, block=0, grid=0, mulmod=0,
-                 temporal=False, graph=True, device=None, cluster=0, interleaved=False):
+                 temporal=False, graph=True, device=None, cluster=0, interleaved=False,
+                 chunks=False):
         import torch
         if isinstance(mulmod, str):
             mulmod = MULMOD_NAMES[mulmod]
         flags = (_native.NN_CFG_TEMPORAL_STORES if temporal else 0) | \
                 (0 if graph else _native.NN_BATCH_NO_GRAPH) | \
-                (_native.NN_BATCH_INTERLEAVED if interleaved else 0)
+                (_native.NN_BATCH_INTERLEAVED if interleaved else 0) | \
+                (_native.NN_BATCH_CHUNKS if chunks else 0)
         cfg = _native.BatchCfg(int(block), int(grid), int(cluster), int(mulmod), flags)
         self.kind = _kind(kind)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None

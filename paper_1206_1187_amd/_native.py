@@ -81,6 +81,7 @@ class BatchCfg(ctypes.Structure):
 
 NN_BATCH_NO_GRAPH = 8
 NN_BATCH_INTERLEAVED = 16
+NN_BATCH_CHUNKS = 32
 
 
 _u64 = ctypes.c_uint64

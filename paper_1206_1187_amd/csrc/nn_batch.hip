@@ -425,6 +425,133 @@ __global__ __launch_bounds__(256) void k_batch_rows(BatchArgs a) {
     }
 }
 
+// Chunked kernel: the flat layout of the plain generator over a batch.  The
+// output is cut into aligned chunks of kChunkRows rows of 512 outputs
+// (16 KiB); the pre-pass (k_batch_rec with one cluster of one workgroup and
+// rows of kChunkOuts outputs) writes one record per chunk and window that
+// meet, in window order: the state of the chunk's element 0 as if the
+// window covered it, the chunk's output index and the window's part of the
+// chunk [lo, hi).  Workgroup w of the grid takes records w, w + grid, ...
+// (the write front moves through the output as in the plain flat layout,
+// with no workgroup launch per chunk), loading the next record while it
+// writes the current one.  Lane l's outputs of a chunk are its pairs
+// 2l, 2l + 1 of each row: states z * (2^53)^(2l) and z * (2^53)^(2l+1), one
+// multiplication each by the lane's fixed multipliers, then one step of
+// (2^53)^512 per row.  A chunk that one window covers is stored without a
+// test; one that a window starts or ends in stores the window's outputs only.
+template <int KIND, bool NT>
+__global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
+    constexpr uint32_t C = kChunkOuts;
+    const const_ptr<BatchHeader> hdr = as_const(a.ws);
+    const uint64_t n = hdr->n_rows;  // records
+    const global_ptr<uint64_t> out = as_global(hdr->out);
+    const const_ptr<u64x2> rec = reinterpret_cast<const_ptr<u64x2>>(as_const(a.rec));
+    const uint32_t l = threadIdx.x;
+    uint64_t j = blockIdx.x;
+    if (j >= n) return;
+    const Mult ma = a.t_lo[2u * l], mb = a.t_lo[2u * l + 1];
+    u64x2 cur = rec[j];
+    for (;;) {
+        const uint64_t jn = j + gridDim.x;
+        const u64x2 nxt = rec[jn < n ? jn : j];  // the next record, in flight meanwhile
+        const double z0 = __builtin_bit_cast(double, cur.x);
+        const uint64_t info = cur.y;
+        double za = VarFP64::mul(z0, ma);
+        double zb = VarFP64::mul(z0, mb);
+        const global_ptr<uint64_t> p = out + ((info & kRecIndexMask & ~(uint64_t)(C - 1)) + 2u * l);
+        const uint32_t hi = (uint32_t)(info >> kRecHiShift);
+        const uint32_t lo = (uint32_t)info & (C - 1);
+        if (hi == C && lo == 0) {
+#pragma unroll
+            for (int r = 0; r < (int)kChunkRows; ++r) {
+                put<NT>(reinterpret_cast<global_ptr<u64x2>>(p + r * kFlatPerBlock),
+                        pair_bits<VarFP64, KIND>(za, zb));
+                za = VarFP64::mul(za, a.JB);
+                zb = VarFP64::mul(zb, a.JB);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < (int)kChunkRows; ++r) {
+                put_pair_in<KIND, NT>(p + r * kFlatPerBlock, za, zb, r * kFlatPerBlock + 2u * l,
+                                      lo, hi);
+                za = VarFP64::mul(za, a.JB);
+                zb = VarFP64::mul(zb, a.JB);
+            }
+        }
+        j = jn;
+        if (j >= n) break;
+        cur = nxt;
+    }
+}
+
+// Small batches in the kernel arguments (see BatchFlatInline): workgroup b
+// finds its window among at most kInlineDescs (a uniform scan), then writes
+// chunk c = b - chunk0 of it exactly as k_generate_flat writes a chunk,
+// storing only the window's outputs.
+template <int KIND, bool NT>
+__global__ __launch_bounds__(kFlatBlock) void k_batch_flat_inline(const Mult* __restrict__ tabs,
+                                                                  Mult M1, Mult J,
+                                                                  BatchFlatInline in) {
+    extern __shared__ char occupancy_cap[];
+    (void)occupancy_cap;
+    constexpr uint32_t C = kChunkOuts;
+    const uint32_t b = blockIdx.x;
+    uint32_t d = 0;
+    for (uint32_t k = 1; k < in.n; ++k)
+        if (in.w[k].chunk0 <= b) d = k;
+    const FlatWin W = in.w[d];
+    const uint64_t c = b - W.chunk0;
+    const uint32_t l = threadIdx.x;
+    double za, zb;
+    flat_start<VarFP64>(c, l, (int)kChunkRows, W.base, tabs, M1, za, zb);
+    // chunk-relative positions k of the window's elements k - s: [s, len + s)
+    const uint64_t first = C * c;
+    const global_ptr<uint64_t> p = as_global(in.out) + (W.out_off - W.s + first + 2u * l);
+    const uint64_t hi = W.len + W.s;
+    if (first >= W.s && first + C <= hi) {
+#pragma unroll
+        for (int r = 0; r < (int)kChunkRows; ++r) {
+            put<NT>(reinterpret_cast<global_ptr<u64x2>>(p + r * kFlatPerBlock),
+                    pair_bits<VarFP64, KIND>(za, zb));
+            za = VarFP64::mul(za, J);
+            zb = VarFP64::mul(zb, J);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
+    // the window's first or last chunk: keep k in [s, len + s)
+    const uint32_t lo = first == 0 ? W.s : 0;
+    const uint32_t top = hi - first < C ? (uint32_t)(hi - first) : C;
+#pragma unroll
+    for (int r = 0; r < (int)kChunkRows; ++r) {
+        put_pair_in<KIND, NT>(p + r * kFlatPerBlock, za, zb, r * kFlatPerBlock + 2u * l, lo, top);
+        za = VarFP64::mul(za, J);
+        zb = VarFP64::mul(zb, J);
+    }
+}
+
+hipError_t launch_batch_flat_inline(int kind, bool nt, uint32_t grid, uint32_t lds,
+                                    hipStream_t s, const Mult* tabs, const Mult& M1,
+                                    const Mult& J, const BatchFlatInline& in) {
+    if (kind == 0) {
+        if (nt)
+            hipLaunchKernelGGL((k_batch_flat_inline<0, true>), dim3(grid), dim3(kFlatBlock), lds,
+                               s, tabs, M1, J, in);
+        else
+            hipLaunchKernelGGL((k_batch_flat_inline<0, false>), dim3(grid), dim3(kFlatBlock), lds,
+                               s, tabs, M1, J, in);
+    } else {
+        if (nt)
+            hipLaunchKernelGGL((k_batch_flat_inline<1, true>), dim3(grid), dim3(kFlatBlock), lds,
+                               s, tabs, M1, J, in);
+        else
+            hipLaunchKernelGGL((k_batch_flat_inline<1, false>), dim3(grid), dim3(kFlatBlock), lds,
+                               s, tabs, M1, J, in);
+    }
+    return hipGetLastError();
+}
+
 // The device request queue (see nn_batch.hpp).  Thread 0 of a workgroup
 // waits for the next entry with acquire loads of the host's `head`, copies
 // the entry to LDS, and claims rows with a compare-and-swap that also checks
@@ -546,6 +673,14 @@ hipError_t launch_queue(int kind, uint32_t grid, uint32_t block, hipStream_t s,
 const void* batch_rec_kernel(bool indexed) {
     return indexed ? reinterpret_cast<const void*>(&k_batch_rec<true>)
                    : reinterpret_cast<const void*>(&k_batch_rec<false>);
+}
+
+const void* batch_chunks_kernel(int kind, bool nt) {
+    if (kind == 0)
+        return nt ? reinterpret_cast<const void*>(&k_batch_chunks<0, true>)
+                  : reinterpret_cast<const void*>(&k_batch_chunks<0, false>);
+    return nt ? reinterpret_cast<const void*>(&k_batch_chunks<1, true>)
+              : reinterpret_cast<const void*>(&k_batch_chunks<1, false>);
 }
 
 const void* batch_rows_kernel(int kind, bool nt) {

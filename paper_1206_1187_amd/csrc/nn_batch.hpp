@@ -105,6 +105,17 @@ struct BatchArgs {
 const void* batch_rec_kernel(bool indexed);
 const void* batch_rows_kernel(int kind, bool nontemporal);
 
+// Chunked kernel (FP64 reduction, 256 threads): the pre-pass writes one
+// record per chunk of kChunkOuts outputs and window that meet (rows of
+// kChunkOuts outputs in k_batch_rec's terms, one cluster of one workgroup,
+// so the records lie in window order), and the workgroups of the chunk
+// kernel deal the records out round-robin.
+constexpr uint32_t kChunkRows = 4;
+constexpr uint32_t kChunkOuts = kChunkRows * 512;
+// Default grid of the chunked kernel: workgroups per compute unit.
+constexpr uint32_t kChunkResidency = 4;
+const void* batch_chunks_kernel(int kind, bool nontemporal);
+
 // The kernel entry for (mulmod, kind, nontemporal, indexed); its single
 // parameter is a BatchArgs passed by value.
 const void* batch_kernel(int mulmod, int kind, bool nontemporal, bool indexed);
@@ -126,6 +137,33 @@ static_assert(sizeof(BatchInline) == sizeof(BatchHeader) + kInlineDescs * sizeof
 hipError_t launch_batch_inline(int mulmod, int kind, bool nontemporal, bool indexed,
                                uint32_t grid, uint32_t block, hipStream_t stream,
                                const BatchArgs& a, const BatchInline& in);
+
+// A small batch of the FP64 reduction in the kernel arguments, each window
+// written as the plain generator's flat layout writes an output: chunks of
+// kChunkRows rows of 512 outputs, one workgroup each, dispatched in order
+// (a window's chunks after the previous window's).  The host gives each
+// window's start state, so a workgroup's start is the plain flat kernel's.
+// Window element x has the state base * (2^53)^(x + s), s = out_off mod 2
+// (chunks are aligned to output pairs, so the 16-byte stores stay aligned).
+struct FlatWin {
+    uint64_t base;     // state of window element -s
+    uint64_t len;      // outputs, > 0
+    uint64_t out_off;  // output index of window element 0
+    uint32_t s;        // out_off & 1
+    uint32_t chunk0;   // the window's first chunk (workgroup index)
+};
+struct BatchFlatInline {
+    uint64_t* out;
+    uint32_t n;
+    uint32_t pad;
+    FlatWin w[kInlineDescs];
+};
+
+// grid = the windows' chunks in total; lds caps residency as for the
+// plain flat layout.
+hipError_t launch_batch_flat_inline(int kind, bool nontemporal, uint32_t grid, uint32_t lds,
+                                    hipStream_t stream, const Mult* tabs, const Mult& M1,
+                                    const Mult& J, const BatchFlatInline& in);
 
 // --------------------------------------------------- device request queue --
 // The served form's low-latency path: a persistent kernel serves requests

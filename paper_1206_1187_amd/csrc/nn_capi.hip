@@ -33,10 +33,10 @@ struct Resolved {
 
 
 // `out` may be NULL (query of the defaults): it is then taken as aligned.
-// `fill`: nn_fill's resolution (its flat layout defaults to one row per
-// workgroup, non-temporal stores and no residency cap).
+// nn_fill resolves through the same function, so a fill and a generation
+// with the same cfg store with the same pattern.
 int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const DeviceTables& d,
-                const void* out, Resolved* r, bool fill = false) {
+                const void* out, Resolved* r) {
     const int cus = d.cus;
     const KindDefaults& kd = kind_defaults(kind);
     nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -129,7 +129,7 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
         return fail(NN_EINVAL, "NN_MULMOD_MODBARRETT steps by 2^53 only: consecutive layout");
     if (r->mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", r->mulmod);
     r->flat = (c.flags & NN_CFG_FLAT) != 0;
-    r->occupancy = c.occupancy ? c.occupancy : (r->flat && !fill ? kFlatDefaultOccupancy : 0u);
+    r->occupancy = c.occupancy ? c.occupancy : (r->flat ? kFlatDefaultOccupancy : 0u);
     r->lds = 0;
     if (r->occupancy) {
         if (r->occupancy < 2 || r->occupancy > 16)
@@ -148,13 +148,13 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
         r->block = kFlatBlock;
         r->width = 2;
         r->ilp = 1;
-        // rows per workgroup; nn_generate takes temporal stores unless asked
-        // otherwise (the measured best, see kFlatDefaultRows)
-        r->unroll = c.unroll ? c.unroll : (fill ? 1u : kFlatDefaultRows);
+        // rows per workgroup; temporal stores unless asked otherwise (the
+        // measured best, see kFlatDefaultRows)
+        r->unroll = c.unroll ? c.unroll : kFlatDefaultRows;
         if (r->unroll == 0 || r->unroll > kFlatMaxRows || (r->unroll & (r->unroll - 1)))
             return fail(NN_EINVAL, "unroll %u: the flat layout writes 1, 2, 4, 8 or 16 rows "
                                    "per workgroup", r->unroll);
-        if (!fill && !store_flags) r->nontemporal = false;
+        if (!store_flags) r->nontemporal = false;
         const uint64_t chunk = count < kFlatMaxCount ? count : kFlatMaxCount;
         const uint64_t per = (uint64_t)kFlatPerBlock * r->unroll;
         r->grid = (uint32_t)((chunk + per - 1) / per);
@@ -422,7 +422,7 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     st = current_device(&d);
     if (st) return st;
     Resolved r;
-    st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r, true);
+    st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r);
     if (st) return st;
     if (r.consec || r.strided) return fail(NN_EINVAL, "nn_fill has no consecutive layout");
     if (r.flat) {
@@ -447,7 +447,7 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
 
 int nn_batch_plan_create(int kind, uint32_t max_streams, uint64_t max_outputs,
                          const nn_batch_cfg* cfg, nn_batch_plan** plan_out) {
-    int st = plan_create(kind, max_streams, max_outputs, cfg, false, nullptr, plan_out);
+    int st = plan_create(kind, max_streams, max_outputs, cfg, false, nullptr, nullptr, plan_out);
     return st == NN_OK ? ok() : st;
 }
 
@@ -464,7 +464,8 @@ int nn_batch_plan_cfg(const nn_batch_plan* plan, nn_batch_cfg* cfg_out) {
     cfg_out->mulmod = plan->mulmod;
     cfg_out->flags = (plan->nontemporal ? 0u : NN_CFG_TEMPORAL_STORES) |
                      (plan->use_graph ? 0u : NN_BATCH_NO_GRAPH) |
-                     (plan->interleaved ? NN_BATCH_INTERLEAVED : 0u);
+                     (plan->interleaved ? NN_BATCH_INTERLEAVED : 0u) |
+                     (plan->chunks ? NN_BATCH_CHUNKS : 0u);
     return ok();
 }
 

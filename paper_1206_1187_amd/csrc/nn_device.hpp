@@ -22,6 +22,24 @@ __device__ __forceinline__ typename V::S thread_start(uint64_t base, uint64_t k,
     return z;
 }
 
+// Flat layout start: the states of lane l's pair (outputs 2l and 2l + 1)
+// of the chunk that begins u = b*R rows of kFlatPerBlock outputs after the
+// output whose state is `base`: two multiplications by uniform table
+// entries (scalar loads that hit L2), one by the lane's offset, one by M1.
+// tabs is the device table allocation (t_lo at 0, t_flo and t_fhi at their
+// offsets); b*R < kFlatMaxRowsPerLaunch.
+template <class V>
+__device__ __forceinline__ void flat_start(uint64_t b, uint32_t l, int R, uint64_t base,
+                                           const Mult* __restrict__ tabs, const Mult& M1,
+                                           typename V::S& za, typename V::S& zb) {
+    const uint64_t u = b * (uint64_t)R;
+    const Mult hi = tabs[kFlatHiOffset + u / kFlatLoSize];
+    const Mult lo = tabs[kFlatLoOffset + u % kFlatLoSize];
+    const Mult lane = tabs[2u * l];  // t_lo: (2^53)^(2l)
+    za = V::mul(V::mul(V::mul(V::load(base), hi), lo), lane);
+    zb = V::mul(za, M1);
+}
+
 // The 64-bit pattern stored for a state: the state itself or its variate.
 template <class V, int KIND>
 __device__ __forceinline__ uint64_t out_bits(typename V::S z) {

@@ -51,7 +51,7 @@ struct nn_batch_slot {
     size_t ws_bytes = 0;
     void* ws_dev = nullptr;
     void* ws_host = nullptr;      // pinned staging, same layout as ws_dev
-    nn::RowRec* rec = nullptr;    // device, cap_rows + grid row records (interleaved)
+    nn::RowRec* rec = nullptr;    // device, cap_rows + 2 grid records (interleaved, chunked)
     hipEvent_t done = nullptr;
     bool pending = false;
     hipGraph_t graph = nullptr;
@@ -65,12 +65,17 @@ struct nn_batch_plan {
     int kind = 0;
     bool indexed = false;
     uint32_t mulmod = 0, block = 0, grid = 0, cluster = 1;
-    bool nontemporal = true, use_graph = true, interleaved = false;
+    bool nontemporal = true, use_graph = true, interleaved = false, chunks = false;
     uint64_t cap_rows = 0;
     uint32_t map_grid = 0;
     uint32_t max_streams = 0;
     uint64_t max_outputs = 0;
     uint32_t cap_desc = 0;
+    // small batches of the FP64 reduction (the flat inline kernel)
+    const uint64_t* host_states = nullptr;  // indexed plans: host copy of the state table
+    const nn::Mult* tabs = nullptr;         // the device tables
+    nn::Mult M1, J512;                      // 2^53 and (2^53)^512
+    uint32_t flat_lds = 0;                  // residency cap of the flat layout
     nn_batch_slot slot[2];
     int next = 0;  // the slot of the next batch
 };
@@ -78,9 +83,12 @@ struct nn_batch_plan {
 namespace nn {
 
 // Creates a plan on the current device.  Indexed plans read window states
-// from `states` (a device table) and take descriptors with src = row.
+// from `states` (a device table; `host_states` is its host copy, read for
+// batches small enough to travel in the kernel arguments) and take
+// descriptors with src = row.
 int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_batch_cfg* cfg,
-                bool indexed, const uint64_t* states, nn_batch_plan** out);
+                bool indexed, const uint64_t* states, const uint64_t* host_states,
+                nn_batch_plan** out);
 void plan_release(nn_batch_plan* p);
 
 // Waits until the next batch's slot is free (the batch before the previous

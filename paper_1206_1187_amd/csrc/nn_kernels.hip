@@ -268,18 +268,6 @@ __global__ __launch_bounds__(1024) void k_fill(uint64_t* __restrict__ out, uint6
 // the base lead the arguments (one scalar load fetches both), the whole-chunk
 // kernel takes no count and tests nothing, and the table indices are in
 // range for every lane.  A ragged last chunk goes to k_generate_flat_tail.
-template <class V>
-__device__ __forceinline__ void flat_start(uint64_t b, uint32_t l, int R, uint64_t base,
-                                           const Mult* __restrict__ tabs, const Mult& M1,
-                                           typename V::S& za, typename V::S& zb) {
-    const uint64_t u = b * (uint64_t)R;  // rows before the chunk, < kFlatMaxRowsPerLaunch
-    const Mult hi = tabs[kFlatHiOffset + u / kFlatLoSize];
-    const Mult lo = tabs[kFlatLoOffset + u % kFlatLoSize];
-    const Mult lane = tabs[2u * l];  // t_lo: (2^53)^(2l)
-    za = V::mul(V::mul(V::mul(V::load(base), hi), lo), lane);
-    zb = V::mul(za, M1);
-}
-
 template <class V, int KIND, bool NT, int R>
 __global__ __launch_bounds__(kFlatBlock) void k_generate_flat(const Mult* __restrict__ tabs,
                                                               uint64_t base,
@@ -332,22 +320,40 @@ __global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(const Mult* _
     }
 }
 
-// The flat layout's store pattern with a constant: workgroup b writes the R
-// rows of kFlatPerBlock outputs from element kFlatPerBlock*R*b on.
+// The paper's "Constant" kernel (Section 4.2) for the flat layout: exactly
+// k_generate_flat's stores with the arithmetic taken out -- whole chunks of
+// R rows of kFlatPerBlock outputs, no count test, each row's store followed
+// by the same scheduling barrier, and a ragged last chunk in a separate
+// one-workgroup kernel (k_fill_flat_tail).
 template <bool NT, int R>
 __global__ __launch_bounds__(kFlatBlock) void k_fill_flat(uint64_t* __restrict__ out,
-                                                          uint64_t count, uint64_t value) {
+                                                          uint64_t value) {
     extern __shared__ char occupancy_cap[];
     (void)occupancy_cap;
     u64x2 v;
     v.x = value;
     v.y = value;
-    uint64_t k = (uint64_t)kFlatPerBlock * R * blockIdx.x + 2u * threadIdx.x;
+    u64x2* p = reinterpret_cast<u64x2*>(out + (uint64_t)kFlatPerBlock * R * blockIdx.x +
+                                        2u * threadIdx.x);
 #pragma unroll
-    for (int r = 0; r < R; ++r, k += kFlatPerBlock) {
+    for (int r = 0; r < R; ++r) {
+        put<NT>(p + r * kFlatBlock, v);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The last, partial chunk of a fill: `count` < kFlatPerBlock*R outputs.
+template <bool NT, int R>
+__global__ __launch_bounds__(kFlatBlock) void k_fill_flat_tail(uint64_t* __restrict__ out,
+                                                               uint64_t count, uint64_t value) {
+    u64x2 v;
+    v.x = value;
+    v.y = value;
+    uint64_t k = 2u * threadIdx.x;
+    for (int r = 0; r < R && k < count; ++r, k += kFlatPerBlock) {
         if (k + 1 < count)
             put<NT>(reinterpret_cast<u64x2*>(out + k), v);
-        else if (k < count)
+        else
             put<NT>(out + k, value);
     }
 }
@@ -407,10 +413,20 @@ template <bool NT, int R>
 static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, uint64_t* out, uint64_t count,
                                 uint64_t value) {
     const uint64_t per = (uint64_t)kFlatPerBlock * R;
-    const uint32_t grid = (uint32_t)((count + per - 1) / per);
-    hipLaunchKernelGGL((k_fill_flat<NT, R>), dim3(grid), dim3(kFlatBlock), lds, s, out, count,
-                       value);
-    return hipGetLastError();
+    const uint64_t full = count / per;
+    const uint64_t tail = count - full * per;
+    if (full) {
+        hipLaunchKernelGGL((k_fill_flat<NT, R>), dim3((uint32_t)full), dim3(kFlatBlock), lds, s,
+                           out, value);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (tail) {
+        hipLaunchKernelGGL((k_fill_flat_tail<NT, R>), dim3(1), dim3(kFlatBlock), 0, s,
+                           out + full * per, tail, value);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 template <bool NT>

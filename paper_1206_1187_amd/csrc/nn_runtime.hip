@@ -207,7 +207,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
                 const uint64_t* states) {
     q.ws_bytes = sizeof(BatchHeader) + (size_t)p->cap_desc * sizeof(BatchDesc);
     hipError_t e = hipMalloc(&q.ws_dev, q.ws_bytes);
-    if (e == hipSuccess && p->interleaved)  // grid * per <= rows + clusters + grid records
+    if (e == hipSuccess && (p->interleaved || p->chunks))  // grid * per <= rows + clusters + grid
         e = hipMalloc((void**)&q.rec, (p->cap_rows + 2ull * p->grid) * sizeof(RowRec));
     if (e != hipSuccess)
         return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", q.ws_bytes, hipGetErrorString(e));
@@ -230,9 +230,16 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     q.args.t_sk = d.t_sk;
     q.args.rec = q.rec;
     q.args.row_outs = 2u * kIlPairs * block;
-    q.args.JR = make_mult(MultPowers::get().pow((uint64_t)q.args.row_outs * 256));
     q.args.grid = p->grid;
     q.args.block = block;
+    if (p->chunks) {
+        // the pre-pass writes chunk records in window order: rows of
+        // kChunkOuts outputs, one cluster of one workgroup
+        q.args.row_outs = kChunkOuts;
+        q.args.grid = 1;
+        q.args.cluster = 1;
+    }
+    q.args.JR = make_mult(MultPowers::get().pow((uint64_t)q.args.row_outs * 256));
     if (!p->use_graph) return NN_OK;
     // The graph holds the kernels; the descriptor upload before each replay
     // is an ordinary async copy on the same stream (a copy node from pinned
@@ -240,7 +247,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     e = hipGraphCreate(&q.graph, 0);
     hipGraphNode_t last = nullptr;
     void* params[] = {&q.args};
-    if (e == hipSuccess && p->interleaved) {
+    if (e == hipSuccess && (p->interleaved || p->chunks)) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
         kp.func = const_cast<void*>(batch_rec_kernel(p->indexed));
@@ -252,7 +259,8 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     if (e == hipSuccess) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
-        kp.func = p->interleaved
+        kp.func = p->chunks ? const_cast<void*>(batch_chunks_kernel(p->kind, p->nontemporal))
+                  : p->interleaved
                       ? const_cast<void*>(batch_rows_kernel(p->kind, p->nontemporal))
                       : const_cast<void*>(
                             batch_kernel((int)p->mulmod, p->kind, p->nontemporal, p->indexed));
@@ -272,14 +280,23 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
 }  // namespace
 
 int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_batch_cfg* cfg,
-                bool indexed, const uint64_t* states, nn_batch_plan** plan_out) {
+                bool indexed, const uint64_t* states, const uint64_t* host_states,
+                nn_batch_plan** plan_out) {
     if (!plan_out) return fail(NN_EINVAL, "plan_out is NULL");
     if (kind != NN_OUT_U64 && kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %d unknown", kind);
     if (max_streams == 0) return fail(NN_EINVAL, "max_streams must be positive");
     nn_batch_cfg c = {0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
-    if (c.flags & ~(NN_CFG_TEMPORAL_STORES | NN_BATCH_NO_GRAPH | NN_BATCH_INTERLEAVED))
+    if (c.flags &
+        ~(NN_CFG_TEMPORAL_STORES | NN_BATCH_NO_GRAPH | NN_BATCH_INTERLEAVED | NN_BATCH_CHUNKS))
         return fail(NN_EINVAL, "unknown batch flags 0x%x", c.flags);
+    const bool chunks = (c.flags & NN_BATCH_CHUNKS) != 0;
+    if (chunks && (c.flags & NN_BATCH_INTERLEAVED))
+        return fail(NN_EINVAL, "NN_BATCH_CHUNKS and NN_BATCH_INTERLEAVED are exclusive");
+    if (chunks && ((c.block && c.block != 256) || c.cluster > 1 ||
+                   (c.mulmod && c.mulmod != NN_MULMOD_FP64)))
+        return fail(NN_EINVAL, "the chunked batch kernel has 256 threads, no clusters and the "
+                               "FP64 reduction");
     DeviceTables* d = nullptr;
     int st = current_device(&d);
     if (st) return st;
@@ -295,7 +312,10 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
         return fail(NN_EINVAL, "mulmod %u: batches take FP64, Barrett, Shoup or Montgomery",
                     mulmod);
     uint32_t grid = c.grid;
-    if (!grid) {
+    if (!grid && chunks) {
+        grid = (uint32_t)((uint64_t)d->cus * kChunkResidency);
+        if (!grid) grid = 1;
+    } else if (!grid) {
         grid = (uint32_t)((uint64_t)d->cus * kd.grid_num / kd.grid_den);
         if (!grid) grid = 1;
     }
@@ -318,6 +338,7 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
     p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
     p->interleaved = (c.flags & NN_BATCH_INTERLEAVED) != 0;
+    p->chunks = chunks;
     if (p->interleaved &&
         (mulmod != NN_MULMOD_FP64 || (block & (block - 1)) || block > 256)) {
         plan_release(p);
@@ -325,11 +346,17 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
                     "block 64, 128 or 256");
     }
     p->cluster = cluster;
-    p->cap_rows = max_outputs / (2ull * block) + 2 * cap_desc;
+    p->cap_rows = max_outputs / (chunks ? (uint64_t)kChunkOuts : 2ull * block) + 2 * cap_desc;
     p->map_grid = (uint32_t)(d->cus > 0 ? d->cus * 4 : 64);
     p->max_streams = max_streams;
     p->max_outputs = max_outputs;
     p->cap_desc = (uint32_t)cap_desc;
+    p->host_states = host_states;
+    p->tabs = d->t_lo;
+    p->M1 = make_mult(kMult);
+    p->J512 = make_mult(MultPowers::get().pow(kFlatPerBlock));
+    p->flat_lds = (d->lds_per_cu / (kFlatDefaultOccupancy + 1) / 512 + 1) * 512;
+    if (p->flat_lds > d->lds_per_block) p->flat_lds = 0;
     for (nn_batch_slot& q : p->slot) {
         st = slot_create(p, q, *d, states);
         if (st) {
@@ -369,20 +396,22 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     // and runs the blocked kernel whichever kernel the plan has; larger ones
     // of an interleaved plan run its pre-pass and row kernel.
     const bool in_args = nd <= kInlineDescs;
-    const bool il = p->interleaved && !in_args;
-    const uint64_t row = (il ? 2ull * kIlPairs : 2ull) * p->block;
+    const bool il = (p->interleaved || p->chunks) && !in_args;
+    const uint64_t row = p->chunks && !in_args ? (uint64_t)kChunkOuts
+                                               : (il ? 2ull * kIlPairs : 2ull) * p->block;
     BatchHeader* hdr = (BatchHeader*)q.ws_host;
     BatchDesc* dd = plan_staged_descs(p);
     uint64_t rows = 0;
     for (uint32_t k = 0; k < nd; ++k) {
         dd[k].row_start = rows;
         // rows aligned to output pairs (blocked kernel) or to whole rows
-        // of the output (interleaved kernel)
+        // of the output (interleaved kernel; chunks for the chunked one)
         const uint64_t s = dd[k].out_off & (il ? row - 1 : 1u);
         rows += (dd[k].len + s + row - 1) / row;
         // row records hold output indices in 52 bits
         if (il && dd[k].out_off + dd[k].len > (1ull << 51))
-            return fail(NN_ERANGE, "interleaved batches take output indices below 2^51");
+            return fail(NN_ERANGE, "interleaved and chunked batches take output indices below "
+                                   "2^51");
     }
     if (il && rows > p->cap_rows)
         return fail(NN_ERANGE, "batch of %llu rows, plan holds %llu", (unsigned long long)rows,
@@ -392,6 +421,34 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     hdr->n_rows = rows;
     const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc);
     hipError_t e;
+    if (in_args && p->mulmod == NN_MULMOD_FP64 && (!p->indexed || p->host_states)) {
+        // each window as the plain flat layout writes it, from a start state
+        // computed here (so no skip-ahead on the device)
+        BatchFlatInline in;
+        memset(&in, 0, sizeof in);
+        in.out = (uint64_t*)out;
+        in.n = nd;
+        uint64_t chunks = 0;
+        for (uint32_t k = 0; k < nd; ++k) {
+            const BatchDesc& D = dd[k];
+            FlatWin& w = in.w[k];
+            w.s = (uint32_t)(D.out_off & 1u);
+            const uint64_t src = p->indexed ? p->host_states[D.src] : D.src;
+            w.base = h_skip(src, (D.pos % kPeriod) + 1 - w.s);  // element -s
+            w.len = D.len;
+            w.out_off = D.out_off;
+            w.chunk0 = (uint32_t)chunks;
+            chunks += (D.len + w.s + kChunkOuts - 1) / kChunkOuts;
+        }
+        e = launch_batch_flat_inline(p->kind, p->nontemporal, (uint32_t)chunks, p->flat_lds,
+                                     stream, p->tabs, p->M1, p->J512, in);
+        if (e != hipSuccess) return fail(NN_EHIP, "batch launch: %s", hipGetErrorString(e));
+        e = hipEventRecord(q.done, stream);
+        if (e != hipSuccess) return fail(NN_EHIP, "batch event: %s", hipGetErrorString(e));
+        q.pending = true;
+        p->next ^= 1;
+        return NN_OK;
+    }
     if (in_args) {
         BatchInline in;
         memset(&in, 0, sizeof in);
@@ -411,10 +468,13 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     } else if (e == hipSuccess) {
         BatchArgs copy = q.args;
         void* params[] = {&copy};
-        if (p->interleaved) {
+        if (p->interleaved || p->chunks) {
             e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(p->map_grid), dim3(256),
                                 params, 0, stream);
-            if (e == hipSuccess)
+            if (e == hipSuccess && p->chunks)
+                e = hipLaunchKernel(batch_chunks_kernel(p->kind, p->nontemporal), dim3(p->grid),
+                                    dim3(kFlatBlock), params, 0, stream);
+            else if (e == hipSuccess)
                 e = hipLaunchKernel(batch_rows_kernel(p->kind, p->nontemporal), dim3(p->grid),
                                     dim3(p->block), params, 0, stream);
         } else {

@@ -469,7 +469,7 @@ int nn_server_create(const nn_server_cfg* cfg, const uint64_t* stream_states, ui
             return fail(NN_EHIP, "lane stream: %s", hipGetErrorString(e));
         }
         int st = plan_create((int)c.kind, c.max_batch_requests, c.max_batch_outputs, &c.batch,
-                             true, s->dev_states, &l.plan);
+                             true, s->dev_states, s->host_states.data(), &l.plan);
         if (st) {
             server_free(s);
             return st;

@@ -59,6 +59,28 @@ def _lookup(form, kind, size, path=CACHE):
     return dict(entry["cfg"]) if entry else {}
 
 
+#: The launch configurations bench.py times on the plain bulk workload, by
+#: output kind (make_cfg keyword arguments).  The full-size GPU parity tests
+#: run exactly these, so the timed kernels are the compared ones.
+BENCH_PLAIN = {
+    "f64": dict(layout="flat", mulmod="fp64", unroll=4, occupancy=4, temporal=True),
+    "u64": dict(layout="flat", mulmod="fp64", unroll=4, occupancy=4, temporal=True),
+}
+
+
+def bench_plain_cfg(kind):
+    """nn_launch_cfg of the benchmark's plain-bulk launch for `kind` ("f64"
+    or "u64")."""
+    import paper_1206_1187_amd as nn
+    return nn.make_cfg(**BENCH_PLAIN[kind])
+
+
+def bench_batch_kw(total, path=CACHE):
+    """BatchPlan keyword arguments of the benchmark's batched leg (f64,
+    `total` outputs): the tuned shape."""
+    return best_batch_cfg("f64", total, path)
+
+
 def best_plain_cfg(kind, count, path=CACHE):
     """make_cfg keyword arguments tuned for ``count`` outputs, or {}."""
     return _lookup("plain", kind, count, path)

@@ -95,6 +95,50 @@ def test_batch_bit_exact_mixed_lengths(kind, mulmod, interleaved):
             assert f == orc.skip(s, n)
 
 
+@pytest.mark.parametrize("kind", ["u64", "f64"])
+def test_chunked_batch_bit_exact_mixed_lengths(kind):
+    """The chunked kernel (records per 2048-output chunk and window, dealt
+    round-robin to persistent workgroups): windows shorter than a chunk,
+    several windows in one chunk, windows starting and ending inside chunks
+    at both offset parities, gaps between windows; grids from one workgroup
+    (every record on it) to more workgroups than records; graph and direct
+    launches; temporal and non-temporal stores."""
+    lengths = LENGTHS + [2047, 2048, 2049, 4095, 4096, 4097, 6143, 1, 2, 5, 3000, 1, 1]
+    states, lengths, offsets, total = _mixed_batch(13, lengths)
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    for grid, graph, temporal in [(0, True, False), (1, True, False), (3, False, True),
+                                  (7, True, True), (1000, True, False), (4096, False, False)]:
+        _say("chunked", kind, grid, graph, temporal)
+        buf = _sentinel(total)
+        with nn.BatchPlan(kind, 64, total, grid=grid, graph=graph, temporal=temporal,
+                          chunks=True) as plan:
+            assert plan.cfg().flags & 32
+            fin = plan.generate(states, lengths, offsets, buf.view(dt), final_states=True)
+            torch.cuda.synchronize()
+        _check_batch(_bits(buf), states, lengths, offsets, kind)
+        for s, n, f in zip(states.tolist(), lengths.tolist(), fin.tolist()):
+            assert f == orc.skip(s, n)
+
+
+def test_chunked_batch_dense_short_windows():
+    """Thousands of windows of 1 to 40 outputs packed back to back, so most
+    chunks hold dozens of windows (one record each), against the oracle."""
+    rng = np.random.default_rng(17)
+    lengths = [int(x) for x in rng.integers(1, 41, 3000)]
+    states, lengths, offsets, total = _mixed_batch(18, lengths)
+    buf = _sentinel(total)
+    with nn.BatchPlan("f64", 4096, total, chunks=True) as plan:
+        plan.generate(states, lengths, offsets, buf.view(torch.float64))
+        torch.cuda.synchronize()
+    _check_batch(_bits(buf), states, lengths, offsets, "f64")
+
+
+def test_chunked_batch_validation():
+    for bad in (dict(block=128), dict(cluster=4), dict(mulmod="shoup"), dict(interleaved=True)):
+        with pytest.raises(nn.NNError):
+            nn.BatchPlan("f64", 2, 1 << 20, chunks=True, **bad)
+
+
 def test_graph_replays_with_eager_work_between():
     """Replay one plan's graph many times with other work and syncs in
     between; every replay must equal the oracle."""
