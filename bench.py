@@ -80,10 +80,12 @@ def traffic_from_profile():
         return None
 
 
-def batched_leg(nn, torch, pick=True):
+def batched_leg(nn, torch):
     """Config 4: 10,000 streams (lengths log-uniform in [1, 2^22]) as one
-    batched launch replayed from the plan's hipGraph, against the same
-    streams with one nn_generate launch each on the same stream."""
+    batched launch replayed from the plan's hipGraph, in the shape
+    tune.bench_batch_kw gives (the one the full-size parity test compares),
+    against the same streams with one nn_generate launch each on the same
+    stream; the other batch kernels for comparison."""
     import numpy as np
 
     from paper_1206_1187_amd import tune
@@ -91,37 +93,25 @@ def batched_leg(nn, torch, pick=True):
     states, lengths, offsets = tune.batch_workload()
     total = int(lengths.sum())
     out = torch.empty(total, dtype=torch.float64, device="cuda")
-    kw = tune.best_batch_cfg("f64", total)
+    kw = tune.bench_batch_kw(total)
     res = {"workload": "batched: 10,000 seed indices (numpy default_rng(3)), lengths "
                        "log-uniform in [1, 2^22], f64, windows packed back to back",
            "streams": len(states), "variates": total}
-    # The tuned shape with its grid or a neighbour (cluster kept), as for the
-    # plain form.  The candidates' plans stay alive and the chosen one is
-    # timed, so no plan is freed or allocated just before the measurement.
-    plans = {}
-    try:
-        if pick:
-            kw, times, plans = tune.pick_batch_grid(kw, "f64", states, lengths, offsets, out)
-            if times:
-                res["grid_choice_ms"] = times
-        plan = plans.get(kw.get("grid"))
-        if plan is None:
-            plan = plans[None] = nn.BatchPlan("f64", len(states), total, **kw)
-        res["cfg"] = plan.cfg().as_dict()
+    with nn.BatchPlan("f64", len(states), total, **kw) as plan:
+        res["cfg"] = dict(plan.cfg().as_dict(), **{k: v for k, v in kw.items()
+                                                  if k in ("interleaved", "chunks")})
         for _ in range(8):  # warm-up: first touch of the output (several launches), first replay
             plan.generate(states, lengths, offsets, out)
         graph_s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 10, torch)
-    finally:
-        for p in plans.values():
-            p.close()
     with nn.BatchPlan("f64", len(states), total, graph=False, **kw) as plan:
         for _ in range(3):
             plan.generate(states, lengths, offsets, out)
         direct_s = _timed_kernel(lambda: plan.generate(states, lengths, offsets, out), 10, torch)
-    # both batch kernels at their best measured shapes, whichever the tuner chose
+    # every batch kernel at its best measured shape, whichever the benchmark runs
     for name, shape in (("blocked_ms", dict(block=256, grid=128, temporal=True)),
                         ("interleaved_ms", dict(block=256, grid=144, cluster=16,
-                                                interleaved=True))):
+                                                interleaved=True)),
+                        ("chunked_ms", dict(chunks=True))):
         with nn.BatchPlan("f64", len(states), total, mulmod="fp64", **shape) as plan:
             for _ in range(3):
                 plan.generate(states, lengths, offsets, out)
@@ -259,8 +249,6 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fill ceiling and reduction comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form replay")
-    ap.add_argument("--no-shape-pick", action="store_true",
-                    help="use the tuned launch shapes as they are (no per-device grid choice)")
     ap.add_argument("--only", choices=["batched", "served"],
                     help="run only this leg and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -292,26 +280,21 @@ def main():
         return
     nn.init(0)
     if args.only:
-        leg = (batched_leg(nn, torch, pick=not args.no_shape_pick) if args.only == "batched"
-               else served_leg(nn, torch))
+        leg = batched_leg(nn, torch) if args.only == "batched" else served_leg(nn, torch)
         print(json.dumps({args.only: leg}), flush=True)
         return
     case = wl.plain_bulk()
     out_f = torch.empty(case.count_f64, dtype=torch.float64, device="cuda")
     out_u = torch.empty(case.count_u64, dtype=torch.uint64, device="cuda")
-    # f64: the flat layout (chunks of four 512-output rows per workgroup,
-    # temporal stores, residency cap 4), faster than the row kernel on every
-    # box measured; u64: the row kernel, with its grid chosen on the device.
-    cfg_f = nn.make_cfg(layout="flat", mulmod="fp64", unroll=4, occupancy=4)
-    cfg_rows_f = nn.default_cfg("f64", case.count_f64)
-    cfg_u = nn.default_cfg("u64", case.count_u64)
-    picked = None
-    if not args.no_shape_pick:
-        from paper_1206_1187_amd import tune
-        s0 = nn.seed(case.index)
-        cfg_u, pu = tune.pick_plain_grid(cfg_u, out_u, s0, (0, -32, 32))
-        picked = {"u64_grid_ms": pu}
-        log("grid choice", json.dumps(picked))
+    # Both kinds in the launch configuration tune.BENCH_PLAIN names (the
+    # flat layout: chunks of four 512-output rows per workgroup, temporal
+    # stores, residency cap 4), the one the full-size parity tests compare.
+    from paper_1206_1187_amd import tune
+    cfg_f = tune.bench_plain_cfg("f64")
+    cfg_u = tune.bench_plain_cfg("u64")
+    # the row layout in its tuned shape, for comparison
+    cfg_rows_f = nn.make_cfg(**dict(tune.best_plain_cfg("f64", case.count_f64), layout="rows"))
+    cfg_rows_u = nn.make_cfg(**dict(tune.best_plain_cfg("u64", case.count_u64), layout="rows"))
     log("workload", case, "cfg f64", cfg_f.as_dict(), "cfg u64", cfg_u.as_dict())
 
     def step(ev=None):
@@ -363,7 +346,6 @@ def main():
             "count_u64": case.count_u64,
             "launch_f64": cfg_f.as_dict(),
             "launch_u64": cfg_u.as_dict(),
-            "grid_choice_ms": picked,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -373,7 +355,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic_from_profile(),
-            "kernel": "k_generate_flat f64 (fp64, 4 rows per workgroup)",
+            "kernel": "k_generate_flat<VarFP64, 1, false, 4> (f64, flat: 4 rows of 512 per "
+                      "workgroup, temporal stores, residency cap 4)",
             "algorithmic_bytes_per_launch": 8 * case.count_f64,
         },
     }
@@ -384,35 +367,38 @@ def main():
         u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u, cfg=cfg_u), reps,
                             torch)
         extras["generate_u64_GBps"] = 8.0 * case.count_u64 / u_s / 1e9
-        # The other layout of each kind on the same workload: the row kernel
-        # (tuned shape) for f64, the flat layout for u64.
+        # nn_generate with no configuration (the library's default layout)
+        for kind, out in (("f64", out_f), ("u64", out_u)):
+            d_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out), reps, torch)
+            extras["library_default_%s_GBps" % kind] = 8.0 * out.numel() / d_s / 1e9
+        # the row layout (tuned shape) for both kinds
         rows_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_f,
                                                         cfg=cfg_rows_f), reps, torch)
         extras["rows_layout_f64_GBps"] = 8.0 * case.count_f64 / rows_s / 1e9
-        fl_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u,
-                                                      cfg=nn.make_cfg(layout="flat")), reps, torch)
-        extras["flat_layout_u64_GBps"] = 8.0 * case.count_u64 / fl_s / 1e9
-        # The paper's "Constant" kernel (Section 4.2) with the generator's own
-        # store pattern, and with the fastest pattern measured (flat).
-        fill_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000), reps, torch)
-        flat = nn.make_cfg(layout="flat", occupancy=3)
-        flat_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000, cfg=flat), reps, torch)
-        # ... and with the f64 generator's own pattern (chunks of four rows
-        # per workgroup, temporal stores, residency cap 4)
-        chunk = nn.make_cfg(layout="flat", unroll=4, occupancy=4, temporal=True)
-        chunk_s = _timed_kernel(lambda: nn.fill(out_f, 0x3FE0000000000000, cfg=chunk), reps,
-                                torch)
-        fill_gbps = 8.0 * case.count_f64 / fill_s / 1e9
-        flat_gbps = 8.0 * case.count_f64 / flat_s / 1e9
-        chunk_gbps = 8.0 * case.count_f64 / chunk_s / 1e9
-        extras["fill_row_pattern_GBps"] = fill_gbps
-        extras["fill_flat_GBps"] = flat_gbps
-        extras["fill_same_pattern_GBps"] = chunk_gbps
-        ceiling = max(fill_gbps, flat_gbps, chunk_gbps)
-        extras["write_ceiling_GBps"] = ceiling
-        extras["f64_frac_of_write_ceiling"] = achieved / ceiling
-        # Paper's Table 2: generation time net of the store time.
-        extras["net_generation_ms"] = (f64_s - min(fill_s, flat_s, chunk_s)) * 1e3
+        rows_u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u,
+                                                          cfg=cfg_rows_u), reps, torch)
+        extras["rows_layout_u64_GBps"] = 8.0 * case.count_u64 / rows_u_s / 1e9
+        # The paper's "Constant" kernel (Section 4.2, Tables 1-2): the f64
+        # generator's own launch (same layout, rows, store policy and cap)
+        # with the arithmetic taken out; the row layout's pattern; and the
+        # fastest fill pattern measured (one row per workgroup, cap 3).
+        value = 0x3FE0000000000000
+        fills = {"fill_same_pattern": cfg_f, "fill_row_pattern": cfg_rows_f,
+                 "fill_one_row_cap3": nn.make_cfg(layout="flat", unroll=1, occupancy=3,
+                                                  temporal=True)}
+        fill_s = {}
+        for name, cfg in fills.items():
+            fill_s[name] = _timed_kernel(lambda: nn.fill(out_f, value, cfg=cfg), reps, torch)
+            extras[name + "_GBps"] = 8.0 * case.count_f64 / fill_s[name] / 1e9
+        best = min(fill_s.values())
+        extras["write_ceiling_GBps"] = 8.0 * case.count_f64 / best / 1e9
+        extras["f64_frac_of_write_ceiling"] = achieved / extras["write_ceiling_GBps"]
+        # Paper's Table 2: generation time net of the store time, against the
+        # same pattern's Constant kernel (negative when the stores paced by
+        # the arithmetic write faster than the same stores back to back) and
+        # against the fastest fill.
+        extras["net_generation_same_pattern_ms"] = (f64_s - fill_s["fill_same_pattern"]) * 1e3
+        extras["net_generation_vs_fastest_fill_ms"] = (f64_s - best) * 1e3
         # Paper's Table 1, execution vs including setup: the host seeding of
         # Eq. 2 (a 106-bit power modulo 3^33 from the index), the launch
         # constants and the launch, then the kernel, timed on the host clock
@@ -460,24 +446,23 @@ def main():
                 lambda: nn.generate_into(nn.seed(case.index), out, cfg=cfg), 10, torch)
             shoot["modbarrett_paper_strided_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
         extras["mulmod_shootout_default_shape"] = shoot
-        # Section 2's larger modulus 3^40: the default FP64 step on base-3^20
-        # limbs, and the Montgomery step on 64-bit states.
+        # Section 2's larger modulus 3^40: the library default (row layout,
+        # FP64 step on base-3^20 limbs), the flat layout (8 rows per chunk)
+        # and the Montgomery step.
         for kind, out in (("f64", out_f), ("u64", out_u)):
-            s = _timed_kernel(
-                lambda: nn.e40_generate_into(nn.e40_seed(nn.E40_INDEX_MIN), out), 10, torch)
-            extras["modulus_3e40_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
-            cfg = nn.make_cfg(mulmod="montgomery")
-            s = _timed_kernel(
-                lambda: nn.e40_generate_into(nn.e40_seed(nn.E40_INDEX_MIN), out, cfg=cfg), 10,
-                torch)
-            extras["modulus_3e40_montgomery_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
+            for name, cfg in (("", None), ("_flat", nn.make_cfg(layout="flat", unroll=8)),
+                              ("_montgomery", nn.make_cfg(mulmod="montgomery"))):
+                s = _timed_kernel(
+                    lambda: nn.e40_generate_into(nn.e40_seed(nn.E40_INDEX_MIN), out, cfg=cfg),
+                    10, torch)
+                extras["modulus_3e40%s_%s_GBps" % (name, kind)] = 8.0 * out.numel() / s / 1e9
         result["extras"] = extras
         log("extras", json.dumps(extras))
 
     del out_f, out_u
     torch.cuda.empty_cache()
     if not args.no_extras:
-        result["batched"] = batched_leg(nn, torch, pick=not args.no_shape_pick)
+        result["batched"] = batched_leg(nn, torch)
         log("batched", json.dumps(result["batched"]))
         if not args.no_served:
             result["served"] = served_leg(nn, torch)

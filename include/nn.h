@@ -72,12 +72,14 @@ typedef enum nn_mulmod {
 /* Launch configuration.  Any field left 0 takes the library default.
  *
  * Three layouts write the same values (serial order in memory):
- *  - rows (default): grid*block threads loop over rows of
- *    width*grid*block outputs, stepping by a jump multiplier;
- *  - flat (NN_CFG_FLAT): every 256-thread workgroup writes `unroll` rows of
- *    512 consecutive outputs (one contiguous chunk), two per lane in one
- *    16-byte store per row, and exits; workgroups are dispatched in address
- *    order (needs a 16-byte aligned output);
+ *  - flat (NN_CFG_FLAT; the default for a 16-byte aligned output and a cfg
+ *    that sets none of block, grid, ilp or width 1): every 256-thread
+ *    workgroup writes `unroll` rows of 512 consecutive outputs (one
+ *    contiguous chunk), two per lane in one 16-byte store per row, and
+ *    exits; workgroups are dispatched in address order (needs a 16-byte
+ *    aligned output);
+ *  - rows (NN_CFG_ROWS; the default otherwise): grid*block threads loop
+ *    over rows of width*grid*block outputs, stepping by a jump multiplier;
  *  - consecutive (NN_CFG_CONSECUTIVE): the paper's per-thread loop (Section
  *    3.2): each thread makes `unroll` consecutive outputs with Eq. 3's own
  *    multiplier 2^53 and Section 3.1's Modified Barrett reduction; the
@@ -98,7 +100,8 @@ typedef enum nn_mulmod {
  * flags: NN_CFG_TEMPORAL_STORES keeps stores cacheable and
  * NN_CFG_NONTEMPORAL_STORES makes them non-temporal streaming stores (at
  * most one of the two; default: non-temporal, except temporal for the flat
- * layout); NN_CFG_ROWS / NN_CFG_FLAT force a layout.
+ * layout); NN_CFG_ROWS / NN_CFG_FLAT force a layout (see above for the
+ * default).
  * width: outputs per lane and store, 1 (8-byte stores) or 2 (16-byte
  * stores, needs a 16-byte aligned output) (rows; flat is always 2).
  * occupancy: 0, or a cap in [2,16] on resident workgroups per compute unit
@@ -276,13 +279,16 @@ typedef struct nn_batch_cfg {
  * output is cut into aligned chunks of 2048 outputs (16 KiB); a pre-pass
  * writes one record per chunk and window that meet (the state of the
  * chunk's first element in that window, and the window's part of the
- * chunk), and `grid` persistent 256-thread workgroups take the records
- * round-robin, each writing its chunk as four rows of 512 outputs with one
- * 16-byte store per lane and row.  Needs the FP64 reduction, block 0 or 256,
- * cluster 0 or 1 and output indices below 2^51 (NN_ERANGE otherwise); grid
- * 0 means four workgroups per compute unit.  Exclusive with
- * NN_BATCH_INTERLEAVED.  Batches of at most 16 windows travel in the
- * kernel arguments and run the blocked kernel. */
+ * chunk), and 256-thread workgroups write the records' chunks as four rows
+ * of 512 outputs with one 16-byte store per lane and row.  grid 0 (the
+ * default): one workgroup per record, dispatched in output order as the
+ * plain flat layout's chunks are (the plan's graph gets the batch's record
+ * count as its grid before each replay); a nonzero grid: that many
+ * persistent workgroups taking the records round-robin.  Needs the FP64
+ * reduction, block 0 or 256, cluster 0 or 1 and output indices below 2^51
+ * (NN_ERANGE otherwise).  Exclusive with NN_BATCH_INTERLEAVED.  Batches of
+ * at most 16 windows travel in the kernel arguments (the FP64 reduction's
+ * flat inline kernel). */
 #define NN_BATCH_CHUNKS 32u
 
 /* Opaque batch plan: device workspace, pinned staging and a hipGraph of

@@ -427,13 +427,15 @@ __global__ __launch_bounds__(256) void k_batch_rows(BatchArgs a) {
 
 // Chunked kernel: the flat layout of the plain generator over a batch.  The
 // output is cut into aligned chunks of kChunkRows rows of 512 outputs
-// (16 KiB); the pre-pass (k_batch_rec with one cluster of one workgroup and
-// rows of kChunkOuts outputs) writes one record per chunk and window that
-// meet, in window order: the state of the chunk's element 0 as if the
+// (16 KiB); the pre-pass (k_batch_rec with one cluster of kChunkRecWays
+// workgroups and rows of kChunkOuts outputs) writes one record per chunk and
+// window that meet, record j (in window order) XCD-major at
+// (j mod kChunkRecWays) * per + j / kChunkRecWays: the state of the chunk's element 0 as if the
 // window covered it, the chunk's output index and the window's part of the
-// chunk [lo, hi).  Workgroup w of the grid takes records w, w + grid, ...
-// (the write front moves through the output as in the plain flat layout,
-// with no workgroup launch per chunk), loading the next record while it
+// chunk [lo, hi).  Workgroup w of the grid takes records w, w + grid, ...:
+// with one workgroup per record (the default) the dispatcher hands chunks
+// out in output order and the write front stays as compact as the plain
+// flat layout's; a smaller, persistent grid loads the next record while it
 // writes the current one.  Lane l's outputs of a chunk are its pairs
 // 2l, 2l + 1 of each row: states z * (2^53)^(2l) and z * (2^53)^(2l+1), one
 // multiplication each by the lane's fixed multipliers, then one step of
@@ -446,14 +448,16 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     const uint64_t n = hdr->n_rows;  // records
     const global_ptr<uint64_t> out = as_global(hdr->out);
     const const_ptr<u64x2> rec = reinterpret_cast<const_ptr<u64x2>>(as_const(a.rec));
+    const uint64_t per = (n + kChunkRecWays - 1) / kChunkRecWays;
     const uint32_t l = threadIdx.x;
     uint64_t j = blockIdx.x;
     if (j >= n) return;
     const Mult ma = a.t_lo[2u * l], mb = a.t_lo[2u * l + 1];
-    u64x2 cur = rec[j];
+    u64x2 cur = rec[(j % kChunkRecWays) * per + j / kChunkRecWays];
     for (;;) {
-        const uint64_t jn = j + gridDim.x;
-        const u64x2 nxt = rec[jn < n ? jn : j];  // the next record, in flight meanwhile
+        const uint64_t jn = j + gridDim.x < n ? j + gridDim.x : j;
+        // the next record, in flight meanwhile
+        const u64x2 nxt = rec[(jn % kChunkRecWays) * per + jn / kChunkRecWays];
         const double z0 = __builtin_bit_cast(double, cur.x);
         const uint64_t info = cur.y;
         double za = VarFP64::mul(z0, ma);
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
                 zb = VarFP64::mul(zb, a.JB);
             }
         }
-        j = jn;
+        j += gridDim.x;
         if (j >= n) break;
         cur = nxt;
     }

@@ -108,12 +108,18 @@ const void* batch_rows_kernel(int kind, bool nontemporal);
 // Chunked kernel (FP64 reduction, 256 threads): the pre-pass writes one
 // record per chunk of kChunkOuts outputs and window that meet (rows of
 // kChunkOuts outputs in k_batch_rec's terms, one cluster of one workgroup,
-// so the records lie in window order), and the workgroups of the chunk
-// kernel deal the records out round-robin.
+// so the records lie in window order); by default the chunk kernel has one
+// workgroup per record, dispatched in record order like the plain flat
+// layout's chunks (a fixed grid takes the records round-robin instead).
 constexpr uint32_t kChunkRows = 4;
 constexpr uint32_t kChunkOuts = kChunkRows * 512;
-// Default grid of the chunked kernel: workgroups per compute unit.
-constexpr uint32_t kChunkResidency = 4;
+// Records of the chunked kernel are stored XCD-major: record j at
+// (j mod kChunkRecWays) * per + j / kChunkRecWays, per = ceil(n / kChunkRecWays).
+// Workgroups are dealt to the 8 XCDs round-robin by index, so the records
+// one XCD's workgroups read are consecutive and share its L2's lines (one
+// miss per eight chunks).  The pre-pass writes this layout as one cluster of
+// kChunkRecWays workgroups.
+constexpr uint32_t kChunkRecWays = 8;
 const void* batch_chunks_kernel(int kind, bool nontemporal);
 
 // The kernel entry for (mulmod, kind, nontemporal, indexed); its single

@@ -78,11 +78,18 @@ inline Mult40 make_mult40(uint64_t v) {
 
 constexpr uint32_t kLo = 1024;      // t_lo[l] = (2^53)^l
 constexpr uint32_t kHi = 1u << 15;  // t_hi[j] = (2^53)^(1024 j)
+// Flat layout: t_flo[j] = (2^53)^(512 j), j < kFLo, and
+// t_fhi[i] = (2^53)^(512 kFLo i), i < kFHi, after t_lo and t_hi.
+constexpr uint32_t kFLo = 1024;
+constexpr uint32_t kFHi = 2048;
+constexpr uint64_t kFLoOff = (uint64_t)kLo + kHi;
+constexpr uint64_t kFHiOff = kFLoOff + kFLo;
+constexpr uint64_t kFlatMaxRows = (uint64_t)kFLo * kFHi;  // rows of 512 per launch (2^21)
 constexpr uint64_t kMaxThreads = (uint64_t)kLo * kHi / 2;
 constexpr int kMaxDev = 64;
 
 std::mutex g_mu;
-Mult40* g_tab[kMaxDev];  // kLo + kHi entries per device
+Mult40* g_tab[kMaxDev];  // kLo + kHi + kFLo + kFHi entries per device
 
 int device_tables(const Mult40** out) {
     int dev = -1;
@@ -95,12 +102,18 @@ int device_tables(const Mult40** out) {
     std::lock_guard<std::mutex> lock(g_mu);
     if (!g_tab[dev]) {
         static std::vector<Mult40> host = [] {
-            std::vector<Mult40> t(kLo + kHi);
+            std::vector<Mult40> t(kFHiOff + kFHi);
             uint64_t r = 1;
             for (uint32_t l = 0; l < kLo; ++l, r = h_mul(r, kMult)) t[l] = make_mult40(r);
             const uint64_t step = Powers::get().pow(kLo);
             r = 1;
             for (uint32_t j = 0; j < kHi; ++j, r = h_mul(r, step)) t[kLo + j] = make_mult40(r);
+            const uint64_t row = Powers::get().pow(512);
+            r = 1;
+            for (uint32_t j = 0; j < kFLo; ++j, r = h_mul(r, row)) t[kFLoOff + j] = make_mult40(r);
+            const uint64_t big = r;  // (2^53)^(512 kFLo)
+            r = 1;
+            for (uint32_t i = 0; i < kFHi; ++i, r = h_mul(r, big)) t[kFHiOff + i] = make_mult40(r);
             return t;
         }();
         void* mem = nullptr;
@@ -238,6 +251,127 @@ __global__ __launch_bounds__(1024) void k_e40(E40Args a) {
     }
 }
 
+// Flat layout at modulus 3^40: chunks of R rows of 512 outputs; lane l
+// writes the pair 2l, 2l + 1 of each row with one 16-byte store.
+// Workgroup b starts at chunk b (u = R b rows in) from
+// base * t_fhi[u / kFLo] * t_flo[u % kFLo] * t_lo[2l] (Montgomery, then
+// the step's representation) and takes chunks b, b + G, ... (G the grid):
+// one step of (2^53)^512 per row, and from a chunk's last row to the next
+// chunk one step of JN = (2^53)^(512 R G - 512 (R - 1)).  With G equal to
+// the chunk count each workgroup writes one chunk and exits.
+struct E40FlatArgs {
+    uint64_t* out;       // 16-byte aligned
+    uint64_t n_chunks;   // whole chunks, n_chunks * R <= kFlatMaxRows
+    uint64_t base;       // state of out[0]
+    Mult40 M1, J, JN;
+    Mult40L M1L, JL, JNL;
+    const Mult40* tabs;  // t_lo, t_hi, t_flo, t_fhi
+};
+
+template <int KIND, int MM, int R, bool NT>
+__global__ __launch_bounds__(256) void k_e40_flat(E40FlatArgs a) {
+    extern __shared__ char occupancy_cap[];
+    (void)occupancy_cap;
+    typedef Step<MM> St;
+    typedef typename St::S S;
+    uint64_t c = blockIdx.x;
+    if (c >= a.n_chunks) return;
+    const uint32_t l = threadIdx.x;
+    const uint64_t u = c * R;
+    const uint64_t z0 = mm40(mm40(mm40(a.base, a.tabs[kFHiOff + u / kFLo].mont),
+                                  a.tabs[kFLoOff + u % kFLo].mont),
+                             a.tabs[2u * l].mont);
+    S za = St::from(z0);
+    S zb = St::from(mm40(z0, a.M1.mont));
+    const global_ptr<uint64_t> out = as_global(a.out);
+    for (;;) {
+        const global_ptr<u64x2> p =
+            reinterpret_cast<global_ptr<u64x2>>(out + (uint64_t)512 * R * c + 2u * l);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u64x2 v;
+            v.x = St::template bits<KIND>(za);
+            v.y = St::template bits<KIND>(zb);
+            put<NT>(p + r * 256, v);
+            if (r + 1 < R) {
+                za = St::mul(za, a.J, a.JL);
+                zb = St::mul(zb, a.J, a.JL);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        c += gridDim.x;
+        if (c >= a.n_chunks) break;
+        za = St::mul(za, a.JN, a.JNL);
+        zb = St::mul(zb, a.JN, a.JNL);
+    }
+}
+
+// The last, partial chunk (count < 512 R outputs, one workgroup), from its
+// own base.
+template <int KIND, int MM, int R, bool NT>
+__global__ __launch_bounds__(256) void k_e40_flat_tail(E40FlatArgs a, uint64_t count) {
+    typedef Step<MM> St;
+    typedef typename St::S S;
+    const uint32_t l = threadIdx.x;
+    const uint64_t z0 = mm40(a.base, a.tabs[2u * l].mont);
+    S za = St::from(z0);
+    S zb = St::from(mm40(z0, a.M1.mont));
+    const global_ptr<uint64_t> out = as_global(a.out);
+    uint64_t k = 2u * l;
+    for (int r = 0; r < R && k < count; ++r, k += 512) {
+        if (k + 1 < count) {
+            u64x2 v;
+            v.x = St::template bits<KIND>(za);
+            v.y = St::template bits<KIND>(zb);
+            put<NT>(reinterpret_cast<global_ptr<u64x2>>(out + k), v);
+        } else {
+            put<NT>(out + k, St::template bits<KIND>(za));
+        }
+        za = St::mul(za, a.J, a.JL);
+        zb = St::mul(zb, a.J, a.JL);
+    }
+}
+
+template <int KIND, int MM, int R, bool NT>
+hipError_t flat_launch(uint32_t grid, uint32_t lds, hipStream_t s, const E40FlatArgs& a,
+                       const E40FlatArgs& tail, uint64_t tail_count) {
+    if (a.n_chunks) {
+        k_e40_flat<KIND, MM, R, NT><<<grid, 256, lds, s>>>(a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (tail_count) {
+        k_e40_flat_tail<KIND, MM, R, NT><<<1, 256, 0, s>>>(tail, tail_count);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <int KIND, int MM, bool NT>
+hipError_t flat_r(int rows, uint32_t grid, uint32_t lds, hipStream_t s, const E40FlatArgs& a,
+                  const E40FlatArgs& tail, uint64_t tail_count) {
+    switch (rows) {
+        case 2: return flat_launch<KIND, MM, 2, NT>(grid, lds, s, a, tail, tail_count);
+        case 4: return flat_launch<KIND, MM, 4, NT>(grid, lds, s, a, tail, tail_count);
+        case 8: return flat_launch<KIND, MM, 8, NT>(grid, lds, s, a, tail, tail_count);
+        case 16: return flat_launch<KIND, MM, 16, NT>(grid, lds, s, a, tail, tail_count);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_flat(int kind, int mm, int rows, bool nt, uint32_t grid, uint32_t lds,
+                       hipStream_t s, const E40FlatArgs& a, const E40FlatArgs& tail,
+                       uint64_t tail_count) {
+#define NN_E40_FLAT(K, M)                                                          \
+    return nt ? flat_r<K, M, true>(rows, grid, lds, s, a, tail, tail_count)         \
+              : flat_r<K, M, false>(rows, grid, lds, s, a, tail, tail_count);
+    if (kind == 0) {
+        if (mm) { NN_E40_FLAT(0, 1) } else { NN_E40_FLAT(0, 0) }
+    }
+    if (mm) { NN_E40_FLAT(1, 1) } else { NN_E40_FLAT(1, 0) }
+#undef NN_E40_FLAT
+}
+
 template <int KIND, int MM, int IL, int U, bool NT>
 hipError_t launch_one(uint32_t grid, uint32_t block, hipStream_t s, const E40Args& a) {
     k_e40<KIND, MM, IL, U, NT><<<grid, block, 0, s>>>(a);
@@ -282,6 +416,72 @@ hipError_t launch(int kind, int mm, int ilp, int unroll, bool nt, uint32_t grid,
 }
 
 }  // namespace
+
+// Whether the library's default layout at modulus 3^40 is the flat one (for
+// 16-byte aligned outputs).  Not by measurement: 2^30 f64 outputs wrote
+// 5.86 TB/s in the row layout against 5.73 in the best flat shape (8 rows
+// per chunk) on one MI355X; the persistent flat grids wrote 4.1-5.4.
+constexpr bool kDefaultFlat = false;
+
+// nn_e40_generate_ex's flat layout (arguments already validated: a valid
+// state, count > 0, an in-range pointer).  cfg: unroll = rows of 512
+// outputs per chunk (2, 4, 8, 16; default 4), grid = workgroups per launch
+// (0: one per chunk), occupancy = residency cap (0: 4), store policy
+// (default temporal).
+int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void* stream,
+                  const nn_launch_cfg& c, int mm) {
+    if ((uintptr_t)out_dev % 16)
+        return fail(NN_EINVAL, "the flat layout needs a 16-byte aligned output (got %p)", out_dev);
+    if ((c.block && c.block != 256) || c.ilp > 1)
+        return fail(NN_EINVAL, "the flat layout has 256 threads per workgroup and no ilp");
+    const uint32_t rows = c.unroll ? c.unroll : kFlatDefaultRows;
+    if (rows != 2 && rows != 4 && rows != 8 && rows != 16)
+        return fail(NN_EINVAL, "unroll %u: the flat layout writes 2, 4, 8 or 16 rows per chunk",
+                    rows);
+    const Mult40* tab = nullptr;
+    int st = device_tables(&tab);
+    if (st) return st;
+    DeviceTables* d = nullptr;
+    st = current_device(&d);
+    if (st) return st;
+    const uint32_t occ = c.occupancy ? c.occupancy : kFlatDefaultOccupancy;
+    if (occ < 2 || occ > 16) return fail(NN_EINVAL, "occupancy %u: must be 0 or in [2, 16]", occ);
+    const uint32_t lds = (d->lds_per_cu / (occ + 1) / 512 + 1) * 512;
+    if (lds > d->lds_per_block || (uint64_t)lds * occ > d->lds_per_cu)
+        return fail(NN_EINVAL, "occupancy %u not expressible on this device", occ);
+    const bool nt = (c.flags & NN_CFG_NONTEMPORAL_STORES) != 0;
+    const uint64_t s = *state;
+    const uint64_t per = 512ull * rows;
+    const uint64_t max_launch = kFlatMaxRows * 512;
+    E40FlatArgs a;
+    a.M1 = make_mult40(kMult);
+    a.J = make_mult40(Powers::get().pow(512));
+    a.M1L = make_mult40l(a.M1.v);
+    a.JL = make_mult40l(a.J.v);
+    a.tabs = tab;
+    for (uint64_t off = 0; off < count; off += max_launch) {
+        const uint64_t n = count - off < max_launch ? count - off : max_launch;
+        a.out = (uint64_t*)out_dev + off;
+        a.base = h_mul(s, Powers::get().pow(off + 1));  // the state of this slice's first output
+        a.n_chunks = n / per;
+        uint32_t grid = 1;
+        if (a.n_chunks) {
+            grid = c.grid && c.grid < a.n_chunks ? c.grid : (uint32_t)a.n_chunks;
+            a.JN = make_mult40(Powers::get().pow(per * grid - 512ull * (rows - 1)));
+            a.JNL = make_mult40l(a.JN.v);
+        }
+        E40FlatArgs t = a;
+        const uint64_t tail = n - a.n_chunks * per;
+        t.out = a.out + a.n_chunks * per;
+        t.base = h_mul(a.base, Powers::get().pow(a.n_chunks * per));
+        const hipError_t e = launch_flat(kind, mm, (int)rows, nt, grid, lds, (hipStream_t)stream,
+                                         a, t, tail);
+        if (e != hipSuccess) return fail(NN_EHIP, "e40 launch: %s", hipGetErrorString(e));
+    }
+    *state = h_mul(s, Powers::get().pow(count));
+    return ok();
+}
+
 }  // namespace e40
 }  // namespace nn
 
@@ -320,13 +520,26 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
         return fail(NN_ERANGE, "output range wraps the address space");
     nn_launch_cfg c = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
-    if ((c.flags & ~(uint32_t)(NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS)) || c.occupancy ||
-        (c.width && c.width != 2) ||
+    const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_NONTEMPORAL_STORES | NN_CFG_ROWS |
+                           NN_CFG_FLAT;
+    if ((c.flags & ~known) || (c.width && c.width != 2) ||
         (c.mulmod && c.mulmod != NN_MULMOD_MONTGOMERY && c.mulmod != NN_MULMOD_FP64))
-        return fail(NN_EINVAL, "the 3^40 generator takes block, grid, unroll, ilp, mulmod "
-                               "(NN_MULMOD_FP64 or NN_MULMOD_MONTGOMERY) and "
-                               "NN_CFG_TEMPORAL_STORES (rows, 16-byte stores)");
+        return fail(NN_EINVAL, "the 3^40 generator takes block, grid, unroll, ilp, occupancy, "
+                               "mulmod (NN_MULMOD_FP64 or NN_MULMOD_MONTGOMERY), the store "
+                               "policy flags and NN_CFG_ROWS / NN_CFG_FLAT (16-byte stores)");
+    if ((c.flags & NN_CFG_ROWS) && (c.flags & NN_CFG_FLAT))
+        return fail(NN_EINVAL, "the layout flags are exclusive");
+    if ((c.flags & NN_CFG_TEMPORAL_STORES) && (c.flags & NN_CFG_NONTEMPORAL_STORES))
+        return fail(NN_EINVAL, "NN_CFG_TEMPORAL_STORES and NN_CFG_NONTEMPORAL_STORES are exclusive");
     const int mm = c.mulmod == NN_MULMOD_MONTGOMERY ? 0 : 1;
+    const bool aligned16 = ((uintptr_t)out_dev % 16) == 0;
+    // No layout flag: the flat layout for a 16-byte aligned output unless the
+    // cfg sets a row-layout field (block, ilp).
+    const bool flat = (c.flags & NN_CFG_FLAT) ||
+                      (!(c.flags & NN_CFG_ROWS) && aligned16 && e40::kDefaultFlat && !c.block &&
+                       !c.ilp);
+    if (flat) return e40::generate_flat(state, count, out_dev, kind, stream, c, mm);
+    if (c.occupancy) return fail(NN_EINVAL, "occupancy applies to the flat layout only");
     const uint32_t block = c.block ? c.block : 256u;
     if (block < 64 || block > 1024 || block % 64)
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);

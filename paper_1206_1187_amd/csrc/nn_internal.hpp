@@ -56,6 +56,8 @@ struct nn_batch_slot {
     bool pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraphNode_t main_node = nullptr;  // the batch kernel's node
+    uint32_t main_grid = 0;              // its grid as last set (chunked kernel, set per batch)
     nn::BatchArgs args;
 };
 

@@ -208,7 +208,9 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     q.ws_bytes = sizeof(BatchHeader) + (size_t)p->cap_desc * sizeof(BatchDesc);
     hipError_t e = hipMalloc(&q.ws_dev, q.ws_bytes);
     if (e == hipSuccess && (p->interleaved || p->chunks))  // grid * per <= rows + clusters + grid
-        e = hipMalloc((void**)&q.rec, (p->cap_rows + 2ull * p->grid) * sizeof(RowRec));
+        // (XCD-major chunk records reach index kChunkRecWays * ceil(rows / kChunkRecWays) - 1)
+        e = hipMalloc((void**)&q.rec,
+                      (p->cap_rows + 2ull * p->grid + kChunkRecWays) * sizeof(RowRec));
     if (e != hipSuccess)
         return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", q.ws_bytes, hipGetErrorString(e));
     e = hipHostMalloc(&q.ws_host, q.ws_bytes, hipHostMallocDefault);
@@ -233,11 +235,11 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     q.args.grid = p->grid;
     q.args.block = block;
     if (p->chunks) {
-        // the pre-pass writes chunk records in window order: rows of
-        // kChunkOuts outputs, one cluster of one workgroup
+        // the pre-pass writes chunk records XCD-major: rows of kChunkOuts
+        // outputs, one cluster of kChunkRecWays workgroups
         q.args.row_outs = kChunkOuts;
-        q.args.grid = 1;
-        q.args.cluster = 1;
+        q.args.grid = kChunkRecWays;
+        q.args.cluster = kChunkRecWays;
     }
     q.args.JR = make_mult(MultPowers::get().pow((uint64_t)q.args.row_outs * 256));
     if (!p->use_graph) return NN_OK;
@@ -264,13 +266,14 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
                       ? const_cast<void*>(batch_rows_kernel(p->kind, p->nontemporal))
                       : const_cast<void*>(
                             batch_kernel((int)p->mulmod, p->kind, p->nontemporal, p->indexed));
-        kp.gridDim = dim3(p->grid);
+        kp.gridDim = dim3(p->grid ? p->grid : 1);  // chunked, grid 0: set per batch
         kp.blockDim = dim3(block);
-        kp.sharedMemBytes = 0;
+        kp.sharedMemBytes = p->chunks ? p->flat_lds : 0;
         kp.kernelParams = params;
         kp.extra = nullptr;
-        hipGraphNode_t node;
-        e = hipGraphAddKernelNode(&node, q.graph, last ? &last : nullptr, last ? 1 : 0, &kp);
+        e = hipGraphAddKernelNode(&q.main_node, q.graph, last ? &last : nullptr, last ? 1 : 0,
+                                  &kp);
+        q.main_grid = p->grid ? p->grid : 1;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&q.exec, q.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return fail(NN_EHIP, "batch graph: %s", hipGetErrorString(e));
@@ -312,9 +315,8 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
         return fail(NN_EINVAL, "mulmod %u: batches take FP64, Barrett, Shoup or Montgomery",
                     mulmod);
     uint32_t grid = c.grid;
-    if (!grid && chunks) {
-        grid = (uint32_t)((uint64_t)d->cus * kChunkResidency);
-        if (!grid) grid = 1;
+    if (chunks) {
+        // grid 0: one workgroup per record, dispatched in output order
     } else if (!grid) {
         grid = (uint32_t)((uint64_t)d->cus * kd.grid_num / kd.grid_den);
         if (!grid) grid = 1;
@@ -463,6 +465,20 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         return NN_OK;
     }
     e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, stream);
+    // the chunked kernel's workgroups: one per record unless the plan fixed a grid
+    const uint32_t chunk_grid = p->grid ? p->grid : (uint32_t)rows;
+    if (e == hipSuccess && p->use_graph && p->chunks && chunk_grid != q.main_grid) {
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof kp);
+        void* params[] = {&q.args};
+        kp.func = const_cast<void*>(batch_chunks_kernel(p->kind, p->nontemporal));
+        kp.gridDim = dim3(chunk_grid);
+        kp.blockDim = dim3(p->block);
+        kp.sharedMemBytes = p->flat_lds;
+        kp.kernelParams = params;
+        e = hipGraphExecKernelNodeSetParams(q.exec, q.main_node, &kp);
+        if (e == hipSuccess) q.main_grid = chunk_grid;
+    }
     if (e == hipSuccess && p->use_graph) {
         e = hipGraphLaunch(q.exec, stream);
     } else if (e == hipSuccess) {
@@ -472,8 +488,9 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
             e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(p->map_grid), dim3(256),
                                 params, 0, stream);
             if (e == hipSuccess && p->chunks)
-                e = hipLaunchKernel(batch_chunks_kernel(p->kind, p->nontemporal), dim3(p->grid),
-                                    dim3(kFlatBlock), params, 0, stream);
+                e = hipLaunchKernel(batch_chunks_kernel(p->kind, p->nontemporal),
+                                    dim3(chunk_grid), dim3(kFlatBlock), params, p->flat_lds,
+                                    stream);
             else if (e == hipSuccess)
                 e = hipLaunchKernel(batch_rows_kernel(p->kind, p->nontemporal), dim3(p->grid),
                                     dim3(p->block), params, 0, stream);

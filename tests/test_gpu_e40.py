@@ -49,9 +49,11 @@ def test_e40_bit_exact_shapes_and_tails():
     z0 = orc.e40_seed(orc.E40_INDEX_MIN + 12345)
     ref_u, _ = orc.e40_gen(z0, 300_000, "u64")
     ref_f, _ = orc.e40_gen(z0, 300_000, "f64")
-    shapes = [dict(), dict(block=64, grid=3, ilp=1, unroll=1), dict(block=1024, grid=7, ilp=4, unroll=4),
+    shapes = [dict(), dict(layout="rows"),
+              dict(block=64, grid=3, ilp=1, unroll=1), dict(block=1024, grid=7, ilp=4, unroll=4),
               dict(block=512, grid=129, ilp=2, unroll=2), dict(block=256, grid=1, ilp=4, unroll=1),
-              dict(mulmod="montgomery"), dict(mulmod="montgomery", block=64, grid=5, ilp=4, unroll=2),
+              dict(mulmod="montgomery"), dict(mulmod="montgomery", layout="rows"),
+              dict(mulmod="montgomery", block=64, grid=5, ilp=4, unroll=2),
               dict(mulmod="fp64", block=128, grid=33, ilp=1, unroll=4)]
     for kw in shapes:
         cfg = nn.make_cfg(**kw)
@@ -64,6 +66,53 @@ def test_e40_bit_exact_shapes_and_tails():
                     assert zn == orc.e40_skip(z0, count)
     got, _ = _gen_guarded(z0, 99_991, "f64", cfg=nn.make_cfg(temporal=True))
     assert np.array_equal(got, ref_f.view(np.uint64)[:99_991])
+
+
+@pytest.mark.parametrize("mulmod", ["fp64", "montgomery"])
+def test_e40_flat_layout_bit_exact(mulmod):
+    """The flat layout at modulus 3^40: 2 to 16 rows of 512 outputs per
+    chunk, one workgroup per chunk or a smaller grid whose workgroups step
+    from chunk to chunk (1, 3 and 7 workgroups), residency caps, both store
+    policies, ragged tails around the row and chunk sizes, both kinds."""
+    z0 = orc.e40_seed(orc.E40_INDEX_MIN + 777)
+    ref_u, _ = orc.e40_gen(z0, 300_000, "u64")
+    ref_f, _ = orc.e40_gen(z0, 300_000, "f64")
+    counts = (1, 2, 3, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 8191, 8193,
+              99_991, 300_000)
+    for rows, grid, occ, temporal in [(0, 0, 0, None), (2, 0, 3, None), (4, 1, 0, None),
+                                      (4, 3, 0, False), (8, 7, 5, True), (16, 0, 0, False),
+                                      (16, 2, 2, None)]:
+        cfg = nn.make_cfg(layout="flat", mulmod=mulmod, unroll=rows, grid=grid, occupancy=occ,
+                          temporal=temporal)
+        for count in counts:
+            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                _say("e40 flat", mulmod, rows, grid, occ, temporal, count, kind)
+                got, zn = _gen_guarded(z0, count, kind, cfg=cfg)
+                assert np.array_equal(got, ref.view(np.uint64)[:count]), \
+                    (rows, grid, occ, temporal, count, kind)
+                assert zn == orc.e40_skip(z0, count)
+    # an output that is only 8-byte aligned cannot take the flat layout
+    buf = torch.empty(4097, dtype=torch.float64, device="cuda")
+    with pytest.raises(nn.NNError):
+        nn.e40_generate_into(z0, buf[1:], cfg=nn.make_cfg(layout="flat"))
+
+
+def test_e40_flat_beyond_one_launch_sampled():
+    """More than 2^30 outputs (several flat launches): windows on both
+    sides of every launch boundary and at the tail."""
+    n = (1 << 30) + 4099
+    z0 = orc.e40_seed(orc.E40_INDEX_MIN + 31337)
+    out = torch.empty(n, dtype=torch.uint64, device="cuda")
+    zn = nn.e40_generate_into(z0, out, cfg=nn.make_cfg(layout="flat"))
+    torch.cuda.synchronize()
+    assert zn == orc.e40_skip(z0, n)
+    flat = out.view(torch.int64)
+    for st, k in ((0, 8192), ((1 << 30) - 8192, 8192 + 4099), (123_456_789, 4096)):
+        ref, _ = orc.e40_gen(orc.e40_skip(z0, st), k, "u64")
+        got = flat[st:st + k].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), st
+    del out, flat
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("mulmod", ["fp64", "montgomery"])
@@ -110,9 +159,12 @@ def test_e40_large_sampled(mulmod):
 def test_e40_config_validation():
     z0 = orc.e40_seed(orc.E40_INDEX_MIN)
     out = torch.empty(4096, dtype=torch.float64, device="cuda")
-    for cfg in [nn.make_cfg(layout="flat"), nn.make_cfg(width=1), nn.make_cfg(mulmod="barrett"),
-                nn.make_cfg(mulmod="shoup"),
-                nn.make_cfg(unroll=8), nn.make_cfg(ilp=3), nn.make_cfg(block=100),
-                nn.make_cfg(occupancy=3), nn.make_cfg(grid=1 << 20, block=1024)]:
+    for cfg in [nn.make_cfg(width=1), nn.make_cfg(mulmod="barrett"),
+                nn.make_cfg(mulmod="shoup"), nn.make_cfg(layout="flat", unroll=3),
+                nn.make_cfg(layout="flat", unroll=32), nn.make_cfg(layout="flat", block=128),
+                nn.make_cfg(layout="flat", occupancy=1), nn.make_cfg(layout="flat", ilp=2),
+                nn.make_cfg(layout="rows", unroll=8), nn.make_cfg(ilp=3), nn.make_cfg(block=100),
+                nn.make_cfg(layout="rows", occupancy=3), nn.make_cfg(grid=1 << 20, block=1024),
+                nn.make_cfg(layout="consecutive")]:
         with pytest.raises(nn.NNError):
             nn.e40_generate_into(z0, out, cfg=cfg)

@@ -168,7 +168,8 @@ def test_pick_plain_layout_returns_a_working_cfg():
     z0 = orc.seed(wl.INDEX_MIN + 777)
     n = 1 << 20
     out = torch.empty(n, dtype=torch.float64, device="cuda")
-    cfg, times = tune.pick_plain_layout(nn.default_cfg("f64", n), out, z0, rounds=1, reps=2)
+    rows = nn.make_cfg(layout="rows")
+    cfg, times = tune.pick_plain_layout(rows, out, z0, rounds=1, reps=2)
     assert set(times) == {"rows", "flat"} and all(t > 0 for t in times.values())
     zn = nn.generate_into(z0, out, cfg=cfg)
     torch.cuda.synchronize()
@@ -176,7 +177,7 @@ def test_pick_plain_layout_returns_a_working_cfg():
     ref, _ = orc.gen(z0, 8192, "f64", threads=0)
     assert np.array_equal(_bits(out)[:8192], ref.view(np.uint64))
     # an output that is only 8-byte aligned keeps the row layout
-    cfg2, times2 = tune.pick_plain_layout(nn.default_cfg("f64", n - 1), out[1:], z0)
+    cfg2, times2 = tune.pick_plain_layout(rows, out[1:], z0)
     assert times2 == {} and not (cfg2.flags & nn._native.NN_CFG_FLAT)
 
 
@@ -200,8 +201,11 @@ def test_config_validation():
         nn.fill(out, 0, cfg=nn.make_cfg(layout="flat", unroll=3))
     with pytest.raises(nn.NNError):
         nn.generate_into(z0, out[1:].view(torch.float64), cfg=nn.make_cfg(layout="flat"))
+    # the default for an aligned output is the flat layout; a row-only field
+    # (block, grid, ilp, width 1) selects the row layout
     d = nn.default_cfg("f64", 1 << 30)
-    assert d.flags & 2 and d.width == 2 and d.block == 256
+    assert d.flags & nn._native.NN_CFG_FLAT and d.width == 2 and d.block == 256
+    assert d.unroll == 4 and d.occupancy == 4 and d.flags & nn._native.NN_CFG_TEMPORAL_STORES
 
 
 def test_chained_calls_concatenate():
@@ -268,9 +272,11 @@ def test_fill_ceiling_kernel_pattern():
 
 
 def test_plain_bulk_full_size_bit_exact():
-    """The benchmark's workload at full size (2^30 f64 then 2^28 u64 from one
-    seed index) in the benchmark's launch configuration, compared in full
-    with the oracle chunk by chunk."""
+    """The plain bulk workload at full size (2^30 f64 then 2^28 u64 from one
+    seed index) through nn_generate with no configuration (the library's
+    default launch), compared in full with the oracle chunk by chunk.  The
+    benchmark's own launch configurations are compared in
+    test_gpu_fullsize.py."""
     case = wl.plain_bulk()
     z0 = nn.seed(case.index)
     chunk = 1 << 25
@@ -291,15 +297,17 @@ def test_plain_bulk_full_size_bit_exact():
         torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("kind,deltas", [("f64", (-16, 16)), ("u64", (-32, 32))])
-def test_plain_bulk_full_size_bench_grids_sampled(kind, deltas):
-    """The benchmark picks its grid on the device among the tuned one and
-    its neighbours; the neighbours at full size, sampled chunks (the start,
-    the ragged end, and random offsets) against the oracle."""
+@pytest.mark.parametrize("kind,deltas", [("f64", (0, -16, 16)), ("u64", (0, -32, 32))])
+def test_plain_bulk_full_size_row_grids_sampled(kind, deltas):
+    """The row layout at full size in its tuned shape and with the
+    neighbouring grids tune.pick_plain_grid chooses among: sampled chunks (the
+    start, the ragged end, and random offsets) against the oracle."""
+    from paper_1206_1187_amd import tune
     case = wl.plain_bulk()
     z0 = nn.seed(case.index)
     count = case.count_f64 if kind == "f64" else case.count_u64
-    base = nn.default_cfg(kind, count)
+    kw = tune.best_plain_cfg(kind, count)
+    base = nn.make_cfg(**dict(kw, layout="rows", grid=kw.get("grid") or 128))
     dt = torch.float64 if kind == "f64" else torch.uint64
     out = torch.empty(count, dtype=dt, device="cuda")
     rng = np.random.default_rng(5)
