@@ -323,6 +323,29 @@ int nn_batch_plan_cfg(const nn_batch_plan *plan, nn_batch_cfg *cfg_out);
 int nn_generate_batch(nn_batch_plan *plan, const nn_stream_desc *descs, uint32_t n,
                       void *out_dev, void *stream, uint64_t *final_states);
 
+/* nn_generate_batch_static -- nn_generate_batch for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): no plan, and no allocation of any kind.  The
+ * workspace (descriptors and chunk records) is a fixed static array of
+ * about 23 MB that every device loading the library holds until the
+ * process ends.  Every stream of `descs` (host array of n) is written to
+ * out_dev (device memory of the current device, 16-byte aligned) with the
+ * chunked batch kernel (NN_BATCH_CHUNKS, non-temporal stores); outputs are
+ * identical to nn_generate on each stream alone.  kind: nn_out_kind.
+ * final_states (host array of n, or NULL) receives each stream's state
+ * after its window.  Limits: at most 65 536 streams and 2^31 outputs per
+ * call, output indices below 2^51 (NN_ERANGE otherwise; nothing is
+ * enqueued).  Asynchronous on `stream`: descs is read by an asynchronous
+ * host-to-device copy on that stream, so keep it unchanged until the stream
+ * has passed this call's work.  All calls on one device share the one
+ * workspace, which keeps the last call's contents: calls that overlap on
+ * one device (different streams, or different host threads, without
+ * ordering between them) race and may write wrong outputs; calls ordered on
+ * one stream are safe.  Errors: NN_EINVAL (kind, states, pointers),
+ * NN_ERANGE, NN_EHIP. */
+int nn_generate_batch_static(const nn_stream_desc *descs, uint32_t n, void *out_dev, int kind,
+                             void *stream, uint64_t *final_states);
+
 /* ------------------------------------------------------------- server -- */
 
 /* The served form: continuous batching of variate requests.  Each client

@@ -244,6 +244,47 @@ def debug_mulmod(variant, a, b):
 _DESC_DTYPE = [("state", "<u8"), ("length", "<u8"), ("out_offset", "<u8")]
 
 
+def _batch_descs(states, lengths, out_offsets, out):
+    import numpy as np
+    n = len(states)
+    descs = np.empty(n, dtype=_DESC_DTYPE)
+    descs["state"] = np.asarray(states, dtype=np.uint64)
+    descs["length"] = np.asarray(lengths, dtype=np.uint64)
+    descs["out_offset"] = np.asarray(out_offsets, dtype=np.uint64)
+    ends = descs["out_offset"] + descs["length"]
+    if n and int(ends.max()) > out.numel():
+        raise NNError(_native.NN_ERANGE, "a window ends past the output tensor")
+    return descs
+
+
+def generate_batch_static(states, lengths, out_offsets, out, stream=None, final_states=False):
+    """nn_generate_batch_static: every stream's window written into the cuda
+    tensor ``out`` (uint64 or float64) with no plan and no allocation (the
+    library's static workspace).  Returns the final states as a numpy uint64
+    array when ``final_states`` is true.  The descriptor array is kept
+    alive until ``stream`` has passed the call (the copy is asynchronous)."""
+    import numpy as np
+    import torch
+    if not out.is_cuda or not out.is_contiguous():
+        raise NNError(_native.NN_EINVAL, "out must be a contiguous cuda tensor")
+    kind = _kind(out.dtype)
+    descs = _batch_descs(states, lengths, out_offsets, out)
+    n = len(descs)
+    fin = np.empty(n, dtype=np.uint64) if final_states else None
+    p64 = ctypes.POINTER(ctypes.c_uint64)
+    with torch.cuda.device(out.device):
+        handle = _stream_handle(stream)
+        rc = _native.lib().nn_generate_batch_static(
+            ctypes.c_void_p(descs.ctypes.data), n, ctypes.c_void_p(out.data_ptr()), kind,
+            handle, fin.ctypes.data_as(p64) if fin is not None else None)
+        _native.check(rc)
+        if n:
+            # the host array must outlive the asynchronous copy that reads it
+            s = torch.cuda.current_stream() if stream is None else stream
+            s.synchronize()
+    return fin
+
+
 class BatchPlan:
     """A batch plan (include/nn.h, nn_batch_plan): many streams generated by
     one persistent kernel replayed from a hipGraph.

@@ -171,6 +171,7 @@ SIGNATURES = {
     "nn_batch_plan_destroy": (_int, [_vp]),
     "nn_batch_plan_cfg": (_int, [_vp, ctypes.POINTER(BatchCfg)]),
     "nn_generate_batch": (_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _pu64]),
+    "nn_generate_batch_static": (_int, [_vp, ctypes.c_uint32, _vp, _int, _vp, _pu64]),
 }
 
 _SERVER_SIGNATURES = {

@@ -664,6 +664,64 @@ __global__ __launch_bounds__(256) void k_queue(QueueArgs a) {
     }
 }
 
+// Static batches (nn_generate_batch_static): the copied descriptors become
+// the chunked kernel's BatchDescs.  Thread t takes the contiguous
+// descriptors [t p, t p + p), p = ceil(n / 1024): it counts their chunk
+// records, the workgroup scans the 1024 counts, and each thread writes its
+// descriptors with their record offsets.
+__global__ __launch_bounds__(1024) void k_static_descs(char* scratch, uint32_t n, uint64_t* out) {
+    constexpr uint32_t T = 1024;
+    constexpr uint64_t C = kChunkOuts;
+    __shared__ uint64_t s_sum[T];
+    const uint64_t* raw = reinterpret_cast<const uint64_t*>(scratch + kStaticRawOff);
+    BatchDesc* dd = reinterpret_cast<BatchDesc*>(scratch + kStaticDescOff);
+    const uint32_t t = threadIdx.x;
+    const uint32_t p = (n + T - 1) / T;
+    const uint32_t d0 = t * p < n ? t * p : n;
+    const uint32_t d1 = d0 + p < n ? d0 + p : n;
+    auto records = [](uint64_t len, uint64_t off) -> uint64_t {
+        return len ? (len + (off & (C - 1)) + C - 1) / C : 0;
+    };
+    uint64_t mine = 0;
+    for (uint32_t d = d0; d < d1; ++d) mine += records(raw[3 * d + 1], raw[3 * d + 2]);
+    s_sum[t] = mine;
+    __syncthreads();
+    // inclusive scan of the counts (Hillis-Steele over the 1024 entries)
+    for (uint32_t k = 1; k < T; k <<= 1) {
+        const uint64_t add = t >= k ? s_sum[t - k] : 0;
+        __syncthreads();
+        s_sum[t] += add;
+        __syncthreads();
+    }
+    uint64_t r = s_sum[t] - mine;  // exclusive prefix
+    for (uint32_t d = d0; d < d1; ++d) {
+        const uint64_t len = raw[3 * d + 1];
+        BatchDesc D;
+        D.src = raw[3 * d];
+        D.pos = 0;
+        D.len = len;
+        D.out_off = len ? raw[3 * d + 2] : 0;  // an empty window gets no record
+        D.row_start = r;
+        dd[d] = D;
+        r += records(len, D.out_off);
+    }
+    if (t == T - 1) {
+        BatchHeader h;
+        h.out = out;
+        h.n_desc = n;
+        h.pad0 = 0;
+        h.n_rows = s_sum[T - 1];
+        h.states = nullptr;
+        for (int i = 0; i < 4; ++i) h.pad[i] = 0;
+        *reinterpret_cast<BatchHeader*>(scratch) = h;
+    }
+}
+
+hipError_t launch_static_descs(hipStream_t s, void* scratch, uint32_t n, uint64_t* out) {
+    k_static_descs<<<1, 1024, 0, s>>>(static_cast<char*>(scratch), n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_queue(int kind, uint32_t grid, uint32_t block, hipStream_t s,
                         const QueueArgs& a) {
     if (block != 256) return hipErrorInvalidValue;

@@ -171,6 +171,38 @@ hipError_t launch_batch_flat_inline(int kind, bool nontemporal, uint32_t grid, u
                                     hipStream_t stream, const Mult* tabs, const Mult& M1,
                                     const Mult& J, const BatchFlatInline& in);
 
+// ------------------------------------------- batches without allocation --
+// nn_generate_batch_static runs the chunked kernel with its workspace in one
+// static device array per device instead of a plan's allocations.  Layout
+// of that array (offsets in bytes):
+//   0                 BatchHeader, written by k_static_descs
+//   kStaticDescOff    BatchDesc[kStaticMaxStreams], prepared by k_static_descs
+//   kStaticRawOff     the caller's nn_stream_desc[n], copied in by the host
+//   kStaticRecOff     chunk records (RowRec), written by k_batch_rec
+// A window of length L at output offset o has ceil((L + o mod kChunkOuts) /
+// kChunkOuts) < L / kChunkOuts + 2 records, so kStaticMaxStreams windows of
+// kStaticMaxOutputs outputs in all never need more than kStaticMaxRecords
+// (the XCD-major record layout reaches kChunkRecWays - 1 entries past the
+// record count).
+constexpr uint32_t kStaticMaxStreams = 1u << 16;
+constexpr uint64_t kStaticMaxOutputs = 1ull << 31;
+constexpr uint64_t kStaticMaxRecords =
+    kStaticMaxOutputs / kChunkOuts + 2ull * kStaticMaxStreams + kChunkRecWays;
+constexpr uint64_t static_align(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+constexpr uint64_t kStaticDescOff = sizeof(BatchHeader);
+constexpr uint64_t kStaticRawOff =
+    static_align(kStaticDescOff + (uint64_t)kStaticMaxStreams * sizeof(BatchDesc));
+constexpr uint64_t kStaticRecOff =
+    static_align(kStaticRawOff + (uint64_t)kStaticMaxStreams * 3 * sizeof(uint64_t));
+constexpr uint64_t kStaticScratchBytes = kStaticRecOff + kStaticMaxRecords * sizeof(RowRec);
+
+// Prepares a static batch on the device (one workgroup of 1024 threads):
+// the n copied descriptors {state, length, out_offset} become BatchDescs
+// (src = state, pos = 0, row_start = the prefix sum of the windows' chunk
+// records), and the header gets out, n and the record count.  Windows of
+// length 0 get no record.
+hipError_t launch_static_descs(hipStream_t stream, void* scratch, uint32_t n, uint64_t* out);
+
 // --------------------------------------------------- device request queue --
 // The served form's low-latency path: a persistent kernel serves requests
 // that the host publishes in a ring in fine-grained (coherent) host memory,

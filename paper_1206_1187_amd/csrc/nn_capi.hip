@@ -8,6 +8,7 @@
 // table upload.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include <mutex>
 
@@ -531,6 +532,82 @@ int nn_generate_batch(nn_batch_plan* plan, const nn_stream_desc* descs, uint32_t
     }
     st = plan_launch_staged(plan, nd, out_dev, (hipStream_t)stream);
     if (st) return st;
+    if (final_states)
+        for (uint32_t i = 0; i < n; ++i) final_states[i] = h_skip(descs[i].state, descs[i].length);
+    return ok();
+}
+
+int nn_generate_batch_static(const nn_stream_desc* descs, uint32_t n, void* out_dev, int kind,
+                             void* stream, uint64_t* final_states) {
+    if (kind != NN_OUT_U64 && kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %d unknown", kind);
+    if (n && !descs) return fail(NN_EINVAL, "descs is NULL");
+    if (n > kStaticMaxStreams)
+        return fail(NN_ERANGE, "batch of %u streams, the static workspace holds %u", n,
+                    kStaticMaxStreams);
+    uint64_t total = 0, records = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const nn_stream_desc& q = descs[i];
+        if (!valid_state(q.state))
+            return fail(NN_EINVAL, "stream %u: state %llu is not a unit modulo 3^33", i,
+                        (unsigned long long)q.state);
+        if (q.length > kStaticMaxOutputs)
+            return fail(NN_ERANGE, "stream %u: %llu outputs, the static workspace holds %llu", i,
+                        (unsigned long long)q.length, (unsigned long long)kStaticMaxOutputs);
+        if (q.length && q.out_offset > (1ull << 51) - q.length)
+            return fail(NN_ERANGE, "stream %u: output indices reach 2^51", i);
+        total += q.length;
+        if (total > kStaticMaxOutputs)
+            return fail(NN_ERANGE, "batch of more than %llu outputs",
+                        (unsigned long long)kStaticMaxOutputs);
+        if (q.length)
+            records += (q.length + (q.out_offset & (kChunkOuts - 1)) + kChunkOuts - 1) / kChunkOuts;
+    }
+    if (total) {
+        if (!out_dev) return fail(NN_EINVAL, "output pointer is NULL");
+        if ((uintptr_t)out_dev % 16)
+            return fail(NN_EINVAL, "batch output %p must be 16-byte aligned", out_dev);
+    }
+    DeviceTables* d = nullptr;
+    int st = current_device(&d);
+    if (st) return st;
+    if (total == 0) {
+        if (final_states)
+            for (uint32_t i = 0; i < n; ++i) final_states[i] = descs[i].state;
+        return ok();
+    }
+    if (records + kChunkRecWays > kStaticMaxRecords)  // cannot happen within the limits above
+        return fail(NN_ERANGE, "batch of %llu chunk records", (unsigned long long)records);
+    const hipStream_t s = (hipStream_t)stream;
+    char* ws = static_cast<char*>(d->scratch);
+    // the caller's descriptors, then the descriptors and header the kernels read
+    hipError_t e = hipMemcpyAsync(ws + kStaticRawOff, descs, (size_t)n * sizeof(nn_stream_desc),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_static_descs(s, ws, n, static_cast<uint64_t*>(out_dev));
+    // the chunked plan's arguments (nn_runtime.hip, slot_create) over the static workspace
+    BatchArgs a;
+    memset(&a, 0, sizeof a);
+    a.ws = reinterpret_cast<const BatchHeader*>(ws);
+    a.JB = make_mult(MultPowers::get().pow(kFlatPerBlock));
+    a.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
+    a.t_lo = d->t_lo;
+    a.t_hi = d->t_hi;
+    a.t_sk = d->t_sk;
+    a.rec = reinterpret_cast<RowRec*>(ws + kStaticRecOff);
+    a.row_outs = kChunkOuts;
+    a.grid = kChunkRecWays;
+    a.cluster = kChunkRecWays;
+    a.block = kFlatBlock;
+    a.JR = make_mult(MultPowers::get().pow((uint64_t)kChunkOuts * 256));
+    uint32_t lds = (d->lds_per_cu / (kFlatDefaultOccupancy + 1) / 512 + 1) * 512;
+    if (lds > d->lds_per_block) lds = 0;
+    void* params[] = {&a};
+    if (e == hipSuccess)
+        e = hipLaunchKernel(batch_rec_kernel(false), dim3(d->cus > 0 ? d->cus * 4 : 64), dim3(256),
+                            params, 0, s);
+    if (e == hipSuccess)
+        e = hipLaunchKernel(batch_chunks_kernel(kind, true), dim3((uint32_t)records),
+                            dim3(kFlatBlock), params, lds, s);
+    if (e != hipSuccess) return fail(NN_EHIP, "static batch launch: %s", hipGetErrorString(e));
     if (final_states)
         for (uint32_t i = 0; i < n; ++i) final_states[i] = h_skip(descs[i].state, descs[i].length);
     return ok();

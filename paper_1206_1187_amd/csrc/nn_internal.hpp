@@ -25,6 +25,7 @@ struct DeviceTables {
     double* t8 = nullptr;       // kSkip8Levels * kSkip8Size * 3 doubles
     Mult* t_flo = nullptr;      // kFlatLoSize entries (flat layout)
     Mult* t_fhi = nullptr;      // kFlatHiSize entries (flat layout)
+    void* scratch = nullptr;    // this device's copy of the static batch workspace
     int cus = 0;
     uint32_t lds_per_cu = 0;
     uint32_t lds_per_block = 0;

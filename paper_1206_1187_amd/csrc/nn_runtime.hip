@@ -53,6 +53,13 @@ const KindDefaults& kind_defaults(int kind) {
 
 namespace {
 
+// The workspace of nn_generate_batch_static (layout in nn_batch.hpp): every
+// device that loads the library holds its own copy until the process ends.
+// Host code never names it after set-up: hipGetSymbolAddress gives each
+// device's address once (DeviceTables::scratch), and that pointer is what
+// kernels, copies and fills receive.
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 constexpr int kMaxDevices = 64;
 std::mutex g_dev_mutex;
 DeviceTables g_dev[kMaxDevices];
@@ -165,6 +172,13 @@ int ensure_device_current(int dev, DeviceTables** out) {
         static_assert(kFlatLoOffset == (uint64_t)kLoSize + kHiSize + kSkipLevels * kSkipSize,
                       "the flat tables follow the skip tables");
         d.t8 = (double*)((char*)mem + mult_bytes + blk_bytes);
+        void* ws = nullptr;
+        e = hipGetSymbolAddress(&ws, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipFree(mem);
+            return fail(NN_EHIP, "static batch workspace address: %s", hipGetErrorString(e));
+        }
+        d.scratch = ws;
         d.cus = prop.multiProcessorCount;
         d.lds_per_cu = (uint32_t)prop.maxSharedMemoryPerMultiProcessor;
         d.lds_per_block = (uint32_t)prop.sharedMemPerBlock;
