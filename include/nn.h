@@ -374,7 +374,7 @@ typedef struct nn_server_cfg {
     double fake_bytes_per_s;     /* fake device: write rate (0 = instant) */
     /* NN_SERVER_DEVICE_QUEUE only: */
     uint64_t queue_max_outputs;  /* requests of at most this many outputs go to
-                                    the device queue; 0 = 2^16 */
+                                    the device queue; 0 = 2^18 */
     uint32_t queue_workgroups;   /* workgroups of the queue kernel; 0 = 16 */
     uint32_t queue_capacity;     /* ring entries, a power of two; 0 = 1024 */
     double queue_idle_s;         /* the queue kernel leaves after this long
@@ -448,6 +448,12 @@ int nn_server_inject_failures(nn_server *srv, uint32_t n);
 typedef struct nn_replay_stats {
     double wall_s;
     uint64_t requests, variates, failed;
+    /* Each request's latency in three stages (seconds, p50 and p99 over the
+     * requests): `seen`, from its arrival to the moment the loop submitted
+     * it; `launch`, from there until its work was enqueued on the GPU (the
+     * server's admission and batching included); `done`, from the enqueue
+     * until its completion was observed. */
+    double seen_p50, seen_p99, launch_p50, launch_p99, done_p50, done_p99;
 } nn_replay_stats;
 
 /* The trace through `srv` (nn_server_submit / _poll / _release). */

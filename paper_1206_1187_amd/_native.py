@@ -194,7 +194,10 @@ _SERVER_SIGNATURES = {
 
 class ReplayStats(ctypes.Structure):
     _fields_ = [("wall_s", ctypes.c_double), ("requests", ctypes.c_uint64),
-                ("variates", ctypes.c_uint64), ("failed", ctypes.c_uint64)]
+                ("variates", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("seen_p50", ctypes.c_double), ("seen_p99", ctypes.c_double),
+                ("launch_p50", ctypes.c_double), ("launch_p99", ctypes.c_double),
+                ("done_p50", ctypes.c_double), ("done_p99", ctypes.c_double)]
 
 
 _pd = ctypes.POINTER(ctypes.c_double)

@@ -561,15 +561,15 @@ hipError_t launch_batch_flat_inline(int kind, bool nt, uint32_t grid, uint32_t l
 // the entry to LDS, and claims rows with a compare-and-swap that also checks
 // the slot's round, so a workgroup arriving after the entry is complete (its
 // slot already reset for the next round) claims nothing.  Each claimed row
-// is generated as in the batch kernel.  The workgroup whose finished rows
-// complete the entry resets the slot for the next round, then publishes
+// is a row of the plain flat layout (kFlatPerBlock outputs, 16-byte stores)
+// started from the entry's host-computed state.  The workgroup whose finished
+// rows complete the entry resets the slot for the next round, then publishes
 // seq + 1 to the host with a system-scope release.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_queue(QueueArgs a) {
+__global__ __launch_bounds__(kFlatBlock) void k_queue(QueueArgs a) {
     __shared__ QueueEntry s_e;
     __shared__ uint32_t s_go;
     __shared__ uint64_t s_claim;
-    const uint32_t B = blockDim.x;
     const uint32_t l = threadIdx.x;
     const uint64_t t0 = (uint64_t)wall_clock64();
     uint64_t last = t0;
@@ -597,12 +597,18 @@ __global__ __launch_bounds__(256) void k_queue(QueueArgs a) {
         __syncthreads();
         if (!s_go) return;
         const QueueEntry E = s_e;
-        const uint64_t rows = (E.count + 2ull * B - 1) / (2ull * B);
+        const uint64_t rows = (E.count + kFlatPerBlock - 1) / kFlatPerBlock;
         const uint64_t round = (seq >> a.cap_log2) & 0xffffffffull;
-        const uint64_t src = a.states[E.src_row];
         const global_ptr<uint64_t> out = as_global(reinterpret_cast<uint64_t*>(E.out));
+        // Rows are claimed ceil(rows / workgroups) at a time (at least
+        // kQueueRowsPerClaim, at most kQueueMaxRowsPerClaim), so a small entry
+        // costs each workgroup one claim; a claim that takes the last rows
+        // also tells its workgroup that nothing is left.
+        uint64_t per_claim = (rows + gridDim.x - 1) / gridDim.x;
+        per_claim = per_claim < kQueueRowsPerClaim ? kQueueRowsPerClaim
+                  : per_claim > kQueueMaxRowsPerClaim ? kQueueMaxRowsPerClaim : per_claim;
         uint64_t mine = 0;
-        for (;;) {
+        for (bool more = true; more;) {
             __syncthreads();  // s_claim and s_e are rewritten below
             if (l == 0) {
                 uint64_t first = ~0ull;
@@ -610,7 +616,7 @@ __global__ __launch_bounds__(256) void k_queue(QueueArgs a) {
                     __hip_atomic_load(&a.claim[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 while ((old >> 32) == round && (old & 0xffffffffull) < rows) {
                     if (__hip_atomic_compare_exchange_strong(
-                            &a.claim[slot], &old, old + kQueueRowsPerClaim, __ATOMIC_RELAXED,
+                            &a.claim[slot], &old, old + per_claim, __ATOMIC_RELAXED,
                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                         first = old & 0xffffffffull;
                         break;
@@ -621,12 +627,20 @@ __global__ __launch_bounds__(256) void k_queue(QueueArgs a) {
             __syncthreads();
             const uint64_t c0 = s_claim;
             if (c0 == ~0ull) break;
-            const uint64_t c1 = c0 + kQueueRowsPerClaim < rows ? c0 + kQueueRowsPerClaim : rows;
-            // Row j covers outputs [2 j B, 2 (j + 1) B); lane l owns x_b - 1 and
-            // x_b = 2 (j B + l) + 1, the state src * (2^53)^(pos + x_b + 1).
-            uint64_t xb = 2ull * (c0 * B + l) + 1;
-            VarFP64::S zb = skip_any<VarFP64>(src, E.pos + xb + 1, a.t_sk);
-            VarFP64::S za = VarFP64::mul(zb, a.Minv);
+            const uint64_t c1 = c0 + per_claim < rows ? c0 + per_claim : rows;
+            more = c1 < rows;
+            // Row j covers outputs [kFlatPerBlock j, kFlatPerBlock (j + 1)); lane l
+            // owns x_b - 1 and x_b = kFlatPerBlock j + 2 l + 1, the states
+            // base * (2^53)^(x_b) and base * (2^53)^(x_b + 1): the row's start
+            // from the flat layout's two row tables, the lane's offset from t_lo
+            // (all three loads independent), then one step per row.
+            uint64_t xb = kFlatPerBlock * c0 + 2u * l + 1;
+            const Mult hi = a.tabs[kFlatHiOffset + c0 / kFlatLoSize];
+            const Mult lo = a.tabs[kFlatLoOffset + c0 % kFlatLoSize];
+            const Mult ma = a.tabs[2u * l + 1], mb = a.tabs[2u * l + 2];
+            const VarFP64::S S = VarFP64::mul(VarFP64::mul(VarFP64::load(E.base), hi), lo);
+            VarFP64::S za = VarFP64::mul(S, ma);
+            VarFP64::S zb = VarFP64::mul(S, mb);
             for (uint64_t j = c0; j < c1; ++j) {
                 const global_ptr<uint64_t> p = out + (xb - 1);
                 if (xb < E.count) {
@@ -639,22 +653,27 @@ __global__ __launch_bounds__(256) void k_queue(QueueArgs a) {
                 }
                 za = VarFP64::mul(za, a.JB);
                 zb = VarFP64::mul(zb, a.JB);
-                xb += 2ull * B;
+                xb += kFlatPerBlock;
             }
             mine += c1 - c0;
         }
         if (mine) {
-            __threadfence();  // this wave's outputs are visible device-wide
+            // Each wave waits for its own stores to reach L2; then one
+            // system-scope release by thread 0 writes this workgroup's outputs
+            // back from the L2 before its rows are counted.  The workgroup whose
+            // count completes the entry (acquiring the others' releases through
+            // the counter) resets the slot and publishes seq + 1 to the host.
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (l == 0) {
-                const uint64_t before = __hip_atomic_fetch_add(&a.fin[slot], mine, __ATOMIC_ACQ_REL,
+                __threadfence_system();  // the release that the count carries
+                const uint64_t before = __hip_atomic_fetch_add(&a.fin[slot], mine, __ATOMIC_ACQUIRE,
                                                                __HIP_MEMORY_SCOPE_AGENT);
                 if (before + mine == rows) {
                     __hip_atomic_store(&a.fin[slot], 0ull, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(&a.claim[slot], (round + 1) << 32, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                    __threadfence_system();
                     __hip_atomic_store(&a.done[slot], seq + 1, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_SYSTEM);
                 }
@@ -724,7 +743,7 @@ hipError_t launch_static_descs(hipStream_t s, void* scratch, uint32_t n, uint64_
 
 hipError_t launch_queue(int kind, uint32_t grid, uint32_t block, hipStream_t s,
                         const QueueArgs& a) {
-    if (block != 256) return hipErrorInvalidValue;
+    if (block != kFlatBlock) return hipErrorInvalidValue;
     if (kind == 0)
         k_queue<0><<<grid, block, 0, s>>>(a);
     else

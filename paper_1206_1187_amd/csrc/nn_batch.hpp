@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "nn_arith.hpp"
+#include "nn_kernels.hpp"
 
 namespace nn {
 
@@ -213,11 +214,14 @@ hipError_t launch_static_descs(hipStream_t stream, void* scratch, uint32_t n, ui
 // sets `stop`, after `idle_ticks` without a new entry, or after `max_ticks`
 // of life; an entry is then either complete or untouched, and the host
 // relaunches from the first incomplete one.
+// The host computes each entry's start state (it holds every stream's
+// state), so a claim starts from three independent table loads and no
+// skip-ahead on the device.
 struct QueueEntry {
-    uint64_t src_row;  // row of the device stream-state table
-    uint64_t pos;      // window position (reduced modulo the period)
-    uint64_t count;    // outputs, > 0
-    uint64_t out;      // device address of output 0, 16-byte aligned
+    uint64_t base;   // state of the window's element -1: output x is base * (2^53)^(x + 1)
+    uint64_t count;  // outputs, in (0, kQueueMaxCount]
+    uint64_t out;    // device address of output 0, 16-byte aligned
+    uint64_t pad;
 };
 
 struct QueueShared {  // host memory, fine-grained
@@ -227,6 +231,10 @@ struct QueueShared {  // host memory, fine-grained
 };
 
 constexpr uint32_t kQueueRowsPerClaim = 4;
+constexpr uint32_t kQueueMaxRowsPerClaim = 64;
+// Rows are the flat layout's rows (kFlatPerBlock outputs, 256 threads), so
+// a row's start is base * t_fhi[u >> 10] * t_flo[u & 1023] for row u < 2^21.
+constexpr uint64_t kQueueMaxCount = kFlatMaxCount;
 
 struct QueueArgs {
     QueueShared* sh;
@@ -237,10 +245,8 @@ struct QueueArgs {
     uint32_t cap;               // ring capacity, a power of two
     uint32_t cap_log2;
     uint64_t start;             // first entry of this launch
-    const uint64_t* states;     // device stream-state table
-    const Mult* t_sk;
-    Mult JB;                    // (2^53)^(2*block): a lane's next row
-    Mult Minv;                  // (2^53)^-1
+    const Mult* tabs;           // the device table allocation (t_lo, t_flo, t_fhi)
+    Mult JB;                    // (2^53)^kFlatPerBlock: a lane's next row
     uint64_t idle_ticks;        // wall-clock ticks
     uint64_t max_ticks;
 };

@@ -114,13 +114,13 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
 // Device request queue (host side in nn_queue.hip, kernel in nn_batch.hip).
 struct DeviceQueue;
 int queue_create(int kind, uint32_t workgroups, uint32_t capacity, double idle_s,
-                 const uint64_t* dev_states, DeviceQueue** out);
+                 DeviceQueue** out);
 // Waits for published entries to finish, stops the kernel, frees.
 void queue_destroy(DeviceQueue* q);
-// Publishes a request (count > 0, 16-byte aligned output); NN_ERANGE when the
-// ring is full.  Launches the kernel if it is not running.
-int queue_submit(DeviceQueue* q, uint64_t src_row, uint64_t pos, uint64_t count, void* out,
-                 uint64_t* seq_out);
+// Publishes a request: `count` outputs (0 < count <= kQueueMaxCount) to a
+// 16-byte aligned `out`, output x being base * (2^53)^(x + 1); NN_ERANGE when
+// the ring is full.  Launches the kernel if it is not running.
+int queue_submit(DeviceQueue* q, uint64_t base, uint64_t count, void* out, uint64_t* seq_out);
 bool queue_done(DeviceQueue* q, uint64_t seq);
 // Relaunches the kernel if it has left while published entries are incomplete.
 int queue_keep_running(DeviceQueue* q);

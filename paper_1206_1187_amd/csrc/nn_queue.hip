@@ -59,7 +59,7 @@ bool kernel_running(DeviceQueue* q) {
 }  // namespace
 
 int queue_create(int kind, uint32_t workgroups, uint32_t capacity, double idle_s,
-                 const uint64_t* dev_states, DeviceQueue** out) {
+                 DeviceQueue** out) {
     if (capacity == 0 || (capacity & (capacity - 1)) || capacity > (1u << 20))
         return fail(NN_EINVAL, "queue capacity %u: a power of two up to 2^20", capacity);
     if (workgroups == 0 || workgroups > 1024)
@@ -101,10 +101,8 @@ int queue_create(int kind, uint32_t workgroups, uint32_t capacity, double idle_s
     a.cap = capacity;
     a.cap_log2 = (uint32_t)__builtin_ctz(capacity);
     a.start = 0;
-    a.states = dev_states;
-    a.t_sk = d->t_sk;
-    a.JB = make_mult(MultPowers::get().pow(2ull * 256));
-    a.Minv = make_mult(MultPowers::get().pow(kPeriod - 1));
+    a.tabs = d->t_lo;  // the table allocation: t_lo at 0, t_flo and t_fhi at their offsets
+    a.JB = make_mult(MultPowers::get().pow(kFlatPerBlock));
     const double ticks_per_s = rate_khz * 1e3;
     a.idle_ticks = (uint64_t)(idle_s * ticks_per_s);
     a.max_ticks = (uint64_t)(60.0 * ticks_per_s);  // a launch lives at most a minute
@@ -123,19 +121,18 @@ void queue_destroy(DeviceQueue* q) {
     delete q;
 }
 
-int queue_submit(DeviceQueue* q, uint64_t src_row, uint64_t pos, uint64_t count, void* out,
-                 uint64_t* seq_out) {
-    if (count == 0 || ((uintptr_t)out % 16))
-        return fail(NN_EINVAL, "queue entry: count > 0 and a 16-byte aligned output");
+int queue_submit(DeviceQueue* q, uint64_t base, uint64_t count, void* out, uint64_t* seq_out) {
+    if (count == 0 || count > kQueueMaxCount || ((uintptr_t)out % 16))
+        return fail(NN_EINVAL, "queue entry: 0 < count <= 2^30 and a 16-byte aligned output");
     const uint64_t seq = q->next_seq;
     const uint32_t slot = (uint32_t)(seq & (q->cap - 1));
     if (seq >= q->cap && q->done[slot] != seq - q->cap + 1)
         return fail(NN_ERANGE, "device queue full");  // the slot's previous entry is running
     QueueEntry& e = q->entries[slot];
-    e.src_row = src_row;
-    e.pos = pos;
+    e.base = base;
     e.count = count;
     e.out = (uint64_t)(uintptr_t)out;
+    e.pad = 0;
     __atomic_store_n(&q->sh->head, seq + 1, __ATOMIC_RELEASE);
     q->next_seq = seq + 1;
     *seq_out = seq;

@@ -18,6 +18,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <deque>
 #include <map>
@@ -276,7 +277,9 @@ bool admit(nn_server* s) {
         if (small) {
             // Straight to the device queue, no batch launch.
             uint64_t seq = 0;
-            const int st = queue_submit(s->dq, r.stream, r.pos, r.count, s->pool + r.pool_off, &seq);
+            // output x of the window is state(0) * (2^53)^(pos + x + 1)
+            const uint64_t base = h_skip(s->host_states[r.stream], r.pos);
+            const int st = queue_submit(s->dq, base, r.count, s->pool + r.pool_off, &seq);
             if (st == NN_OK) {
                 r.state = kInFlight;
                 r.t_launch = t;
@@ -396,7 +399,10 @@ int nn_server_create(const nn_server_cfg* cfg, const uint64_t* stream_states, ui
         return fail(NN_EINVAL, "unknown server flags 0x%x", c.flags);
     if ((c.flags & NN_SERVER_DEVICE_QUEUE) && (c.flags & NN_SERVER_FAKE_DEVICE))
         return fail(NN_EINVAL, "the device queue needs a GPU");
-    if (!c.queue_max_outputs) c.queue_max_outputs = 1ull << 16;
+    if (!c.queue_max_outputs) c.queue_max_outputs = 1ull << 18;
+    if (c.queue_max_outputs > kQueueMaxCount)
+        return fail(NN_EINVAL, "queue_max_outputs %llu: at most 2^30",
+                    (unsigned long long)c.queue_max_outputs);
     if (!c.queue_workgroups) c.queue_workgroups = 16;
     if (!c.queue_capacity) c.queue_capacity = 1024;
     if (!(c.queue_idle_s > 0.0)) c.queue_idle_s = 0.05;
@@ -477,7 +483,7 @@ int nn_server_create(const nn_server_cfg* cfg, const uint64_t* stream_states, ui
     }
     if (c.flags & NN_SERVER_DEVICE_QUEUE) {
         int st = queue_create((int)c.kind, c.queue_workgroups, c.queue_capacity, c.queue_idle_s,
-                              s->dev_states, &s->dq);
+                              &s->dq);
         if (st) {
             server_free(s);
             return st;
@@ -612,6 +618,24 @@ int nn_server_inject_failures(nn_server* s, uint32_t n) {
 
 // --------------------------------------------------------------- replay --
 
+// p50 and p99 of v (reordered in place); zero for an empty v.
+static void percentiles(std::vector<double>& v, double* p50, double* p99) {
+    *p50 = *p99 = 0.0;
+    if (v.empty()) return;
+    const size_t i50 = (v.size() - 1) / 2, i99 = (size_t)((v.size() - 1) * 0.99);
+    std::nth_element(v.begin(), v.begin() + i50, v.end());
+    *p50 = v[i50];
+    std::nth_element(v.begin(), v.begin() + i99, v.end());
+    *p99 = v[i99];
+}
+
+static void stage_stats(std::vector<double>& seen, std::vector<double>& launch,
+                        std::vector<double>& done, nn_replay_stats* st) {
+    percentiles(seen, &st->seen_p50, &st->seen_p99);
+    percentiles(launch, &st->launch_p50, &st->launch_p99);
+    percentiles(done, &st->done_p50, &st->done_p99);
+}
+
 static int replay_check(const double* t_arrive, const uint32_t* stream_id, const uint64_t* count,
                         uint64_t n, double time_scale, double* latency_out) {
     if (n && (!t_arrive || !stream_id || !count || !latency_out))
@@ -630,6 +654,7 @@ int nn_server_replay(nn_server* s, const double* t_arrive, const uint32_t* strea
     if (st) return st;
     if (s->fake) return fail(NN_EINVAL, "replay runs in real time: not on the fake device");
     std::vector<nn_completion> buf(1024);
+    std::vector<double> st_seen(n), st_launch(n), st_done(n);
     uint64_t first_ticket = 0, i = 0, done = 0, failed = 0, variates = 0;
     const double t0 = s->now();
     while (done < n) {
@@ -648,6 +673,9 @@ int nn_server_replay(nn_server* s, const double* t_arrive, const uint32_t* strea
             const nn_completion& c = buf[k];
             const uint64_t idx = c.ticket - first_ticket;
             latency_out[idx] = c.t_done - t0 - t_arrive[idx] / time_scale;
+            st_seen[idx] = c.t_submit - t0 - t_arrive[idx] / time_scale;
+            st_launch[idx] = c.t_launch - c.t_submit;
+            st_done[idx] = c.t_done - c.t_launch;
             if (c.status != NN_OK) ++failed;
             variates += c.count;
             st = nn_server_release(s, c.ticket);
@@ -663,6 +691,7 @@ int nn_server_replay(nn_server* s, const double* t_arrive, const uint32_t* strea
         stats_out->requests = n;
         stats_out->variates = variates;
         stats_out->failed = failed;
+        stage_stats(st_seen, st_launch, st_done, stats_out);
     }
     return ok();
 }
@@ -686,7 +715,9 @@ int nn_replay_per_request(const uint64_t* stream_states, uint32_t n_streams,
     struct Flight {
         hipEvent_t ev;
         uint64_t idx, used;
+        double t_enq;  // the launch and its event are enqueued
     };
+    std::vector<double> st_seen(n), st_launch(n), st_done(n);
     std::deque<Flight> flights;
     std::vector<hipEvent_t> free_events;
     uint64_t head = 0, used = 0, i = 0, done = 0, variates = 0;
@@ -726,7 +757,10 @@ int nn_replay_per_request(const uint64_t* stream_states, uint32_t n_streams,
                 st = fail(NN_EHIP, "event record");
                 break;
             }
-            flights.push_back({ev, i, waste + c});
+            const double t_enq = now();
+            st_seen[i] = t - t_arrive[i] / time_scale;
+            st_launch[i] = t_enq - t;
+            flights.push_back({ev, i, waste + c, t_enq});
             used += waste + c;
             head = start + c;
             ++i;
@@ -734,7 +768,9 @@ int nn_replay_per_request(const uint64_t* stream_states, uint32_t n_streams,
         while (!flights.empty() && hipEventQuery(flights.front().ev) == hipSuccess) {
             const Flight f = flights.front();
             flights.pop_front();
-            latency_out[f.idx] = now() - t_arrive[f.idx] / time_scale;
+            const double t_done = now();
+            latency_out[f.idx] = t_done - t_arrive[f.idx] / time_scale;
+            st_done[f.idx] = t_done - f.t_enq;
             variates += count[f.idx];
             used -= f.used;
             free_events.push_back(f.ev);
@@ -754,6 +790,7 @@ int nn_replay_per_request(const uint64_t* stream_states, uint32_t n_streams,
         stats_out->requests = n;
         stats_out->variates = variates;
         stats_out->failed = 0;
+        stage_stats(st_seen, st_launch, st_done, stats_out);
     }
     return ok();
 }

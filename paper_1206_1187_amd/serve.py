@@ -240,11 +240,25 @@ def _trace_arrays(trace, n=None):
     return t, s, c
 
 
-def _result(lat, st):
+#: Results split latency at requests of this many outputs (the median
+#: request size of the served workload is about 2^16).
+SMALL_REQUEST = 1 << 16
+
+
+def _result(lat, st, count=None):
     res = {"requests": int(st.requests), "variates": int(st.variates), "wall_s": st.wall_s,
            "variates_per_s": st.variates / st.wall_s if st.wall_s > 0 else 0.0,
            "failed": int(st.failed)}
     res.update(_percentiles(lat))
+    if count is not None:
+        small = np.asarray(count) <= SMALL_REQUEST
+        for name, sel in (("small", small), ("large", ~small)):
+            pc = _percentiles(np.asarray(lat)[sel])
+            res["%s_p50_ms" % name] = pc.get("p50_ms", 0.0)
+            res["%s_p99_ms" % name] = pc.get("p99_ms", 0.0)
+    res["stages_ms"] = {k: getattr(st, k) * 1e3 for k in
+                        ("seen_p50", "seen_p99", "launch_p50", "launch_p99", "done_p50",
+                         "done_p99")}
     return res
 
 
@@ -259,7 +273,7 @@ def replay_served_native(server, trace, time_scale=1.0, timeout_s=0.0, n=None):
         server._h, t.ctypes.data_as(pd), s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
         c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), t.size, float(time_scale),
         float(timeout_s), lat.ctypes.data_as(pd), ctypes.byref(st)))
-    return _result(lat, st)
+    return _result(lat, st, c)
 
 
 def replay_per_request_native(trace, stream_states, pool_elems, kind="f64", time_scale=1.0,
@@ -283,4 +297,4 @@ def replay_per_request_native(trace, stream_states, pool_elems, kind="f64", time
         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), lat.ctypes.data_as(pd),
         ctypes.byref(st)))
     del pool
-    return _result(lat, st)
+    return _result(lat, st, c)

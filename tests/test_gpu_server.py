@@ -71,25 +71,30 @@ def test_served_requests_equal_oracle_and_plain_alone(kind, interleaved):
         assert st["pool_used"] == 0 and st["released"] == len(reqs) and st["batches"] >= 10
 
 
+def _full_check(states, bad):
+    """A replay consumer comparing all of a completed f64 request's outputs
+    with the oracle on its window (its stream's state skipped to the
+    window's position); failing tickets go to `bad`."""
+    buf = np.empty(1 << 24, dtype=np.float64)
+
+    def consumer(server, c):
+        ref = buf[:c.count]
+        orc.gen_into(orc.skip(int(states[c.stream_id]), c.position), ref, threads=0)
+        if not np.array_equal(_bits(server.data(c)), ref.view(np.uint64)):
+            bad.append(c.ticket)
+    return consumer
+
+
 def test_served_trace_slice_checked_per_request():
     """A slice of the served workload (Poisson arrivals, sizes log-uniform in
-    [256, 2^24]) replayed in real time; each request's first and last 32
-    outputs are checked against the oracle before release."""
+    [256, 2^24]) replayed in real time; every output of every request is
+    checked against the oracle before release."""
     tr = wl.served()
     n = 600
     sl = wl.ServedTrace(tr.stream_indices, tr.t_arrive[:n], tr.stream_id[:n], tr.count[:n])
     states = np.array([orc.seed(int(a)) for a in tr.stream_indices], dtype=np.uint64)
     bad = []
-
-    def consumer(server, c):
-        d = server.data(c)
-        k = min(32, c.count)
-        s0 = int(states[c.stream_id])
-        head, _ = orc.gen(orc.skip(s0, c.position), k, "f64")
-        tail, _ = orc.gen(orc.skip(s0, c.position + c.count - k), k, "f64")
-        if not (np.array_equal(_bits(d[:k]), head.view(np.uint64)) and
-                np.array_equal(_bits(d[c.count - k:]), tail.view(np.uint64))):
-            bad.append(c.ticket)
+    consumer = _full_check(states, bad)
 
     with serve.Server(states, 16 << 30, lanes=2) as srv:
         res = serve.replay_served(srv, sl, consumer=consumer, timeout_s=60)
@@ -101,7 +106,7 @@ def test_pool_pressure_admission_and_cancel_on_device():
     """A pool far smaller than the demand: requests wait at the head of the
     queue until releases free memory, a queued request cancelled meanwhile
     completes with NN_ECANCELED and keeps its window, and every served
-    request equals the oracle on its window."""
+    request equals the oracle on its whole window."""
     states = _states(4, 31)
     pool_bytes = 8 << 20  # 1 Mi f64
     rng = np.random.default_rng(32)
@@ -119,13 +124,8 @@ def test_pool_pressure_admission_and_cancel_on_device():
                     assert c.status == serve.NN_ECANCELED
                     continue
                 assert c.status == 0
-                st = int(states[c.stream_id])
-                k = min(64, c.count)
-                d = srv.data(c)
-                head, _ = orc.gen(orc.skip(st, c.position), k, "f64")
-                tail, _ = orc.gen(orc.skip(st, c.position + c.count - k), k, "f64")
-                assert np.array_equal(_bits(d[:k]), head.view(np.uint64))
-                assert np.array_equal(_bits(d[c.count - k:]), tail.view(np.uint64))
+                ref, _ = orc.gen(orc.skip(int(states[c.stream_id]), c.position), c.count, "f64")
+                assert np.array_equal(_bits(srv.data(c)), ref.view(np.uint64))
                 srv.release(c.ticket)
             guard += 1
             assert guard < 10_000_000
@@ -219,23 +219,14 @@ def test_device_queue_idle_exit_and_relaunch():
 
 
 def test_device_queue_trace_slice():
-    """A slice of the served workload with the device queue: first and last
-    outputs of every request against the oracle."""
+    """A slice of the served workload with the device queue: every output of
+    every request against the oracle."""
     tr = wl.served()
     n = 600
     sl = wl.ServedTrace(tr.stream_indices, tr.t_arrive[:n], tr.stream_id[:n], tr.count[:n])
     states = np.array([orc.seed(int(a)) for a in tr.stream_indices], dtype=np.uint64)
     bad = []
-
-    def consumer(server, c):
-        d = server.data(c)
-        k = min(32, c.count)
-        s0 = int(states[c.stream_id])
-        head, _ = orc.gen(orc.skip(s0, c.position), k, "f64")
-        tail, _ = orc.gen(orc.skip(s0, c.position + c.count - k), k, "f64")
-        if not (np.array_equal(_bits(d[:k]), head.view(np.uint64)) and
-                np.array_equal(_bits(d[c.count - k:]), tail.view(np.uint64))):
-            bad.append(c.ticket)
+    consumer = _full_check(states, bad)
 
     with serve.Server(states, 16 << 30, lanes=2, device_queue=True) as srv:
         res = serve.replay_served(srv, sl, consumer=consumer, timeout_s=60)
