@@ -230,6 +230,13 @@ int nn_dev_skip_table(const nn_dev_mult **table_out);
  * rules and errors as nn_generate. */
 int nn_fill(uint64_t count, void *out_dev, uint64_t value, void *stream,
             const nn_launch_cfg *cfg);
+/* nn_fill only, flat layout: also make the generator's start in each
+ * workgroup -- its table loads, with a comparison in place of its
+ * multiplications -- before the stores, so the fill is the generator minus
+ * its arithmetic (Table 2 removes the memory-access time from the
+ * generation time; on MI355X a fill of bare back-to-back stores in the
+ * generator's pattern writes slower than the generator itself). */
+#define NN_FILL_WITH_START 64u
 
 /* -------------------------------------------------------------- batch -- */
 
@@ -510,7 +517,11 @@ int nn_e40_skip(uint64_t state, uint64_t k, uint64_t *state_out);
  * three exact FP64 products modulo 3^20; defaults 256 threads, one
  * workgroup per CU, ilp 2, unroll 1) or NN_MULMOD_MONTGOMERY (64-bit
  * states, R = 2^64; defaults 256 threads, three workgroups per CU, ilp 4,
- * unroll 2).  The layout is the row layout with 16-byte stores.  Both
+ * unroll 2).  Layouts: the row layout, or (NN_CFG_FLAT, and the default for
+ * a 16-byte aligned binary64 output with the FP64 step) the flat layout:
+ * one 256-thread workgroup per chunk of `unroll` rows of 512 outputs
+ * (2, 4, 8, 16; default 8), residency capped by `occupancy` (default 4);
+ * NN_CFG_ROWS forces the row layout.  16-byte stores in both.  Both
  * reductions give the same bits.  Errors as nn_generate_ex. */
 int nn_e40_generate_ex(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream,
                        const nn_launch_cfg *cfg);

@@ -129,12 +129,19 @@ def generate(state, count, dtype="f64", device="cuda", stream=None, cfg=None):
     return out, generate_into(state, out, stream=stream, cfg=cfg)
 
 
-def fill(out, value, stream=None, cfg=None):
+def fill(out, value, stream=None, cfg=None, with_start=False):
     """The paper's "Constant" kernel: write ``value`` (a 64-bit pattern) with
-    the generator's store pattern."""
+    the generator's store pattern; ``with_start`` (flat layout) also makes
+    the generator's start-up table loads (NN_FILL_WITH_START)."""
     import torch
     if not out.is_cuda or not out.is_contiguous() or out.element_size() != 8:
         raise NNError(_native.NN_EINVAL, "out must be a contiguous 8-byte cuda tensor")
+    if with_start:
+        c = _native.LaunchCfg()
+        if cfg is not None:
+            ctypes.pointer(c)[0] = cfg
+        c.flags |= _native.NN_FILL_WITH_START
+        cfg = c
     with torch.cuda.device(out.device):
         rc = _native.lib().nn_fill(out.numel(), ctypes.c_void_p(out.data_ptr()),
                                    int(value) % 2 ** 64, _stream_handle(stream),

@@ -207,11 +207,20 @@ __global__ __launch_bounds__(1024) void k_batch_inline(BatchArgs a, BatchInline 
 // leave partial lines in two L2s.)  Workgroups take windows d = blockIdx.x,
 // + gridDim.x, ...; thread t of 256 takes the window's rows t, t + 256, ...:
 // one skip-ahead to its first row, then a step of (2^53)^(W*256) per row.
+//
+// The chunked kernel's owned mode (kChunkOwned) numbers records by chunk:
+// record k of the window's chunk j is k + j, k from the descriptor, and a
+// record goes to the chunk array only if its chunk is the window's own
+// first (its first chunk does not hold an earlier window's end), or a later
+// chunk of the window; every window's first-chunk record also goes to ext,
+// where the workgroup of a chunk that windows share finds them.  An empty
+// window gets an empty ext record.
 template <bool INDEXED>
 __global__ __launch_bounds__(256) void k_batch_rec(BatchArgs a) {
     const const_ptr<BatchHeader> hdr = as_const(a.ws);
     const uint32_t n_desc = hdr->n_desc;
     const uint64_t n_rows = hdr->n_rows;
+    const bool owned = hdr->mode == kChunkOwned;
     const const_ptr<BatchDesc> desc = reinterpret_cast<const_ptr<BatchDesc>>(hdr + 1);
     // row r -> cluster c = r / Rc, member (r - c Rc) mod K, its row (r - c Rc) / K
     const uint64_t K = a.cluster, C = a.grid / a.cluster;
@@ -219,12 +228,25 @@ __global__ __launch_bounds__(256) void k_batch_rec(BatchArgs a) {
     const uint64_t per = (Rc + K - 1) / K;
     const uint64_t W = a.row_outs;  // outputs per row, a power of two
     const global_ptr<u64x2> rec = reinterpret_cast<global_ptr<u64x2>>(as_global(a.rec));
+    const global_ptr<u64x2> ext = reinterpret_cast<global_ptr<u64x2>>(as_global(a.ext));
     for (uint32_t d = blockIdx.x; d < n_desc; d += gridDim.x) {
         const BatchDesc D = load_desc(desc + d);
+        if (owned && D.len == 0) {
+            if (threadIdx.x == 0) {
+                u64x2 E;
+                E.x = 0;
+                E.y = kRecEmpty;
+                ext[d] = E;
+            }
+            continue;
+        }
         const uint64_t s = D.out_off & (W - 1);
         const uint64_t nr = (D.len + s + W - 1) / W;
         uint64_t j = threadIdx.x;
         if (j >= nr) continue;
+        const uint64_t r0 = owned ? D.row_start & ~(kDescFirstShared | kDescLastShared) : D.row_start;
+        const bool first_shared = owned && (D.row_start & kDescFirstShared);
+        const bool last_shared = owned && (D.row_start & kDescLastShared);
         uint64_t src;
         if constexpr (INDEXED)
             src = as_const(hdr->states)[D.src];
@@ -236,14 +258,20 @@ __global__ __launch_bounds__(256) void k_batch_rec(BatchArgs a) {
         e = e >= s ? e - s : e + kPeriod - s;
         double z = skip_any<VarFP64>(src, e, a.t_sk);
         for (; j < nr; j += 256) {
-            const uint64_t r = D.row_start + j;
+            const uint64_t r = r0 + j;
             const uint64_t first = W * j;  // s + (window index of element 0)
             const uint64_t hi = D.len + s - first < W ? D.len + s - first : W;
+            const uint64_t lo = j == 0 ? s : 0;
             u64x2 R;  // a RowRec
             R.x = __builtin_bit_cast(uint64_t, z);
-            R.y = (D.out_off - s + first) | (j == 0 ? s : 0) | (hi << kRecHiShift);
-            const uint64_t c = r / Rc, o = r - c * Rc;
-            rec[(c * K + o % K) * per + o / K] = R;
+            R.y = (D.out_off - s + first) | lo | (hi << kRecHiShift);
+            if (owned && j == 0) ext[d] = R;
+            if (!(owned && j == 0 && first_shared)) {
+                if (owned && j + 1 == nr && last_shared)  // later windows share this chunk
+                    R.y = ((uint64_t)(d + 1) << 11) | lo | (1ull << kRecMulti) | (hi << kRecHiShift);
+                const uint64_t c = r / Rc, o = r - c * Rc;
+                rec[(c * K + o % K) * per + o / K] = R;
+            }
             z = VarFP64::mul(z, a.JR);
         }
     }
@@ -441,6 +469,11 @@ __global__ __launch_bounds__(256) void k_batch_rows(BatchArgs a) {
 // multiplication each by the lane's fixed multipliers, then one step of
 // (2^53)^512 per row.  A chunk that one window covers is stored without a
 // test; one that a window starts or ends in stores the window's outputs only.
+// In the owned mode (sorted, disjoint windows) there is one record per chunk
+// instead, so no two workgroups write into one chunk: a chunk that several
+// windows share is written whole by its workgroup, window by window.  (With
+// write-back stores, chunks written in parts by workgroups on different
+// XCDs cost the 10,000-window batch 12 % of its rate.)
 template <int KIND, bool NT>
 __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     constexpr uint32_t C = kChunkOuts;
@@ -448,24 +481,39 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     const uint64_t n = hdr->n_rows;  // records
     const global_ptr<uint64_t> out = as_global(hdr->out);
     const const_ptr<u64x2> rec = reinterpret_cast<const_ptr<u64x2>>(as_const(a.rec));
+    const const_ptr<u64x2> ext = reinterpret_cast<const_ptr<u64x2>>(as_const(a.ext));
     const uint64_t per = (n + kChunkRecWays - 1) / kChunkRecWays;
     const uint32_t l = threadIdx.x;
     uint64_t j = blockIdx.x;
     if (j >= n) return;
     const Mult ma = a.t_lo[2u * l], mb = a.t_lo[2u * l + 1];
     u64x2 cur = rec[(j % kChunkRecWays) * per + j / kChunkRecWays];
+    // one window's part [lo, hi) of the chunk at output g, from the state z0
+    // of the chunk's element 0 as if the window covered it
+    auto part = [&](uint64_t g, double z0, uint32_t lo, uint32_t hi) {
+        const global_ptr<uint64_t> p = out + (g + 2u * l);
+        double za = VarFP64::mul(z0, ma);
+        double zb = VarFP64::mul(z0, mb);
+#pragma unroll
+        for (int r = 0; r < (int)kChunkRows; ++r) {
+            put_pair_in<KIND, NT>(p + r * kFlatPerBlock, za, zb, r * kFlatPerBlock + 2u * l, lo,
+                                  hi);
+            za = VarFP64::mul(za, a.JB);
+            zb = VarFP64::mul(zb, a.JB);
+        }
+    };
     for (;;) {
         const uint64_t jn = j + gridDim.x < n ? j + gridDim.x : j;
         // the next record, in flight meanwhile
         const u64x2 nxt = rec[(jn % kChunkRecWays) * per + jn / kChunkRecWays];
         const double z0 = __builtin_bit_cast(double, cur.x);
         const uint64_t info = cur.y;
-        double za = VarFP64::mul(z0, ma);
-        double zb = VarFP64::mul(z0, mb);
-        const global_ptr<uint64_t> p = out + ((info & kRecIndexMask & ~(uint64_t)(C - 1)) + 2u * l);
         const uint32_t hi = (uint32_t)(info >> kRecHiShift);
         const uint32_t lo = (uint32_t)info & (C - 1);
         if (hi == C && lo == 0) {
+            double za = VarFP64::mul(z0, ma);
+            double zb = VarFP64::mul(z0, mb);
+            const global_ptr<uint64_t> p = out + ((info & kRecIndexMask) + 2u * l);
 #pragma unroll
             for (int r = 0; r < (int)kChunkRows; ++r) {
                 put<NT>(reinterpret_cast<global_ptr<u64x2>>(p + r * kFlatPerBlock),
@@ -474,13 +522,31 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
                 zb = VarFP64::mul(zb, a.JB);
                 __builtin_amdgcn_sched_barrier(0);
             }
+        } else if (!((info >> kRecMulti) & 1)) {
+            part(info & kRecIndexMask & ~(uint64_t)(C - 1), z0, lo, hi);
         } else {
-#pragma unroll
-            for (int r = 0; r < (int)kChunkRows; ++r) {
-                put_pair_in<KIND, NT>(p + r * kFlatPerBlock, za, zb, r * kFlatPerBlock + 2u * l,
-                                      lo, hi);
-                za = VarFP64::mul(za, a.JB);
-                zb = VarFP64::mul(zb, a.JB);
+            // Owned mode, a chunk that windows d, d + 1, ... share: the later
+            // windows' records are their ext records (empty windows skipped);
+            // the first of them also gives the chunk's output index.
+            const uint32_t n_desc = hdr->n_desc;
+            uint64_t w = (info & kRecIndexMask) >> 11;  // d + 1
+            u64x2 R;
+            R.y = kRecEmpty;
+            for (; w < n_desc; ++w) {
+                R = ext[w];
+                if (R.y != kRecEmpty) break;
+            }
+            const uint64_t g = R.y & kRecIndexMask & ~(uint64_t)(C - 1);
+            part(g, z0, lo, hi);
+            while (R.y != kRecEmpty && (R.y & kRecIndexMask & ~(uint64_t)(C - 1)) == g) {
+                const uint32_t h = (uint32_t)(R.y >> kRecHiShift);
+                part(g, __builtin_bit_cast(double, R.x), (uint32_t)R.y & (C - 1), h);
+                if (h == C) break;  // that window reaches the chunk's end
+                R.y = kRecEmpty;
+                for (++w; w < n_desc; ++w) {
+                    R = ext[w];
+                    if (R.y != kRecEmpty) break;
+                }
             }
         }
         j += gridDim.x;
@@ -728,7 +794,7 @@ __global__ __launch_bounds__(1024) void k_static_descs(char* scratch, uint32_t n
         BatchHeader h;
         h.out = out;
         h.n_desc = n;
-        h.pad0 = 0;
+        h.mode = kChunkPerRecord;
         h.n_rows = s_sum[T - 1];
         h.states = nullptr;
         for (int i = 0; i < 4; ++i) h.pad[i] = 0;

@@ -36,7 +36,7 @@ constexpr uint64_t kBatchMaxLen = 1ull << 24;
 struct BatchHeader {
     uint64_t* out;
     uint32_t n_desc;
-    uint32_t pad0;
+    uint32_t mode;  // chunked kernel: kChunkPerRecord or kChunkOwned
     uint64_t n_rows;
     const uint64_t* states;  // indexed batches: the stream-state table
     uint64_t pad[4];
@@ -69,11 +69,19 @@ constexpr uint32_t kIlRows = 4;
 // a multiple of W), so lo < W fits below g.
 struct RowRec {
     double z;       // state of the row's element 0
-    uint64_t info;  // g | lo | hi << 52
+    uint64_t info;  // g | lo | hi << 52 (see kRecMulti for the chunked kernel's other form)
 };
 static_assert(sizeof(RowRec) == 16, "one 16-byte record per row");
-constexpr uint64_t kRecIndexMask = (1ull << 52) - 1;  // g | lo
+constexpr uint64_t kRecIndexMask = (1ull << 51) - 1;  // g | lo (output indices < 2^51)
 constexpr uint32_t kRecHiShift = 52;
+// Chunked kernel, one workgroup per chunk: a chunk that more windows share
+// has its first window's record with bit kRecMulti set and, in place of g,
+// (d + 1) << 11 | lo, d that window's index: the chunk's other windows are
+// the next windows, d + 1, d + 2, ..., whose records for it are the ext
+// records (the record of each window's first chunk).
+constexpr uint32_t kRecMulti = 51;
+// An ext record of an empty window.
+constexpr uint64_t kRecEmpty = ~0ull;
 // Records are stored workgroup-major: each workgroup of the row kernel reads
 // the records of its rows as one contiguous run (per = ceil(ceil(n_rows / C)
 // / K) of them, C = grid / K clusters of K workgroups), kRecChunk at a time
@@ -90,8 +98,9 @@ struct BatchArgs {
     const Mult* t_lo;
     const Mult* t_hi;
     const Mult* t_sk;       // kSkipLevels * kSkipSize entries
-    // Interleaved kernel only:
+    // Interleaved and chunked kernels only:
     RowRec* rec;            // row records (device workspace)
+    RowRec* ext;            // chunked, owned mode: each window's first-chunk record
     Mult JR;                // (2^53)^(row_outs*256): a pre-pass thread's next row
     uint32_t grid;          // workgroups of the row kernel
     uint32_t block;         // threads per workgroup of the row kernel
@@ -121,6 +130,22 @@ constexpr uint32_t kChunkOuts = kChunkRows * 512;
 // miss per eight chunks).  The pre-pass writes this layout as one cluster of
 // kChunkRecWays workgroups.
 constexpr uint32_t kChunkRecWays = 8;
+// Record modes of the chunked kernel (BatchHeader::mode):
+//  * per record: a record per chunk and window that meet, one workgroup each
+//    (windows in any order; a chunk that windows share is written by
+//    several workgroups);
+//  * owned: windows sorted by output offset and disjoint (the host checks),
+//    a record per chunk, so every chunk is written by one workgroup, which
+//    also writes the chunk's other windows from their ext records.  The
+//    descriptors' row_start then holds k | first_shared << 62 |
+//    last_shared << 63: k the chunk number of the window's first chunk
+//    (chunks that windows meet, numbered in output order), first_shared
+//    whether that chunk holds the end of an earlier window, last_shared
+//    whether the window's last chunk holds the start of a later one.
+constexpr uint32_t kChunkPerRecord = 0;
+constexpr uint32_t kChunkOwned = 1;
+constexpr uint64_t kDescFirstShared = 1ull << 62;
+constexpr uint64_t kDescLastShared = 1ull << 63;
 const void* batch_chunks_kernel(int kind, bool nontemporal);
 
 // The kernel entry for (mulmod, kind, nontemporal, indexed); its single

@@ -428,16 +428,22 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     DeviceTables* d = nullptr;
     st = current_device(&d);
     if (st) return st;
+    nn_launch_cfg c;
+    memset(&c, 0, sizeof c);
+    if (cfg) c = *cfg;
+    const bool with_start = (c.flags & NN_FILL_WITH_START) != 0;
+    c.flags &= ~NN_FILL_WITH_START;
     Resolved r;
-    st = resolve_cfg(cfg, NN_OUT_F64, count, *d, out_dev, &r);
+    st = resolve_cfg(&c, NN_OUT_F64, count, *d, out_dev, &r);
     if (st) return st;
     if (r.consec || r.strided) return fail(NN_EINVAL, "nn_fill has no consecutive layout");
+    if (with_start && !r.flat) return fail(NN_EINVAL, "NN_FILL_WITH_START needs the flat layout");
     if (r.flat) {
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
             hipError_t e = launch_fill_flat(r.nontemporal, (int)r.unroll, r.lds,
-                                            (hipStream_t)stream, (uint64_t*)out_dev + off, n,
-                                            value);
+                                            (hipStream_t)stream, with_start ? d->t_lo : nullptr,
+                                            (uint64_t*)out_dev + off, n, value);
             if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
         }
         return ok();

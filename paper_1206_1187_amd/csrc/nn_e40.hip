@@ -85,6 +85,10 @@ constexpr uint32_t kFHi = 2048;
 constexpr uint64_t kFLoOff = (uint64_t)kLo + kHi;
 constexpr uint64_t kFHiOff = kFLoOff + kFLo;
 constexpr uint64_t kFlatMaxRows = (uint64_t)kFLo * kFHi;  // rows of 512 per launch (2^21)
+// The tables' entries as Mult40, then the same entries as base-B limbs
+// (Mult40L, the same size), so the FP64 step starts without Montgomery.
+constexpr uint64_t kTabEntries = kFHiOff + kFHi;
+static_assert(sizeof(Mult40L) == sizeof(Mult40), "limb entries follow at the same stride");
 constexpr uint64_t kMaxThreads = (uint64_t)kLo * kHi / 2;
 constexpr int kMaxDev = 64;
 
@@ -102,7 +106,7 @@ int device_tables(const Mult40** out) {
     std::lock_guard<std::mutex> lock(g_mu);
     if (!g_tab[dev]) {
         static std::vector<Mult40> host = [] {
-            std::vector<Mult40> t(kFHiOff + kFHi);
+            std::vector<Mult40> t(2 * kTabEntries);
             uint64_t r = 1;
             for (uint32_t l = 0; l < kLo; ++l, r = h_mul(r, kMult)) t[l] = make_mult40(r);
             const uint64_t step = Powers::get().pow(kLo);
@@ -114,6 +118,8 @@ int device_tables(const Mult40** out) {
             const uint64_t big = r;  // (2^53)^(512 kFLo)
             r = 1;
             for (uint32_t i = 0; i < kFHi; ++i, r = h_mul(r, big)) t[kFHiOff + i] = make_mult40(r);
+            Mult40L* limbs = reinterpret_cast<Mult40L*>(t.data() + kTabEntries);
+            for (uint64_t i = 0; i < kTabEntries; ++i) limbs[i] = make_mult40l(t[i].v);
             return t;
         }();
         void* mem = nullptr;
@@ -265,7 +271,8 @@ struct E40FlatArgs {
     uint64_t base;       // state of out[0]
     Mult40 M1, J, JN;
     Mult40L M1L, JL, JNL;
-    const Mult40* tabs;  // t_lo, t_hi, t_flo, t_fhi
+    const Mult40* tabs;  // t_lo, t_hi, t_flo, t_fhi, then the same as limbs
+    double base_lo, base_hi;  // base as base-B limbs
 };
 
 template <int KIND, int MM, int R, bool NT>
@@ -278,11 +285,23 @@ __global__ __launch_bounds__(256) void k_e40_flat(E40FlatArgs a) {
     if (c >= a.n_chunks) return;
     const uint32_t l = threadIdx.x;
     const uint64_t u = c * R;
-    const uint64_t z0 = mm40(mm40(mm40(a.base, a.tabs[kFHiOff + u / kFLo].mont),
-                                  a.tabs[kFLoOff + u % kFLo].mont),
-                             a.tabs[2u * l].mont);
-    S za = St::from(z0);
-    S zb = St::from(mm40(z0, a.M1.mont));
+    S za, zb;
+    if constexpr (MM == 1) {
+        // in limbs throughout: the chunk's two row multipliers, then the
+        // lane's two offsets (all four loads independent), no Montgomery
+        const Mult40L* lt = reinterpret_cast<const Mult40L*>(a.tabs + kTabEntries);
+        const Mult40L hi = lt[kFHiOff + u / kFLo], lo = lt[kFLoOff + u % kFLo];
+        const Mult40L la = lt[2u * l], lb = lt[2u * l + 1];
+        const L2 S0 = mul40l(mul40l(L2{a.base_lo, a.base_hi}, hi), lo);
+        za = mul40l(S0, la);
+        zb = mul40l(S0, lb);
+    } else {
+        const uint64_t z0 = mm40(mm40(mm40(a.base, a.tabs[kFHiOff + u / kFLo].mont),
+                                      a.tabs[kFLoOff + u % kFLo].mont),
+                                 a.tabs[2u * l].mont);
+        za = St::from(z0);
+        zb = St::from(mm40(z0, a.M1.mont));
+    }
     const global_ptr<uint64_t> out = as_global(a.out);
     for (;;) {
         const global_ptr<u64x2> p =
@@ -417,15 +436,17 @@ hipError_t launch(int kind, int mm, int ilp, int unroll, bool nt, uint32_t grid,
 
 }  // namespace
 
-// Whether the library's default layout at modulus 3^40 is the flat one (for
-// 16-byte aligned outputs).  Not by measurement: 2^30 f64 outputs wrote
-// 5.86 TB/s in the row layout against 5.73 in the best flat shape (8 rows
-// per chunk) on one MI355X; the persistent flat grids wrote 4.1-5.4.
-constexpr bool kDefaultFlat = false;
+// The library's default layout at modulus 3^40 for a 16-byte aligned f64
+// output with the FP64 step: the flat one, 8 rows of 512 per chunk, since
+// its start moved into the limb domain (2^30 f64 outputs, one MI355X:
+// 5.84-5.87 TB/s against 5.49-5.59 for the row layout; 4 rows 5.73; caps 3
+// to 5 within 1 %).  Raw u64 states keep the row layout (6.19 against 6.08).
+constexpr bool kDefaultFlatF64 = true;
+constexpr uint32_t kE40FlatDefaultRows = 8;
 
 // nn_e40_generate_ex's flat layout (arguments already validated: a valid
 // state, count > 0, an in-range pointer).  cfg: unroll = rows of 512
-// outputs per chunk (2, 4, 8, 16; default 4), grid = workgroups per launch
+// outputs per chunk (2, 4, 8, 16; default 8), grid = workgroups per launch
 // (0: one per chunk), occupancy = residency cap (0: 4), store policy
 // (default temporal).
 int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void* stream,
@@ -434,7 +455,7 @@ int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void
         return fail(NN_EINVAL, "the flat layout needs a 16-byte aligned output (got %p)", out_dev);
     if ((c.block && c.block != 256) || c.ilp > 1)
         return fail(NN_EINVAL, "the flat layout has 256 threads per workgroup and no ilp");
-    const uint32_t rows = c.unroll ? c.unroll : kFlatDefaultRows;
+    const uint32_t rows = c.unroll ? c.unroll : kE40FlatDefaultRows;
     if (rows != 2 && rows != 4 && rows != 8 && rows != 16)
         return fail(NN_EINVAL, "unroll %u: the flat layout writes 2, 4, 8 or 16 rows per chunk",
                     rows);
@@ -463,6 +484,8 @@ int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void
         const uint64_t n = count - off < max_launch ? count - off : max_launch;
         a.out = (uint64_t*)out_dev + off;
         a.base = h_mul(s, Powers::get().pow(off + 1));  // the state of this slice's first output
+        a.base_lo = (double)(a.base % kLimb);
+        a.base_hi = (double)(a.base / kLimb);
         a.n_chunks = n / per;
         uint32_t grid = 1;
         if (a.n_chunks) {
@@ -533,11 +556,11 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
         return fail(NN_EINVAL, "NN_CFG_TEMPORAL_STORES and NN_CFG_NONTEMPORAL_STORES are exclusive");
     const int mm = c.mulmod == NN_MULMOD_MONTGOMERY ? 0 : 1;
     const bool aligned16 = ((uintptr_t)out_dev % 16) == 0;
-    // No layout flag: the flat layout for a 16-byte aligned output unless the
-    // cfg sets a row-layout field (block, ilp).
+    // No layout flag: the flat layout for a 16-byte aligned f64 output with
+    // the FP64 step unless the cfg sets a row-layout field (block, ilp).
     const bool flat = (c.flags & NN_CFG_FLAT) ||
-                      (!(c.flags & NN_CFG_ROWS) && aligned16 && e40::kDefaultFlat && !c.block &&
-                       !c.ilp);
+                      (!(c.flags & NN_CFG_ROWS) && aligned16 && kind == NN_OUT_F64 && mm == 1 &&
+                       e40::kDefaultFlatF64 && !c.block && !c.ilp);
     if (flat) return e40::generate_flat(state, count, out_dev, kind, stream, c, mm);
     if (c.occupancy) return fail(NN_EINVAL, "occupancy applies to the flat layout only");
     const uint32_t block = c.block ? c.block : 256u;

@@ -53,12 +53,15 @@ struct nn_batch_slot {
     void* ws_dev = nullptr;
     void* ws_host = nullptr;      // pinned staging, same layout as ws_dev
     nn::RowRec* rec = nullptr;    // device, cap_rows + 2 grid records (interleaved, chunked)
+    nn::RowRec* ext = nullptr;    // device, cap_desc first-chunk records (chunked)
     hipEvent_t done = nullptr;
     bool pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t main_node = nullptr;  // the batch kernel's node
     uint32_t main_grid = 0;              // its grid as last set (chunked kernel, set per batch)
+    hipGraphNode_t rec_node = nullptr;   // the record pre-pass's node (interleaved, chunked)
+    uint32_t rec_grid = 0;               // its grid as last set (one workgroup per window)
     nn::BatchArgs args;
 };
 

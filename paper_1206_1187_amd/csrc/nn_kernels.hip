@@ -325,14 +325,28 @@ __global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(const Mult* _
 // R rows of kFlatPerBlock outputs, no count test, each row's store followed
 // by the same scheduling barrier, and a ragged last chunk in a separate
 // one-workgroup kernel (k_fill_flat_tail).
-template <bool NT, int R>
-__global__ __launch_bounds__(kFlatBlock) void k_fill_flat(uint64_t* __restrict__ out,
+//
+// START: also the generator's start -- its three table loads (the chunk's
+// two row multipliers and the lane's offset) -- with only a comparison in
+// place of its multiplications, so the stores wait for the same loads:
+// the generator minus its arithmetic.  (The entries are positive, so the
+// comparison always keeps `value`.)
+template <bool NT, int R, bool START>
+__global__ __launch_bounds__(kFlatBlock) void k_fill_flat(const Mult* __restrict__ tabs,
+                                                          uint64_t* __restrict__ out,
                                                           uint64_t value) {
     extern __shared__ char occupancy_cap[];
     (void)occupancy_cap;
     u64x2 v;
     v.x = value;
-    v.y = value;
+    if constexpr (START) {
+        const uint64_t u = (uint64_t)blockIdx.x * R;
+        const double hi = tabs[kFlatHiOffset + u / kFlatLoSize].v;
+        const double lo = tabs[kFlatLoOffset + u % kFlatLoSize].v;
+        const double lane = tabs[2u * threadIdx.x].v;
+        v.x = hi + lo + lane > 0.0 ? value : 0;
+    }
+    v.y = v.x;
     u64x2* p = reinterpret_cast<u64x2*>(out + (uint64_t)kFlatPerBlock * R * blockIdx.x +
                                         2u * threadIdx.x);
 #pragma unroll
@@ -410,14 +424,18 @@ hipError_t launch_generate_flat(int mulmod, int kind, bool nt, int rows, uint32_
 }
 
 template <bool NT, int R>
-static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, uint64_t* out, uint64_t count,
-                                uint64_t value) {
+static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, const Mult* tabs, uint64_t* out,
+                                uint64_t count, uint64_t value) {
     const uint64_t per = (uint64_t)kFlatPerBlock * R;
     const uint64_t full = count / per;
     const uint64_t tail = count - full * per;
     if (full) {
-        hipLaunchKernelGGL((k_fill_flat<NT, R>), dim3((uint32_t)full), dim3(kFlatBlock), lds, s,
-                           out, value);
+        if (tabs)
+            hipLaunchKernelGGL((k_fill_flat<NT, R, true>), dim3((uint32_t)full), dim3(kFlatBlock),
+                               lds, s, tabs, out, value);
+        else
+            hipLaunchKernelGGL((k_fill_flat<NT, R, false>), dim3((uint32_t)full),
+                               dim3(kFlatBlock), lds, s, tabs, out, value);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -430,22 +448,22 @@ static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, uint64_t* out, uint
 }
 
 template <bool NT>
-static hipError_t fill_flat_r(int rows, uint32_t lds, hipStream_t s, uint64_t* out,
-                              uint64_t count, uint64_t value) {
+static hipError_t fill_flat_r(int rows, uint32_t lds, hipStream_t s, const Mult* tabs,
+                              uint64_t* out, uint64_t count, uint64_t value) {
     switch (rows) {
-        case 1: return fill_flat_one<NT, 1>(lds, s, out, count, value);
-        case 2: return fill_flat_one<NT, 2>(lds, s, out, count, value);
-        case 4: return fill_flat_one<NT, 4>(lds, s, out, count, value);
-        case 8: return fill_flat_one<NT, 8>(lds, s, out, count, value);
-        case 16: return fill_flat_one<NT, 16>(lds, s, out, count, value);
+        case 1: return fill_flat_one<NT, 1>(lds, s, tabs, out, count, value);
+        case 2: return fill_flat_one<NT, 2>(lds, s, tabs, out, count, value);
+        case 4: return fill_flat_one<NT, 4>(lds, s, tabs, out, count, value);
+        case 8: return fill_flat_one<NT, 8>(lds, s, tabs, out, count, value);
+        case 16: return fill_flat_one<NT, 16>(lds, s, tabs, out, count, value);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_fill_flat(bool nt, int rows, uint32_t lds, hipStream_t s, uint64_t* out,
-                            uint64_t count, uint64_t value) {
-    return nt ? fill_flat_r<true>(rows, lds, s, out, count, value)
-              : fill_flat_r<false>(rows, lds, s, out, count, value);
+hipError_t launch_fill_flat(bool nt, int rows, uint32_t lds, hipStream_t s, const Mult* tabs,
+                            uint64_t* out, uint64_t count, uint64_t value) {
+    return nt ? fill_flat_r<true>(rows, lds, s, tabs, out, count, value)
+              : fill_flat_r<false>(rows, lds, s, tabs, out, count, value);
 }
 
 // Kernel selector: W = 1, W = 2, or W = 2 with IL = 2 or 4 rows in flight.

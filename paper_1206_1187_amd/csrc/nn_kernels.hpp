@@ -92,8 +92,10 @@ struct FlatArgs {
 // resident workgroups per compute unit.
 hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, int rows,
                                 uint32_t lds_bytes, hipStream_t stream, const FlatArgs& a);
+// tabs: NULL for the plain fill; the device table allocation for the fill
+// that keeps the generator's start (NN_FILL_WITH_START).
 hipError_t launch_fill_flat(bool nontemporal, int rows, uint32_t lds_bytes, hipStream_t stream,
-                            uint64_t* out, uint64_t count, uint64_t value);
+                            const Mult* tabs, uint64_t* out, uint64_t count, uint64_t value);
 
 // Consecutive layout: the output is cut into tiles of block*E elements;
 // workgroup w makes tiles w, w + grid, ...  In a tile, thread t makes

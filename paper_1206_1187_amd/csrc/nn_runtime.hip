@@ -1,6 +1,8 @@
 // nn_runtime.hip -- status reporting, per-device skip tables and batch plans
 // (shared by the C-ABI entry points of the plain, batched and served forms).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -209,6 +211,7 @@ void plan_release(nn_batch_plan* p) {
         if (q.graph) (void)hipGraphDestroy(q.graph);
         if (q.ws_dev) (void)hipFree(q.ws_dev);
         if (q.rec) (void)hipFree(q.rec);
+        if (q.ext) (void)hipFree(q.ext);
         if (q.ws_host) (void)hipHostFree(q.ws_host);
     }
     delete p;
@@ -225,6 +228,8 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
         // (XCD-major chunk records reach index kChunkRecWays * ceil(rows / kChunkRecWays) - 1)
         e = hipMalloc((void**)&q.rec,
                       (p->cap_rows + 2ull * p->grid + kChunkRecWays) * sizeof(RowRec));
+    if (e == hipSuccess && p->chunks)
+        e = hipMalloc((void**)&q.ext, (size_t)p->cap_desc * sizeof(RowRec));
     if (e != hipSuccess)
         return fail(NN_ENOMEM, "batch workspace (%zu bytes): %s", q.ws_bytes, hipGetErrorString(e));
     e = hipHostMalloc(&q.ws_host, q.ws_bytes, hipHostMallocDefault);
@@ -245,6 +250,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     q.args.t_hi = d.t_hi;
     q.args.t_sk = d.t_sk;
     q.args.rec = q.rec;
+    q.args.ext = q.ext;
     q.args.row_outs = 2u * kIlPairs * block;
     q.args.grid = p->grid;
     q.args.block = block;
@@ -271,6 +277,8 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
         kp.blockDim = dim3(256);
         kp.kernelParams = params;
         e = hipGraphAddKernelNode(&last, q.graph, nullptr, 0, &kp);
+        q.rec_node = last;
+        q.rec_grid = p->map_grid;
     }
     if (e == hipSuccess) {
         hipKernelNodeParams kp;
@@ -432,8 +440,50 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     if (il && rows > p->cap_rows)
         return fail(NN_ERANGE, "batch of %llu rows, plan holds %llu", (unsigned long long)rows,
                     (unsigned long long)p->cap_rows);
+    // The chunked kernel's owned mode (one record, and one workgroup, per
+    // chunk) needs the non-empty windows sorted by output offset and
+    // disjoint.  Windows are independent, so they are sorted here if they
+    // are not (a server's batches come in admission order); overlapping
+    // windows take a record per chunk and window.
+    bool owned = p->chunks && !in_args;
+    if (owned) {
+        bool sorted = true;
+        for (uint32_t k = 1; k < nd && sorted; ++k) sorted = dd[k - 1].out_off <= dd[k].out_off;
+        if (!sorted)
+            std::sort(dd, dd + nd,
+                      [](const BatchDesc& x, const BatchDesc& y) { return x.out_off < y.out_off; });
+    }
+    uint64_t end = 0;
+    for (uint32_t k = 0; k < nd && owned; ++k) {
+        if (!dd[k].len) continue;
+        if (dd[k].out_off < end) owned = false;
+        end = dd[k].out_off + dd[k].len;
+    }
+    if (owned) {
+        // chunks numbered in output order; a window whose first chunk holds
+        // the previous window's end starts at that chunk's number
+        uint64_t K = 0, prev_last = 0;
+        int64_t prev = -1;
+        for (uint32_t k = 0; k < nd; ++k) {
+            BatchDesc& D = dd[k];
+            if (!D.len) {
+                D.row_start = 0;
+                continue;
+            }
+            const uint64_t first = D.out_off / row, last = (D.out_off + D.len - 1) / row;
+            const bool shared = prev >= 0 && prev_last == first;
+            const uint64_t k0 = shared ? K - 1 : K;
+            K = k0 + (last - first + 1);
+            if (shared) dd[prev].row_start |= kDescLastShared;
+            D.row_start = k0 | (shared ? kDescFirstShared : 0);
+            prev = k;
+            prev_last = last;
+        }
+        rows = K;
+    }
     hdr->out = (uint64_t*)out;
     hdr->n_desc = nd;
+    hdr->mode = owned ? kChunkOwned : kChunkPerRecord;
     hdr->n_rows = rows;
     const size_t bytes = sizeof(BatchHeader) + nd * sizeof(BatchDesc);
     hipError_t e;
@@ -481,6 +531,20 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, stream);
     // the chunked kernel's workgroups: one per record unless the plan fixed a grid
     const uint32_t chunk_grid = p->grid ? p->grid : (uint32_t)rows;
+    // the record pre-pass: a workgroup per window (the window's skip-ahead is
+    // its one long dependent chain), at least one
+    const uint32_t rec_grid = nd < 1 ? 1u : nd > 65535 ? 65535u : nd;
+    if (e == hipSuccess && p->use_graph && q.rec_node && rec_grid != q.rec_grid) {
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof kp);
+        void* params[] = {&q.args};
+        kp.func = const_cast<void*>(batch_rec_kernel(p->indexed));
+        kp.gridDim = dim3(rec_grid);
+        kp.blockDim = dim3(256);
+        kp.kernelParams = params;
+        e = hipGraphExecKernelNodeSetParams(q.exec, q.rec_node, &kp);
+        if (e == hipSuccess) q.rec_grid = rec_grid;
+    }
     if (e == hipSuccess && p->use_graph && p->chunks && chunk_grid != q.main_grid) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
@@ -499,7 +563,7 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         BatchArgs copy = q.args;
         void* params[] = {&copy};
         if (p->interleaved || p->chunks) {
-            e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(p->map_grid), dim3(256),
+            e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(rec_grid), dim3(256),
                                 params, 0, stream);
             if (e == hipSuccess && p->chunks)
                 e = hipLaunchKernel(batch_chunks_kernel(p->kind, p->nontemporal),

@@ -64,7 +64,8 @@ def _lookup(form, kind, size, path=CACHE):
 #: run exactly these, so the timed kernels are the compared ones.
 BENCH_PLAIN = {
     "f64": dict(layout="flat", mulmod="fp64", unroll=4, occupancy=4, temporal=True),
-    "u64": dict(layout="flat", mulmod="fp64", unroll=4, occupancy=4, temporal=True),
+    # raw states: Shoup's reduction keeps the state an integer (no conversion)
+    "u64": dict(layout="flat", mulmod="shoup", unroll=4, occupancy=4, temporal=True),
 }
 
 
@@ -81,9 +82,10 @@ def bench_batch_kw(total, path=CACHE):
     return best_batch_cfg("f64", total, path)
 
 
-def best_plain_cfg(kind, count, path=CACHE):
-    """make_cfg keyword arguments tuned for ``count`` outputs, or {}."""
-    return _lookup("plain", kind, count, path)
+def best_plain_cfg(kind, count, path=CACHE, layout=None):
+    """make_cfg keyword arguments tuned for ``count`` outputs, or {};
+    ``layout="rows"``: the best shape of the row layout."""
+    return _lookup("plain" if layout is None else "plain_" + layout, kind, count, path)
 
 
 def best_batch_cfg(kind, total, path=CACHE):
@@ -202,10 +204,16 @@ def tune_plain(kind, count, reps=9, log=print):
     s0 = nn.seed(nn.INDEX_MIN)
     results = []
     grids = sorted({max(1, cus * k // 8) for k in (2, 3, 4, 5, 6, 8)})
-    for mulmod, grid, ilp, unroll, temporal in itertools.product(
-            ("fp64", "shoup"), grids, (1, 2, 4), (2, 4, 8), (False, True)):
-        kw = dict(block=256, grid=grid, mulmod=mulmod, ilp=ilp, unroll=unroll, width=2,
+    cands = [dict(block=256, grid=grid, mulmod=mulmod, ilp=ilp, unroll=unroll, width=2,
                   layout="rows", temporal=temporal)
+             for mulmod, grid, ilp, unroll, temporal in itertools.product(
+                 ("fp64", "shoup"), grids, (1, 2, 4), (2, 4, 8), (False, True))]
+    # flat layout: `unroll` rows of 512 outputs per workgroup, one workgroup
+    # per chunk, residency capped at `occupancy` workgroups per compute unit
+    cands += [dict(layout="flat", mulmod=mulmod, unroll=rows, occupancy=occ, temporal=temporal)
+              for mulmod, rows, occ, temporal in itertools.product(
+                  ("fp64", "shoup"), (2, 4, 8), (3, 4, 5, 6), (False, True))]
+    for kw in cands:
         cfg = nn.make_cfg(**kw)
         ms = _median_ms(lambda: nn.generate_into(s0, out, cfg=cfg), reps)
         results.append((ms, kw))
@@ -244,10 +252,12 @@ def tune_batch(kind, reps=5, log=print, workload=None):
     # interleaved kernel: cluster 0 = all workgroups interleave over one range
     shapes += [dict(mulmod="fp64", block=256, cluster=k, temporal=t, interleaved=True)
                for k in (0, 8, 16, 32) for t in (False, True)]
-    for shape, grid in itertools.product(shapes, grids):
-        if shape["cluster"] and grid % shape["cluster"]:
-            continue
-        kw = dict(shape, grid=grid)
+    cands = [dict(shape, grid=grid) for shape, grid in itertools.product(shapes, grids)
+             if not (shape["cluster"] and grid % shape["cluster"])]
+    # chunked kernel: one workgroup per 16 KiB chunk (grid 0), or persistent
+    cands += [dict(mulmod="fp64", chunks=True, temporal=t, grid=g)
+              for t in (False, True) for g in (0, cus * 2, cus * 4)]
+    for kw in cands:
         with nn.BatchPlan(kind, len(states), total, **kw) as plan:
             ms = _median_ms(lambda: plan.generate(states, lengths, offsets, out), reps)
         results.append((ms, kw))
@@ -257,15 +267,24 @@ def tune_batch(kind, reps=5, log=print, workload=None):
 
 
 def record(form, kind, size, results, path=CACHE):
+    """Records the fastest of `results` (sorted (ms, kw) pairs) for `form`;
+    for the plain form also the fastest row-layout shape (form "plain_rows"),
+    which callers that run the row kernel on purpose read."""
     cache = load_cache(path)
-    ms, kw = results[0]
-    cache[_key(form, kind, size)] = {
-        "cfg": kw,
-        "ms": ms,
-        "GBps": 8 * size / ms / 1e6,
-        "candidates": len(results),
-        "tuned_at": time.strftime("%Y-%m-%d"),
-    }
+    entries = [(form, results)]
+    if form == "plain":
+        entries.append(("plain_rows", [r for r in results if r[1].get("layout") == "rows"]))
+    for f, res in entries:
+        if not res:
+            continue
+        ms, kw = res[0]
+        cache[_key(f, kind, size)] = {
+            "cfg": kw,
+            "ms": ms,
+            "GBps": 8 * size / ms / 1e6,
+            "candidates": len(res),
+            "tuned_at": time.strftime("%Y-%m-%d"),
+        }
     tmp = path + ".tmp"
     with open(tmp, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)

@@ -97,8 +97,9 @@ def test_batch_bit_exact_mixed_lengths(kind, mulmod, interleaved):
 
 @pytest.mark.parametrize("kind", ["u64", "f64"])
 def test_chunked_batch_bit_exact_mixed_lengths(kind):
-    """The chunked kernel (records per 2048-output chunk and window, dealt
-    round-robin to persistent workgroups): windows shorter than a chunk,
+    """The chunked kernel (sorted windows: a record per 2048-output chunk,
+    one workgroup writing every window's part of it; dealt round-robin to
+    persistent workgroups when the grid is fixed): windows shorter than a chunk,
     several windows in one chunk, windows starting and ending inside chunks
     at both offset parities, gaps between windows; grids from one workgroup
     (every record on it) to more workgroups than records; graph and direct
@@ -122,7 +123,8 @@ def test_chunked_batch_bit_exact_mixed_lengths(kind):
 
 def test_chunked_batch_dense_short_windows():
     """Thousands of windows of 1 to 40 outputs packed back to back, so most
-    chunks hold dozens of windows (one record each), against the oracle."""
+    chunks hold dozens of windows (all written by the chunk's one workgroup
+    from the windows' first-chunk records), against the oracle."""
     rng = np.random.default_rng(17)
     lengths = [int(x) for x in rng.integers(1, 41, 3000)]
     states, lengths, offsets, total = _mixed_batch(18, lengths)
@@ -131,6 +133,24 @@ def test_chunked_batch_dense_short_windows():
         plan.generate(states, lengths, offsets, buf.view(torch.float64))
         torch.cuda.synchronize()
     _check_batch(_bits(buf), states, lengths, offsets, "f64")
+
+
+@pytest.mark.parametrize("temporal", [False, True])
+def test_chunked_batch_unsorted_windows(temporal):
+    """Windows given out of output order (the same windows as the mixed
+    batch, shuffled; the plan sorts them by output offset): against the
+    oracle, final states in the caller's order, nothing written outside."""
+    lengths = LENGTHS + [2047, 2048, 2049, 4097, 1, 2, 5, 3000, 1, 1]
+    states, lengths, offsets, total = _mixed_batch(19, lengths)
+    perm = np.random.default_rng(20).permutation(len(lengths))
+    states, lengths, offsets = states[perm], lengths[perm], offsets[perm]
+    buf = _sentinel(total)
+    with nn.BatchPlan("f64", 64, total, chunks=True, temporal=temporal) as plan:
+        fin = plan.generate(states, lengths, offsets, buf.view(torch.float64), final_states=True)
+        torch.cuda.synchronize()
+    _check_batch(_bits(buf), states, lengths, offsets, "f64")
+    for s, n, f in zip(states.tolist(), lengths.tolist(), fin.tolist()):
+        assert f == orc.skip(s, n)
 
 
 def test_chunked_batch_validation():

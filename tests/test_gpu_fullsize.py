@@ -2,14 +2,17 @@
 
 The plain bulk workload (2^30 f64 variates, then 2^28 raw u64 states from
 one seed index) in the launch configuration bench.py uses for each kind,
-and the batched workload (10,000 streams, 2.7e9 outputs) in the batch shape
-bench.py uses, each compared element by element with the oracle.  The
+the batched workload (10,000 streams, 2.7e9 outputs) in the batch shape
+bench.py uses, and the 3^40 generator's default launch for 2^30 f64
+outputs (the bench's modulus-3^40 figure), each compared element by element
+with the oracle.  The
 configurations come from one place (``tune.BENCH_PLAIN`` and
 ``tune.bench_batch_kw``), which bench.py reads too.  Bit-exact: the path is
 integer work and the variate is one IEEE multiplication (Section 2's
 parallel sequence must equal the serial one).
 """
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -111,5 +114,33 @@ def test_bench_batched_launch_full_size_bit_exact():
             raise AssertionError(("stream", k, "element", o0 + int(bad[0]) - int(offsets[k]),
                                   got[bad[0]], ref[bad[0]]))
         i = j
+    del out, flat
+    torch.cuda.empty_cache()
+
+
+def test_e40_default_launch_full_size_bit_exact():
+    """The 3^40 generator's default launch for 2^30 f64 outputs (the flat
+    layout, 8 rows per chunk, FP64 limb step), every output against the
+    3^40 oracle: slices of 2^26 filled on host threads, each from the
+    oracle's own skip-ahead."""
+    n = 1 << 30
+    z0 = orc.e40_seed(orc.E40_INDEX_MIN + 123456789)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    out.view(torch.int64).fill_(-1)
+    _say("e40 default launch, 2^30 f64")
+    zn = nn.e40_generate_into(z0, out)
+    torch.cuda.synchronize()
+    assert zn == orc.e40_skip(z0, n)
+    flat = out.view(torch.int64)
+    piece = 1 << 26
+
+    def ref(i):
+        return orc.e40_gen(orc.e40_skip(z0, i * piece), piece, "f64")[0].view(np.uint64)
+
+    with ThreadPoolExecutor(max_workers=min(16, orc.max_threads())) as ex:
+        for i, want in enumerate(ex.map(ref, range(n // piece))):
+            got = flat[i * piece:(i + 1) * piece].cpu().numpy().view(np.uint64)
+            bad = np.nonzero(got != want)[0]
+            assert bad.size == 0, ("e40", i * piece + int(bad[0]), got[bad[0]], want[bad[0]])
     del out, flat
     torch.cuda.empty_cache()

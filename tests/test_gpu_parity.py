@@ -269,6 +269,19 @@ def test_fill_ceiling_kernel_pattern():
         h = _bits(buf)
         assert (h[:256] == SENTINEL).all() and (h[256 + count:] == SENTINEL).all()
         assert (h[256:256 + count] == 0x3FF0000000000001).all()
+    # the fill that keeps the generator's start (flat layout only), past one
+    # launch's 2^30 outputs so the chunk tables' last entries are read
+    for cfg, count in [(cfgs[6], (1 << 30) + 4099), (cfgs[5], 100_003), (cfgs[7], 2049)]:
+        buf = _sentinel_buffer(count + 512)
+        nn.fill(buf[256:256 + count], 0x3FF0000000000001, cfg=cfg, with_start=True)
+        torch.cuda.synchronize()
+        h = _bits(buf)
+        assert (h[:256] == SENTINEL).all() and (h[256 + count:] == SENTINEL).all()
+        assert (h[256:256 + count] == 0x3FF0000000000001).all()
+        del buf, h
+    with pytest.raises(nn.NNError):
+        nn.fill(torch.empty(1024, dtype=torch.float64, device="cuda"), 0, cfg=cfgs[0],
+                with_start=True)
 
 
 def test_plain_bulk_full_size_bit_exact():
@@ -306,7 +319,7 @@ def test_plain_bulk_full_size_row_grids_sampled(kind, deltas):
     case = wl.plain_bulk()
     z0 = nn.seed(case.index)
     count = case.count_f64 if kind == "f64" else case.count_u64
-    kw = tune.best_plain_cfg(kind, count)
+    kw = tune.best_plain_cfg(kind, count, layout="rows")
     base = nn.make_cfg(**dict(kw, layout="rows", grid=kw.get("grid") or 128))
     dt = torch.float64 if kind == "f64" else torch.uint64
     out = torch.empty(count, dtype=dt, device="cuda")

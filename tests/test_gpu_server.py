@@ -37,18 +37,24 @@ def _device():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("kind,interleaved", [("f64", False), ("u64", False), ("f64", True),
-                                              ("u64", True)])
-def test_served_requests_equal_oracle_and_plain_alone(kind, interleaved):
-    """Both batch kernels in the server's indexed mode (states read from the
-    device table)."""
-    _say("served", kind, "interleaved" if interleaved else "blocked")
+LANE_SHAPES = {"blocked": {}, "interleaved": dict(interleaved=True, block=128),
+               "chunked": dict(chunks=True, temporal=True)}
+
+
+@pytest.mark.parametrize("kind,shape", [("f64", "blocked"), ("u64", "blocked"),
+                                        ("f64", "interleaved"), ("u64", "interleaved"),
+                                        ("f64", "chunked"), ("u64", "chunked")])
+def test_served_requests_equal_oracle_and_plain_alone(kind, shape):
+    """Every batch kernel in the server's indexed mode (states read from the
+    device table; the chunked kernel with its windows sorted by pool offset,
+    one workgroup per chunk)."""
+    _say("served", kind, shape)
     states = _states(8, 21)
     rng = np.random.default_rng(22)
     reqs = [(int(rng.integers(0, 8)), int(np.floor(np.exp(rng.uniform(0, np.log(1 << 18))))))
             for _ in range(300)] + [(3, 0), (5, 1), (5, (1 << 20) + 3)]
     with serve.Server(states, 1 << 28, kind=kind, lanes=3, max_batch_requests=32,
-                      interleaved=interleaved, **({"block": 128} if interleaved else {})) as srv:
+                      **LANE_SHAPES[shape]) as srv:
         tickets = [srv.submit(s, n) for s, n in reqs]
         done = {}
         while len(done) < len(reqs):
