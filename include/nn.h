@@ -284,18 +284,21 @@ typedef struct nn_batch_cfg {
 #define NN_BATCH_INTERLEAVED 16u
 /* Chunked kernel: the plain generator's flat layout over a batch.  The
  * output is cut into aligned chunks of 2048 outputs (16 KiB); a pre-pass
- * writes one record per chunk and window that meet (the state of the
- * chunk's first element in that window, and the window's part of the
- * chunk), and 256-thread workgroups write the records' chunks as four rows
- * of 512 outputs with one 16-byte store per lane and row.  grid 0 (the
- * default): one workgroup per record, dispatched in output order as the
- * plain flat layout's chunks are (the plan's graph gets the batch's record
- * count as its grid before each replay); a nonzero grid: that many
- * persistent workgroups taking the records round-robin.  Needs the FP64
- * reduction, block 0 or 256, cluster 0 or 1 and output indices below 2^51
- * (NN_ERANGE otherwise).  Exclusive with NN_BATCH_INTERLEAVED.  Batches of
- * at most 16 windows travel in the kernel arguments (the FP64 reduction's
- * flat inline kernel). */
+ * writes the chunks' records (the state of the chunk's first element as if
+ * the window covered it, and the window's part of the chunk), and
+ * 256-thread workgroups write the records' chunks as four rows of 512
+ * outputs with one 16-byte store per lane and row.  The plan sorts the
+ * windows by output offset (they are independent) and gives each chunk one
+ * record and one workgroup, which writes every window's part of it; windows
+ * that overlap each other get a record per chunk and window instead.
+ * grid 0 (the default): one workgroup per record, dispatched in output
+ * order as the plain flat layout's chunks are (the plan's graph gets the
+ * batch's record count as its grid before each replay); a nonzero grid:
+ * that many persistent workgroups taking the records round-robin.  Needs
+ * the FP64 reduction, block 0 or 256, cluster 0 or 1 and output indices
+ * below 2^51 (NN_ERANGE otherwise).  Exclusive with NN_BATCH_INTERLEAVED.
+ * Batches of at most 16 windows travel in the kernel arguments (the FP64
+ * reduction's flat inline kernel). */
 #define NN_BATCH_CHUNKS 32u
 
 /* Opaque batch plan: device workspace, pinned staging and a hipGraph of
@@ -318,6 +321,12 @@ int nn_batch_plan_cfg(const nn_batch_plan *plan, nn_batch_cfg *cfg_out);
 /* nn_generate_batch -- the batched form of Algorithm BB step 3: every
  * stream of `descs` (host array of n) is generated by one persistent kernel
  * launch on `stream` (a hipStream_t), replayed from the plan's hipGraph.
+ * It takes a plan rather than (descs, n, out, kind, stream) alone because a
+ * hipGraph is replayed with fixed kernel arguments: the plan owns the
+ * instantiated graphs and the device workspace their arguments point to
+ * (descriptors, records), and fixes the output kind and kernel shape, so a
+ * call uploads descriptors and replays without allocating or capturing.
+ * nn_generate_batch_static below is the plan-free form of the same call.
  * out_dev: device memory of the plan's device, 16-byte aligned, holding
  * every window.  Streams longer than 2^24 outputs are split internally.
  * Outputs are identical to nn_generate on each stream alone.  final_states
