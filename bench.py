@@ -457,13 +457,23 @@ def main():
         # Section 2's larger modulus 3^40: the library default (FP64 step on
         # base-3^20 limbs; the flat layout with 8 rows per chunk for f64, the
         # row layout for u64), both layouts explicitly, and the Montgomery step.
+        # Every configuration is run once before any is timed, then the
+        # configurations are timed in turn over two rounds (the best round
+        # counts): the first 3^40 launches of a process ran several per cent
+        # slower than later ones of the same kernel.
+        z40 = nn.e40_seed(nn.E40_INDEX_MIN)
         for kind, out in (("f64", out_f), ("u64", out_u)):
-            for name, cfg in (("", None), ("_flat", nn.make_cfg(layout="flat", unroll=8)),
-                              ("_rows", nn.make_cfg(layout="rows")),
-                              ("_montgomery", nn.make_cfg(mulmod="montgomery"))):
-                s = _timed_kernel(
-                    lambda: nn.e40_generate_into(nn.e40_seed(nn.E40_INDEX_MIN), out, cfg=cfg),
-                    10, torch)
+            e40_cfgs = (("", None), ("_flat", nn.make_cfg(layout="flat", unroll=8)),
+                        ("_rows", nn.make_cfg(layout="rows")),
+                        ("_montgomery", nn.make_cfg(mulmod="montgomery")))
+            for _, cfg in e40_cfgs:
+                nn.e40_generate_into(z40, out, cfg=cfg)
+            best = {}
+            for _ in range(2):
+                for name, cfg in e40_cfgs:
+                    s = _timed_kernel(lambda: nn.e40_generate_into(z40, out, cfg=cfg), 10, torch)
+                    best[name] = min(best.get(name, s), s)
+            for name, s in best.items():
                 extras["modulus_3e40%s_%s_GBps" % (name, kind)] = 8.0 * out.numel() / s / 1e9
         result["extras"] = extras
         log("extras", json.dumps(extras))

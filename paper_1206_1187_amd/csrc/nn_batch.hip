@@ -478,8 +478,8 @@ template <int KIND, bool NT>
 __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     constexpr uint32_t C = kChunkOuts;
     const const_ptr<BatchHeader> hdr = as_const(a.ws);
-    const uint64_t n = hdr->n_rows;  // records
-    const global_ptr<uint64_t> out = as_global(hdr->out);
+    const uint64_t n = a.n_rec;  // records (== hdr->n_rows)
+    const global_ptr<uint64_t> out = as_global(a.out);
     const const_ptr<u64x2> rec = reinterpret_cast<const_ptr<u64x2>>(as_const(a.rec));
     const const_ptr<u64x2> ext = reinterpret_cast<const_ptr<u64x2>>(as_const(a.ext));
     const uint64_t per = (n + kChunkRecWays - 1) / kChunkRecWays;

@@ -101,6 +101,11 @@ struct BatchArgs {
     // Interleaved and chunked kernels only:
     RowRec* rec;            // row records (device workspace)
     RowRec* ext;            // chunked, owned mode: each window's first-chunk record
+    // Chunked kernel only, set for each batch (the plan updates its graph
+    // node's arguments with the grid): the record count and the output, so
+    // a workgroup's start waits on its record load alone.
+    uint64_t n_rec;
+    uint64_t* out;
     Mult JR;                // (2^53)^(row_outs*256): a pre-pass thread's next row
     uint32_t grid;          // workgroups of the row kernel
     uint32_t block;         // threads per workgroup of the row kernel

@@ -604,11 +604,14 @@ int nn_generate_batch_static(const nn_stream_desc* descs, uint32_t n, void* out_
     a.cluster = kChunkRecWays;
     a.block = kFlatBlock;
     a.JR = make_mult(MultPowers::get().pow((uint64_t)kChunkOuts * 256));
+    a.n_rec = records;
+    a.out = static_cast<uint64_t*>(out_dev);
     uint32_t lds = (d->lds_per_cu / (kFlatDefaultOccupancy + 1) / 512 + 1) * 512;
     if (lds > d->lds_per_block) lds = 0;
     void* params[] = {&a};
+    // the record pre-pass: a workgroup per window
     if (e == hipSuccess)
-        e = hipLaunchKernel(batch_rec_kernel(false), dim3(d->cus > 0 ? d->cus * 4 : 64), dim3(256),
+        e = hipLaunchKernel(batch_rec_kernel(false), dim3(n > 65535 ? 65535u : n), dim3(256),
                             params, 0, s);
     if (e == hipSuccess)
         e = hipLaunchKernel(batch_chunks_kernel(kind, true), dim3((uint32_t)records),

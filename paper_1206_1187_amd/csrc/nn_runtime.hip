@@ -529,8 +529,11 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         return NN_OK;
     }
     e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, stream);
-    // the chunked kernel's workgroups: one per record unless the plan fixed a grid
+    // the chunked kernel's workgroups: one per record unless the plan fixed a grid;
+    // its arguments carry the record count and the output
     const uint32_t chunk_grid = p->grid ? p->grid : (uint32_t)rows;
+    q.args.n_rec = rows;
+    q.args.out = (uint64_t*)out;
     // the record pre-pass: a workgroup per window (the window's skip-ahead is
     // its one long dependent chain), at least one
     const uint32_t rec_grid = nd < 1 ? 1u : nd > 65535 ? 65535u : nd;
@@ -545,7 +548,7 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         e = hipGraphExecKernelNodeSetParams(q.exec, q.rec_node, &kp);
         if (e == hipSuccess) q.rec_grid = rec_grid;
     }
-    if (e == hipSuccess && p->use_graph && p->chunks && chunk_grid != q.main_grid) {
+    if (e == hipSuccess && p->use_graph && p->chunks) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
         void* params[] = {&q.args};
