@@ -325,7 +325,6 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
         FlatArgs f;
         f.M1 = make_mult(kMult);
         f.J = make_mult(MultPowers::get().pow(kFlatPerBlock));
-        f.tabs = d->t_lo;
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
             f.out = (uint64_t*)out_dev + off;
@@ -442,7 +441,7 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
         for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
             hipError_t e = launch_fill_flat(r.nontemporal, (int)r.unroll, r.lds,
-                                            (hipStream_t)stream, with_start ? d->t_lo : nullptr,
+                                            (hipStream_t)stream, with_start,
                                             (uint64_t*)out_dev + off, n, value);
             if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
         }

@@ -256,6 +256,33 @@ __global__ __launch_bounds__(1024) void k_fill(uint64_t* __restrict__ out, uint6
     }
 }
 
+// The flat kernels' multipliers in a static device array of this module:
+// the lane offsets (2^53)^(2l) for l < kFlatBlock, then t_flo and t_fhi.
+// Its address is a link-time constant of the code, so a workgroup issues
+// its table loads at once instead of after the load of a table pointer
+// from its arguments.  Filled per device at set-up (upload_flat_symbol).
+__device__ Mult flat_sym[kFlatSymEntries];
+
+// flat_start over flat_sym: the states of lane l's pair (outputs 2l and
+// 2l + 1) of the chunk that begins u = b*R rows after the output whose state
+// is `base`.  b*R < kFlatMaxRowsPerLaunch.
+template <class V>
+__device__ __forceinline__ void flat_start_sym(uint64_t b, uint32_t l, int R, uint64_t base,
+                                               const Mult& M1, typename V::S& za,
+                                               typename V::S& zb) {
+    const uint64_t u = b * (uint64_t)R;
+    const Mult hi = flat_sym[kFlatSymHi + u / kFlatLoSize];
+    const Mult lo = flat_sym[kFlatSymLo + u % kFlatLoSize];
+    const Mult lane = flat_sym[kFlatSymLane + l];
+    za = V::mul(V::mul(V::mul(V::load(base), hi), lo), lane);
+    zb = V::mul(za, M1);
+}
+
+hipError_t upload_flat_symbol(const Mult* entries) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(flat_sym), entries, sizeof(Mult) * kFlatSymEntries, 0,
+                             hipMemcpyHostToDevice);
+}
+
 // Flat layout (see launch_generate_flat).  Workgroup b writes the R rows of
 // kFlatPerBlock outputs from element kFlatPerBlock*R*b on, lane l the pair
 // 2l of each row, and exits.  Its start is two multiplications by uniform
@@ -264,13 +291,13 @@ __global__ __launch_bounds__(1024) void k_fill(uint64_t* __restrict__ out, uint6
 // two multiplications to the next.
 //
 // A workgroup lives a few microseconds, so its start must not wait on more
-// round trips of scalar-load latency than needed: the table allocation and
-// the base lead the arguments (one scalar load fetches both), the whole-chunk
-// kernel takes no count and tests nothing, and the table indices are in
-// range for every lane.  A ragged last chunk goes to k_generate_flat_tail.
+// round trips of scalar-load latency than needed: the tables sit at a fixed
+// address (flat_sym), so their loads go out with the load of the base, the
+// whole-chunk kernel takes no count and tests nothing, and the table
+// indices are in range for every lane.  A ragged last chunk goes to
+// k_generate_flat_tail.
 template <class V, int KIND, bool NT, int R>
-__global__ __launch_bounds__(kFlatBlock) void k_generate_flat(const Mult* __restrict__ tabs,
-                                                              uint64_t base,
+__global__ __launch_bounds__(kFlatBlock) void k_generate_flat(uint64_t base,
                                                               uint64_t* __restrict__ out,
                                                               Mult M1, Mult J) {
     extern __shared__ char occupancy_cap[];  // dynamic LDS only limits residency
@@ -278,7 +305,7 @@ __global__ __launch_bounds__(kFlatBlock) void k_generate_flat(const Mult* __rest
     const uint64_t b = blockIdx.x;
     const uint32_t l = threadIdx.x;
     typename V::S za, zb;
-    flat_start<V>(b, l, R, base, tabs, M1, za, zb);
+    flat_start_sym<V>(b, l, R, base, M1, za, zb);
     u64x2* p = reinterpret_cast<u64x2*>(out + (uint64_t)kFlatPerBlock * R * b + 2u * l);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -297,14 +324,13 @@ __global__ __launch_bounds__(kFlatBlock) void k_generate_flat(const Mult* __rest
 // The last, partial chunk: `count` < kFlatPerBlock*R outputs from `out`,
 // one workgroup (b = 0 relative to `base`).
 template <class V, int KIND, bool NT, int R>
-__global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(const Mult* __restrict__ tabs,
-                                                                   uint64_t base,
+__global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(uint64_t base,
                                                                    uint64_t* __restrict__ out,
                                                                    Mult M1, Mult J,
                                                                    uint64_t count) {
     const uint32_t l = threadIdx.x;
     typename V::S za, zb;
-    flat_start<V>(0, l, R, base, tabs, M1, za, zb);
+    flat_start_sym<V>(0, l, R, base, M1, za, zb);
     uint64_t k = 2u * l;
     for (int r = 0; r < R && k < count; ++r, k += kFlatPerBlock) {
         if (k + 1 < count) {
@@ -332,8 +358,7 @@ __global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(const Mult* _
 // the generator minus its arithmetic.  (The entries are positive, so the
 // comparison always keeps `value`.)
 template <bool NT, int R, bool START>
-__global__ __launch_bounds__(kFlatBlock) void k_fill_flat(const Mult* __restrict__ tabs,
-                                                          uint64_t* __restrict__ out,
+__global__ __launch_bounds__(kFlatBlock) void k_fill_flat(uint64_t* __restrict__ out,
                                                           uint64_t value) {
     extern __shared__ char occupancy_cap[];
     (void)occupancy_cap;
@@ -341,9 +366,9 @@ __global__ __launch_bounds__(kFlatBlock) void k_fill_flat(const Mult* __restrict
     v.x = value;
     if constexpr (START) {
         const uint64_t u = (uint64_t)blockIdx.x * R;
-        const double hi = tabs[kFlatHiOffset + u / kFlatLoSize].v;
-        const double lo = tabs[kFlatLoOffset + u % kFlatLoSize].v;
-        const double lane = tabs[2u * threadIdx.x].v;
+        const double hi = flat_sym[kFlatSymHi + u / kFlatLoSize].v;
+        const double lo = flat_sym[kFlatSymLo + u % kFlatLoSize].v;
+        const double lane = flat_sym[kFlatSymLane + threadIdx.x].v;
         v.x = hi + lo + lane > 0.0 ? value : 0;
     }
     v.y = v.x;
@@ -379,14 +404,14 @@ static hipError_t flat_one(uint32_t lds, hipStream_t s, const FlatArgs& a) {
     const uint64_t tail = a.count - full * per;
     if (full) {
         hipLaunchKernelGGL((k_generate_flat<V, KIND, NT, R>), dim3((uint32_t)full),
-                           dim3(kFlatBlock), lds, s, a.tabs, a.base, a.out, a.M1, a.J);
+                           dim3(kFlatBlock), lds, s, a.base, a.out, a.M1, a.J);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (tail) {
         // the tail chunk starts full*R rows in: its own base, one workgroup
         hipLaunchKernelGGL((k_generate_flat_tail<V, KIND, NT, R>), dim3(1), dim3(kFlatBlock), 0,
-                           s, a.tabs, a.tail_base, a.out + full * per, a.M1, a.J, tail);
+                           s, a.tail_base, a.out + full * per, a.M1, a.J, tail);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -424,18 +449,18 @@ hipError_t launch_generate_flat(int mulmod, int kind, bool nt, int rows, uint32_
 }
 
 template <bool NT, int R>
-static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, const Mult* tabs, uint64_t* out,
+static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, bool start, uint64_t* out,
                                 uint64_t count, uint64_t value) {
     const uint64_t per = (uint64_t)kFlatPerBlock * R;
     const uint64_t full = count / per;
     const uint64_t tail = count - full * per;
     if (full) {
-        if (tabs)
+        if (start)
             hipLaunchKernelGGL((k_fill_flat<NT, R, true>), dim3((uint32_t)full), dim3(kFlatBlock),
-                               lds, s, tabs, out, value);
+                               lds, s, out, value);
         else
             hipLaunchKernelGGL((k_fill_flat<NT, R, false>), dim3((uint32_t)full),
-                               dim3(kFlatBlock), lds, s, tabs, out, value);
+                               dim3(kFlatBlock), lds, s, out, value);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -448,22 +473,22 @@ static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, const Mult* tabs, u
 }
 
 template <bool NT>
-static hipError_t fill_flat_r(int rows, uint32_t lds, hipStream_t s, const Mult* tabs,
+static hipError_t fill_flat_r(int rows, uint32_t lds, hipStream_t s, bool start,
                               uint64_t* out, uint64_t count, uint64_t value) {
     switch (rows) {
-        case 1: return fill_flat_one<NT, 1>(lds, s, tabs, out, count, value);
-        case 2: return fill_flat_one<NT, 2>(lds, s, tabs, out, count, value);
-        case 4: return fill_flat_one<NT, 4>(lds, s, tabs, out, count, value);
-        case 8: return fill_flat_one<NT, 8>(lds, s, tabs, out, count, value);
-        case 16: return fill_flat_one<NT, 16>(lds, s, tabs, out, count, value);
+        case 1: return fill_flat_one<NT, 1>(lds, s, start, out, count, value);
+        case 2: return fill_flat_one<NT, 2>(lds, s, start, out, count, value);
+        case 4: return fill_flat_one<NT, 4>(lds, s, start, out, count, value);
+        case 8: return fill_flat_one<NT, 8>(lds, s, start, out, count, value);
+        case 16: return fill_flat_one<NT, 16>(lds, s, start, out, count, value);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_fill_flat(bool nt, int rows, uint32_t lds, hipStream_t s, const Mult* tabs,
+hipError_t launch_fill_flat(bool nt, int rows, uint32_t lds, hipStream_t s, bool start,
                             uint64_t* out, uint64_t count, uint64_t value) {
-    return nt ? fill_flat_r<true>(rows, lds, s, tabs, out, count, value)
-              : fill_flat_r<false>(rows, lds, s, tabs, out, count, value);
+    return nt ? fill_flat_r<true>(rows, lds, s, start, out, count, value)
+              : fill_flat_r<false>(rows, lds, s, start, out, count, value);
 }
 
 // Kernel selector: W = 1, W = 2, or W = 2 with IL = 2 or 4 rows in flight.

@@ -78,6 +78,15 @@ constexpr uint32_t kFlatMaxRows = 16;
 constexpr uint32_t kFlatDefaultRows = 4;
 constexpr uint32_t kFlatDefaultOccupancy = 4;
 
+// The flat kernels' own copy of their multipliers (a static device array):
+// kFlatBlock lane offsets (2^53)^(2l), then t_flo and t_fhi.
+constexpr uint32_t kFlatSymLane = 0;
+constexpr uint32_t kFlatSymLo = kFlatBlock;
+constexpr uint32_t kFlatSymHi = kFlatSymLo + kFlatLoSize;
+constexpr uint32_t kFlatSymEntries = kFlatSymHi + kFlatHiSize;
+// Copies kFlatSymEntries entries into the current device's array.
+hipError_t upload_flat_symbol(const Mult* entries);
+
 struct FlatArgs {
     uint64_t* out;   // 16-byte aligned
     uint64_t count;  // <= kFlatMaxCount
@@ -85,17 +94,15 @@ struct FlatArgs {
     uint64_t tail_base;  // state of the first output of the partial last chunk, if any
     Mult M1;         // 2^53
     Mult J;          // (2^53)^kFlatPerBlock: the next row of a lane
-    const Mult* tabs;   // the device tables: t_lo at 0, t_flo and t_fhi at their offsets
 };
 
 // rows: rows per workgroup (1, 2, 4, 8, 16); lds_bytes > 0 caps the
 // resident workgroups per compute unit.
 hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, int rows,
                                 uint32_t lds_bytes, hipStream_t stream, const FlatArgs& a);
-// tabs: NULL for the plain fill; the device table allocation for the fill
-// that keeps the generator's start (NN_FILL_WITH_START).
+// start: the fill that keeps the generator's table loads (NN_FILL_WITH_START).
 hipError_t launch_fill_flat(bool nontemporal, int rows, uint32_t lds_bytes, hipStream_t stream,
-                            const Mult* tabs, uint64_t* out, uint64_t count, uint64_t value);
+                            bool start, uint64_t* out, uint64_t count, uint64_t value);
 
 // Consecutive layout: the output is cut into tiles of block*E elements;
 // workgroup w makes tiles w, w + grid, ...  In a tile, thread t makes

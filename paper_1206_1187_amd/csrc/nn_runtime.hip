@@ -174,6 +174,17 @@ int ensure_device_current(int dev, DeviceTables** out) {
         static_assert(kFlatLoOffset == (uint64_t)kLoSize + kHiSize + kSkipLevels * kSkipSize,
                       "the flat tables follow the skip tables");
         d.t8 = (double*)((char*)mem + mult_bytes + blk_bytes);
+        {
+            // the flat kernels' static copy: even t_lo entries, t_flo, t_fhi
+            std::vector<Mult> sym(kFlatSymEntries);
+            for (uint32_t l = 0; l < kFlatBlock; ++l) sym[kFlatSymLane + l] = h[2u * l];
+            std::copy(hb.begin(), hb.end(), sym.begin() + kFlatSymLo);
+            e = upload_flat_symbol(sym.data());
+            if (e != hipSuccess) {
+                (void)hipFree(mem);
+                return fail(NN_EHIP, "flat table upload: %s", hipGetErrorString(e));
+            }
+        }
         void* ws = nullptr;
         e = hipGetSymbolAddress(&ws, HIP_SYMBOL(scratch));
         if (e != hipSuccess) {
