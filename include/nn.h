@@ -262,13 +262,16 @@ typedef struct nn_stream_desc {
  * grid; 0 = grid); mulmod: an
  * nn_mulmod; flags: NN_CFG_TEMPORAL_STORES, NN_BATCH_NO_GRAPH (enqueue a
  * copy and a kernel launch instead of replaying the plan's graph),
- * NN_BATCH_INTERLEAVED. */
+ * NN_BATCH_INTERLEAVED; occupancy: NN_BATCH_CHUNKS only, 0 (4) or a cap in
+ * [2,16] on the chunk kernel's resident workgroups per compute unit (as
+ * nn_launch_cfg's occupancy caps the plain flat layout's). */
 typedef struct nn_batch_cfg {
     uint32_t block;
     uint32_t grid;
     uint32_t cluster;
     uint32_t mulmod;
     uint32_t flags;
+    uint32_t occupancy;
 } nn_batch_cfg;
 #define NN_BATCH_NO_GRAPH 8u
 /* Interleaved kernel: a pre-pass writes one record per row of 2*block

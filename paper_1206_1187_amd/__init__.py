@@ -302,7 +302,7 @@ class BatchPlan:
 
     def __init__(self, kind, max_streams, max_outputs, block=0, grid=0, mulmod=0,
                  temporal=False, graph=True, device=None, cluster=0, interleaved=False,
-                 chunks=False):
+                 chunks=False, occupancy=0):
         import torch
         if isinstance(mulmod, str):
             mulmod = MULMOD_NAMES[mulmod]
@@ -310,7 +310,8 @@ class BatchPlan:
                 (0 if graph else _native.NN_BATCH_NO_GRAPH) | \
                 (_native.NN_BATCH_INTERLEAVED if interleaved else 0) | \
                 (_native.NN_BATCH_CHUNKS if chunks else 0)
-        cfg = _native.BatchCfg(int(block), int(grid), int(cluster), int(mulmod), flags)
+        cfg = _native.BatchCfg(int(block), int(grid), int(cluster), int(mulmod), flags,
+                               int(occupancy))
         self.kind = _kind(kind)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else int(device))

@@ -74,6 +74,7 @@ class BatchCfg(ctypes.Structure):
         ("cluster", ctypes.c_uint32),
         ("mulmod", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
+        ("occupancy", ctypes.c_uint32),
     ]
 
     def as_dict(self):

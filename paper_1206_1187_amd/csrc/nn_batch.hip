@@ -474,20 +474,31 @@ __global__ __launch_bounds__(256) void k_batch_rows(BatchArgs a) {
 // windows share is written whole by its workgroup, window by window.  (With
 // write-back stores, chunks written in parts by workgroups on different
 // XCDs cost the 10,000-window batch 12 % of its rate.)
+__device__ Mult chunk_sym[kChunkSymEntries];
+
+hipError_t upload_chunk_symbol(const Mult* entries) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(chunk_sym), entries, sizeof(Mult) * kChunkSymEntries, 0,
+                             hipMemcpyHostToDevice);
+}
+
 template <int KIND, bool NT>
 __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     constexpr uint32_t C = kChunkOuts;
-    const const_ptr<BatchHeader> hdr = as_const(a.ws);
     const uint64_t n = a.n_rec;  // records (== hdr->n_rows)
-    const global_ptr<uint64_t> out = as_global(a.out);
     const const_ptr<u64x2> rec = reinterpret_cast<const_ptr<u64x2>>(as_const(a.rec));
-    const const_ptr<u64x2> ext = reinterpret_cast<const_ptr<u64x2>>(as_const(a.ext));
     const uint64_t per = (n + kChunkRecWays - 1) / kChunkRecWays;
+    auto at = [&](uint64_t i) { return (i % kChunkRecWays) * per + i / kChunkRecWays; };
     const uint32_t l = threadIdx.x;
     uint64_t j = blockIdx.x;
+    // Loads before tests: the multipliers (at a fixed address) and the
+    // workgroup's record go out before anything waits.  A workgroup past the
+    // last record (a fixed grid larger than the batch) reads record 0, which
+    // every record array holds, and leaves.
+    const Mult ma = chunk_sym[2u * l], mb = chunk_sym[2u * l + 1];
+    const Mult JB = chunk_sym[2 * kFlatBlock];
+    u64x2 cur = rec[at(j < n ? j : 0)];
     if (j >= n) return;
-    const Mult ma = a.t_lo[2u * l], mb = a.t_lo[2u * l + 1];
-    u64x2 cur = rec[(j % kChunkRecWays) * per + j / kChunkRecWays];
+    const global_ptr<uint64_t> out = as_global(a.out);
     // one window's part [lo, hi) of the chunk at output g, from the state z0
     // of the chunk's element 0 as if the window covered it
     auto part = [&](uint64_t g, double z0, uint32_t lo, uint32_t hi) {
@@ -498,14 +509,15 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
         for (int r = 0; r < (int)kChunkRows; ++r) {
             put_pair_in<KIND, NT>(p + r * kFlatPerBlock, za, zb, r * kFlatPerBlock + 2u * l, lo,
                                   hi);
-            za = VarFP64::mul(za, a.JB);
-            zb = VarFP64::mul(zb, a.JB);
+            za = VarFP64::mul(za, JB);
+            zb = VarFP64::mul(zb, JB);
         }
     };
     for (;;) {
-        const uint64_t jn = j + gridDim.x < n ? j + gridDim.x : j;
-        // the next record, in flight meanwhile
-        const u64x2 nxt = rec[(jn % kChunkRecWays) * per + jn / kChunkRecWays];
+        const uint64_t jn = j + gridDim.x;
+        // a fixed grid's next record, in flight meanwhile
+        u64x2 nxt = cur;
+        if (jn < n) nxt = rec[at(jn)];
         const double z0 = __builtin_bit_cast(double, cur.x);
         const uint64_t info = cur.y;
         const uint32_t hi = (uint32_t)(info >> kRecHiShift);
@@ -518,8 +530,8 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
             for (int r = 0; r < (int)kChunkRows; ++r) {
                 put<NT>(reinterpret_cast<global_ptr<u64x2>>(p + r * kFlatPerBlock),
                         pair_bits<VarFP64, KIND>(za, zb));
-                za = VarFP64::mul(za, a.JB);
-                zb = VarFP64::mul(zb, a.JB);
+                za = VarFP64::mul(za, JB);
+                zb = VarFP64::mul(zb, JB);
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else if (!((info >> kRecMulti) & 1)) {
@@ -528,7 +540,8 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
             // Owned mode, a chunk that windows d, d + 1, ... share: the later
             // windows' records are their ext records (empty windows skipped);
             // the first of them also gives the chunk's output index.
-            const uint32_t n_desc = hdr->n_desc;
+            const const_ptr<u64x2> ext = reinterpret_cast<const_ptr<u64x2>>(as_const(a.ext));
+            const uint32_t n_desc = as_const(a.ws)->n_desc;
             uint64_t w = (info & kRecIndexMask) >> 11;  // d + 1
             u64x2 R;
             R.y = kRecEmpty;
@@ -549,7 +562,7 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
                 }
             }
         }
-        j += gridDim.x;
+        j = jn;
         if (j >= n) break;
         cur = nxt;
     }

@@ -88,8 +88,15 @@ constexpr uint64_t kRecEmpty = ~0ull;
 // through LDS.
 constexpr uint32_t kRecChunk = 4096;
 
-// Kernel arguments (fixed for the life of a plan).
+// Kernel arguments (fixed for the life of a plan but for n_rec and out).
 struct BatchArgs {
+    // Chunked kernel: its record array and, set for each batch (the plan
+    // updates its graph node's arguments with the grid), the record count and
+    // the output; record and count lead, so one scalar load fetches both.
+    RowRec* rec;            // row records (device workspace; interleaved kernels too)
+    uint64_t n_rec;
+    uint64_t* out;
+    RowRec* ext;            // chunked, owned mode: each window's first-chunk record
     const BatchHeader* ws;  // device workspace
     uint32_t cluster;       // workgroups sharing a row range (both batch kernels)
     Mult JB;                // (2^53)^(2*block*cluster): the next row of a lane
@@ -98,14 +105,6 @@ struct BatchArgs {
     const Mult* t_lo;
     const Mult* t_hi;
     const Mult* t_sk;       // kSkipLevels * kSkipSize entries
-    // Interleaved and chunked kernels only:
-    RowRec* rec;            // row records (device workspace)
-    RowRec* ext;            // chunked, owned mode: each window's first-chunk record
-    // Chunked kernel only, set for each batch (the plan updates its graph
-    // node's arguments with the grid): the record count and the output, so
-    // a workgroup's start waits on its record load alone.
-    uint64_t n_rec;
-    uint64_t* out;
     Mult JR;                // (2^53)^(row_outs*256): a pre-pass thread's next row
     uint32_t grid;          // workgroups of the row kernel
     uint32_t block;         // threads per workgroup of the row kernel
@@ -128,6 +127,11 @@ const void* batch_rows_kernel(int kind, bool nontemporal);
 // layout's chunks (a fixed grid takes the records round-robin instead).
 constexpr uint32_t kChunkRows = 4;
 constexpr uint32_t kChunkOuts = kChunkRows * 512;
+// The chunked kernel's multipliers in a static device array of its module:
+// (2^53)^k for k < 2*kFlatBlock (a lane's pair), then (2^53)^kFlatPerBlock
+// (one row).  Filled per device at set-up.
+constexpr uint32_t kChunkSymEntries = 2 * kFlatBlock + 1;
+hipError_t upload_chunk_symbol(const Mult* entries);
 // Records of the chunked kernel are stored XCD-major: record j at
 // (j mod kChunkRecWays) * per + j / kChunkRecWays, per = ceil(n / kChunkRecWays).
 // Workgroups are dealt to the 8 XCDs round-robin by index, so the records

@@ -478,6 +478,7 @@ int nn_batch_plan_cfg(const nn_batch_plan* plan, nn_batch_cfg* cfg_out) {
                      (plan->use_graph ? 0u : NN_BATCH_NO_GRAPH) |
                      (plan->interleaved ? NN_BATCH_INTERLEAVED : 0u) |
                      (plan->chunks ? NN_BATCH_CHUNKS : 0u);
+    cfg_out->occupancy = plan->chunks ? plan->occupancy : 0u;
     return ok();
 }
 

@@ -81,7 +81,8 @@ struct nn_batch_plan {
     const uint64_t* host_states = nullptr;  // indexed plans: host copy of the state table
     const nn::Mult* tabs = nullptr;         // the device tables
     nn::Mult M1, J512;                      // 2^53 and (2^53)^512
-    uint32_t flat_lds = 0;                  // residency cap of the flat layout
+    uint32_t occupancy = 0;                 // chunk kernel: resident workgroups per CU
+    uint32_t flat_lds = 0;                  // its residency cap as dynamic LDS
     nn_batch_slot slot[2];
     int next = 0;  // the slot of the next batch
 };

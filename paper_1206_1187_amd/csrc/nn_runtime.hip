@@ -180,9 +180,13 @@ int ensure_device_current(int dev, DeviceTables** out) {
             for (uint32_t l = 0; l < kFlatBlock; ++l) sym[kFlatSymLane + l] = h[2u * l];
             std::copy(hb.begin(), hb.end(), sym.begin() + kFlatSymLo);
             e = upload_flat_symbol(sym.data());
+            // the chunked batch kernel's: t_lo's first 2*kFlatBlock entries, one row's step
+            std::vector<Mult> cs(h.begin(), h.begin() + 2 * kFlatBlock);
+            cs.push_back(make_mult(MultPowers::get().pow(kFlatPerBlock)));
+            if (e == hipSuccess) e = upload_chunk_symbol(cs.data());
             if (e != hipSuccess) {
                 (void)hipFree(mem);
-                return fail(NN_EHIP, "flat table upload: %s", hipGetErrorString(e));
+                return fail(NN_EHIP, "static table upload: %s", hipGetErrorString(e));
             }
         }
         void* ws = nullptr;
@@ -321,7 +325,7 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     if (!plan_out) return fail(NN_EINVAL, "plan_out is NULL");
     if (kind != NN_OUT_U64 && kind != NN_OUT_F64) return fail(NN_EINVAL, "kind %d unknown", kind);
     if (max_streams == 0) return fail(NN_EINVAL, "max_streams must be positive");
-    nn_batch_cfg c = {0, 0, 0, 0, 0};
+    nn_batch_cfg c = {0, 0, 0, 0, 0, 0};
     if (cfg) c = *cfg;
     if (c.flags &
         ~(NN_CFG_TEMPORAL_STORES | NN_BATCH_NO_GRAPH | NN_BATCH_INTERLEAVED | NN_BATCH_CHUNKS))
@@ -333,6 +337,10 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
                    (c.mulmod && c.mulmod != NN_MULMOD_FP64)))
         return fail(NN_EINVAL, "the chunked batch kernel has 256 threads, no clusters and the "
                                "FP64 reduction");
+    if (c.occupancy && !chunks)
+        return fail(NN_EINVAL, "occupancy applies to the chunked batch kernel only");
+    if (c.occupancy && (c.occupancy < 2 || c.occupancy > 16))
+        return fail(NN_EINVAL, "occupancy %u: must be 0 or in [2, 16]", c.occupancy);
     DeviceTables* d = nullptr;
     int st = current_device(&d);
     if (st) return st;
@@ -390,7 +398,10 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->tabs = d->t_lo;
     p->M1 = make_mult(kMult);
     p->J512 = make_mult(MultPowers::get().pow(kFlatPerBlock));
-    p->flat_lds = (d->lds_per_cu / (kFlatDefaultOccupancy + 1) / 512 + 1) * 512;
+    // the chunk kernel's residency cap: dynamic LDS that leaves room for
+    // `occupancy` workgroups per compute unit, not one more
+    p->occupancy = c.occupancy ? c.occupancy : kFlatDefaultOccupancy;
+    p->flat_lds = (d->lds_per_cu / (p->occupancy + 1) / 512 + 1) * 512;
     if (p->flat_lds > d->lds_per_block) p->flat_lds = 0;
     for (nn_batch_slot& q : p->slot) {
         st = slot_create(p, q, *d, states);

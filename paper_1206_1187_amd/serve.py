@@ -44,7 +44,8 @@ class Server:
                          int(batch_kw.get("cluster", 0)), int(mulmod),
                          (_native.NN_CFG_TEMPORAL_STORES if batch_kw.get("temporal") else 0) |
                          (_native.NN_BATCH_INTERLEAVED if batch_kw.get("interleaved") else 0) |
-                         (_native.NN_BATCH_CHUNKS if batch_kw.get("chunks") else 0))
+                         (_native.NN_BATCH_CHUNKS if batch_kw.get("chunks") else 0),
+                         int(batch_kw.get("occupancy", 0)))
         self.pool_bytes = int(pool_bytes) & ~255
         self.pool = None
         pool_ptr = None

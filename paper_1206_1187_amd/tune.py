@@ -254,9 +254,12 @@ def tune_batch(kind, reps=5, log=print, workload=None):
                for k in (0, 8, 16, 32) for t in (False, True)]
     cands = [dict(shape, grid=grid) for shape, grid in itertools.product(shapes, grids)
              if not (shape["cluster"] and grid % shape["cluster"])]
-    # chunked kernel: one workgroup per 16 KiB chunk (grid 0), or persistent
+    # chunked kernel: one workgroup per 16 KiB chunk (grid 0) at residency
+    # caps around the plain flat layout's, or persistent
+    cands += [dict(mulmod="fp64", chunks=True, temporal=t, grid=0, occupancy=o)
+              for t in (False, True) for o in (3, 4, 5, 6, 8)]
     cands += [dict(mulmod="fp64", chunks=True, temporal=t, grid=g)
-              for t in (False, True) for g in (0, cus * 2, cus * 4)]
+              for t in (False, True) for g in (cus * 2, cus * 4)]
     for kw in cands:
         with nn.BatchPlan(kind, len(states), total, **kw) as plan:
             ms = _median_ms(lambda: plan.generate(states, lengths, offsets, out), reps)

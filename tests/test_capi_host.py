@@ -233,6 +233,20 @@ def test_generate_validation_before_device():
     assert lib.nn_fill(8, ctypes.c_void_p(aligned + 4), 0, None, None) == _native.NN_EINVAL
 
 
+def test_batch_plan_validation_before_device():
+    """Batch-plan configurations that are refused before any HIP call: the
+    residency cap belongs to the chunked kernel and lies in [2, 16]."""
+    lib = _native.lib()
+    h = ctypes.c_void_p()
+    for flags, occ in [(0, 4), (_native.NN_BATCH_INTERLEAVED, 4),
+                       (_native.NN_BATCH_CHUNKS, 1), (_native.NN_BATCH_CHUNKS, 17)]:
+        cfg = _native.BatchCfg(0, 0, 0, 0, flags, occ)
+        assert lib.nn_batch_plan_create(1, 8, 1 << 20, ctypes.byref(cfg),
+                                        ctypes.byref(h)) == _native.NN_EINVAL
+        assert b"occupancy" in lib.nn_last_error()
+        assert not h.value
+
+
 def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_native, "LIB_PATH", "/nonexistent/libnn.so")
     monkeypatch.setattr(_native, "_lib", None)

@@ -103,17 +103,21 @@ def test_chunked_batch_bit_exact_mixed_lengths(kind):
     several windows in one chunk, windows starting and ending inside chunks
     at both offset parities, gaps between windows; grids from one workgroup
     (every record on it) to more workgroups than records; graph and direct
-    launches; temporal and non-temporal stores."""
+    launches; temporal and non-temporal stores; residency caps from 2 to 16
+    workgroups per compute unit."""
     lengths = LENGTHS + [2047, 2048, 2049, 4095, 4096, 4097, 6143, 1, 2, 5, 3000, 1, 1]
     states, lengths, offsets, total = _mixed_batch(13, lengths)
     dt = torch.float64 if kind == "f64" else torch.uint64
-    for grid, graph, temporal in [(0, True, False), (1, True, False), (3, False, True),
-                                  (7, True, True), (1000, True, False), (4096, False, False)]:
-        _say("chunked", kind, grid, graph, temporal)
+    for grid, graph, temporal, occ in [(0, True, False, 0), (1, True, False, 0),
+                                       (3, False, True, 0), (7, True, True, 2),
+                                       (1000, True, False, 0), (4096, False, False, 0),
+                                       (0, True, True, 6), (0, False, False, 16)]:
+        _say("chunked", kind, grid, graph, temporal, occ)
         buf = _sentinel(total)
         with nn.BatchPlan(kind, 64, total, grid=grid, graph=graph, temporal=temporal,
-                          chunks=True) as plan:
+                          chunks=True, occupancy=occ) as plan:
             assert plan.cfg().flags & 32
+            assert plan.cfg().occupancy == (occ or 4)
             fin = plan.generate(states, lengths, offsets, buf.view(dt), final_states=True)
             torch.cuda.synchronize()
         _check_batch(_bits(buf), states, lengths, offsets, kind)
