@@ -76,8 +76,11 @@ typedef enum nn_mulmod {
  *    that sets none of block, grid, ilp or width 1): every 256-thread
  *    workgroup writes `unroll` rows of 512 consecutive outputs (one
  *    contiguous chunk), two per lane in one 16-byte store per row, and
- *    exits; workgroups are dispatched in address order (needs a 16-byte
- *    aligned output);
+ *    exits (needs a 16-byte aligned output).  With 4 rows the chunks are
+ *    taken in XCD runs: of every 2048 consecutive chunks, each of the 8
+ *    XCDs (which take consecutive workgroups in turn) writes 256
+ *    consecutive ones (4 MiB); chunks after the last full run, and every
+ *    chunk with other row counts, in address order;
  *  - rows (NN_CFG_ROWS; the default otherwise): grid*block threads loop
  *    over rows of width*grid*block outputs, stepping by a jump multiplier;
  *  - consecutive (NN_CFG_CONSECUTIVE): the paper's per-thread loop (Section
@@ -294,10 +297,10 @@ typedef struct nn_batch_cfg {
  * windows by output offset (they are independent) and gives each chunk one
  * record and one workgroup, which writes every window's part of it; windows
  * that overlap each other get a record per chunk and window instead.
- * grid 0 (the default): one workgroup per record, dispatched in output
- * order as the plain flat layout's chunks are (the plan's graph gets the
- * batch's record count as its grid before each replay); a nonzero grid:
- * that many persistent workgroups taking the records round-robin.  Needs
+ * grid 0 (the default): one workgroup per record, the records taken in
+ * the plain flat layout's XCD runs (the plan's graph gets the batch's
+ * record count as its grid before each replay); a nonzero grid: that many
+ * persistent workgroups taking the records round-robin in the same order.  Needs
  * the FP64 reduction, block 0 or 256, cluster 0 or 1 and output indices
  * below 2^51 (NN_ERANGE otherwise).  Exclusive with NN_BATCH_INTERLEAVED.
  * Batches of at most 16 windows travel in the kernel arguments (the FP64

@@ -455,16 +455,16 @@ __global__ __launch_bounds__(256) void k_batch_rows(BatchArgs a) {
 
 // Chunked kernel: the flat layout of the plain generator over a batch.  The
 // output is cut into aligned chunks of kChunkRows rows of 512 outputs
-// (16 KiB); the pre-pass (k_batch_rec with one cluster of kChunkRecWays
-// workgroups and rows of kChunkOuts outputs) writes one record per chunk and
-// window that meet, record j (in window order) XCD-major at
-// (j mod kChunkRecWays) * per + j / kChunkRecWays: the state of the chunk's element 0 as if the
-// window covered it, the chunk's output index and the window's part of the
-// chunk [lo, hi).  Workgroup w of the grid takes records w, w + grid, ...:
-// with one workgroup per record (the default) the dispatcher hands chunks
-// out in output order and the write front stays as compact as the plain
-// flat layout's; a smaller, persistent grid loads the next record while it
-// writes the current one.  Lane l's outputs of a chunk are its pairs
+// (16 KiB); the pre-pass (k_batch_rec with one cluster of one workgroup and
+// rows of kChunkOuts outputs) writes one record per chunk and window that
+// meet, record j (in window order) at j: the state of the chunk's element 0
+// as if the window covered it, the chunk's output index and the window's
+// part of the chunk [lo, hi).  Workgroup w of the grid takes the virtual
+// indices w, w + grid, ..., and index v the record xcd_run_index(v) while v
+// lies in a whole XCD run, v after the last one: with one workgroup per
+// record (the default) the dispatcher hands the chunks out in the plain flat
+// layout's order (each XCD 4 MiB of consecutive chunks per run); a smaller,
+// persistent grid loads the next record while it writes the current one.  Lane l's outputs of a chunk are its pairs
 // 2l, 2l + 1 of each row: states z * (2^53)^(2l) and z * (2^53)^(2l+1), one
 // multiplication each by the lane's fixed multipliers, then one step of
 // (2^53)^512 per row.  A chunk that one window covers is stored without a
@@ -486,8 +486,9 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     constexpr uint32_t C = kChunkOuts;
     const uint64_t n = a.n_rec;  // records (== hdr->n_rows)
     const const_ptr<u64x2> rec = reinterpret_cast<const_ptr<u64x2>>(as_const(a.rec));
-    const uint64_t per = (n + kChunkRecWays - 1) / kChunkRecWays;
-    auto at = [&](uint64_t i) { return (i % kChunkRecWays) * per + i / kChunkRecWays; };
+    constexpr uint64_t kRun = (uint64_t)kFlatXcds * kFlatXcdRun;
+    const uint64_t runs = n / kRun * kRun;  // records in whole XCD runs
+    auto at = [&](uint64_t v) { return v < runs ? xcd_run_index(v) : v; };
     const uint32_t l = threadIdx.x;
     uint64_t j = blockIdx.x;
     // Loads before tests: the multipliers (at a fixed address) and the

@@ -132,13 +132,13 @@ constexpr uint32_t kChunkOuts = kChunkRows * 512;
 // (one row).  Filled per device at set-up.
 constexpr uint32_t kChunkSymEntries = 2 * kFlatBlock + 1;
 hipError_t upload_chunk_symbol(const Mult* entries);
-// Records of the chunked kernel are stored XCD-major: record j at
-// (j mod kChunkRecWays) * per + j / kChunkRecWays, per = ceil(n / kChunkRecWays).
-// Workgroups are dealt to the 8 XCDs round-robin by index, so the records
-// one XCD's workgroups read are consecutive and share its L2's lines (one
-// miss per eight chunks).  The pre-pass writes this layout as one cluster of
-// kChunkRecWays workgroups.
-constexpr uint32_t kChunkRecWays = 8;
+// Records of the chunked kernel lie in record order (record j at j; the
+// pre-pass writes them as one cluster of one workgroup).  The kernel takes
+// them in the plain flat layout's XCD runs (xcd_run_index): in each run of
+// kFlatXcds*kFlatXcdRun workgroups, XCD x takes the kFlatXcdRun consecutive
+// records [x kFlatXcdRun, (x + 1) kFlatXcdRun) of the run, so one XCD's
+// records share its L2's lines and it writes 4 MiB of consecutive chunks;
+// records after the last full run go in workgroup order.
 // Record modes of the chunked kernel (BatchHeader::mode):
 //  * per record: a record per chunk and window that meet, one workgroup each
 //    (windows in any order; a chunk that windows share is written by
@@ -216,13 +216,10 @@ hipError_t launch_batch_flat_inline(int kind, bool nontemporal, uint32_t grid, u
 //   kStaticRecOff     chunk records (RowRec), written by k_batch_rec
 // A window of length L at output offset o has ceil((L + o mod kChunkOuts) /
 // kChunkOuts) < L / kChunkOuts + 2 records, so kStaticMaxStreams windows of
-// kStaticMaxOutputs outputs in all never need more than kStaticMaxRecords
-// (the XCD-major record layout reaches kChunkRecWays - 1 entries past the
-// record count).
+// kStaticMaxOutputs outputs in all never need more than kStaticMaxRecords.
 constexpr uint32_t kStaticMaxStreams = 1u << 16;
 constexpr uint64_t kStaticMaxOutputs = 1ull << 31;
-constexpr uint64_t kStaticMaxRecords =
-    kStaticMaxOutputs / kChunkOuts + 2ull * kStaticMaxStreams + kChunkRecWays;
+constexpr uint64_t kStaticMaxRecords = kStaticMaxOutputs / kChunkOuts + 2ull * kStaticMaxStreams;
 constexpr uint64_t static_align(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 constexpr uint64_t kStaticDescOff = sizeof(BatchHeader);
 constexpr uint64_t kStaticRawOff =

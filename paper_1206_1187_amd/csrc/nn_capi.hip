@@ -331,6 +331,7 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
             f.count = n;
             f.base = h_skip(s, off + 1);  // the first output of this chunk
             const uint64_t per = (uint64_t)kFlatPerBlock * r.unroll;
+            f.mid_base = h_skip(f.base, flat_run_chunks((int)r.unroll, n / per) * per);
             f.tail_base = h_skip(f.base, n / per * per);
             hipError_t e = launch_generate_flat((int)r.mulmod, kind, r.nontemporal, (int)r.unroll,
                                                 r.lds, (hipStream_t)stream, f);
@@ -581,7 +582,7 @@ int nn_generate_batch_static(const nn_stream_desc* descs, uint32_t n, void* out_
             for (uint32_t i = 0; i < n; ++i) final_states[i] = descs[i].state;
         return ok();
     }
-    if (records + kChunkRecWays > kStaticMaxRecords)  // cannot happen within the limits above
+    if (records > kStaticMaxRecords)  // cannot happen within the limits above
         return fail(NN_ERANGE, "batch of %llu chunk records", (unsigned long long)records);
     const hipStream_t s = (hipStream_t)stream;
     char* ws = static_cast<char*>(d->scratch);
@@ -600,8 +601,8 @@ int nn_generate_batch_static(const nn_stream_desc* descs, uint32_t n, void* out_
     a.t_sk = d->t_sk;
     a.rec = reinterpret_cast<RowRec*>(ws + kStaticRecOff);
     a.row_outs = kChunkOuts;
-    a.grid = kChunkRecWays;
-    a.cluster = kChunkRecWays;
+    a.grid = 1;
+    a.cluster = 1;
     a.block = kFlatBlock;
     a.JR = make_mult(MultPowers::get().pow((uint64_t)kChunkOuts * 256));
     a.n_rec = records;

@@ -40,6 +40,16 @@ __device__ __forceinline__ void flat_start(uint64_t b, uint32_t l, int R, uint64
     zb = V::mul(za, M1);
 }
 
+// XCD runs (see kFlatXcdRun): the chunk (or record) that workgroup w takes
+// when runs of kFlatXcds*kFlatXcdRun workgroups give XCD x = w mod kFlatXcds
+// the kFlatXcdRun consecutive ones [x kFlatXcdRun, (x + 1) kFlatXcdRun) of
+// its run.  A permutation of every whole run.
+__device__ __forceinline__ uint64_t xcd_run_index(uint64_t w) {
+    constexpr uint64_t run = (uint64_t)kFlatXcds * kFlatXcdRun;
+    const uint64_t r = w % run;
+    return w - r + (r % kFlatXcds) * kFlatXcdRun + r / kFlatXcds;
+}
+
 // The 64-bit pattern stored for a state: the state itself or its variate.
 template <class V, int KIND>
 __device__ __forceinline__ uint64_t out_bits(typename V::S z) {

@@ -283,9 +283,20 @@ hipError_t upload_flat_symbol(const Mult* entries) {
                              hipMemcpyHostToDevice);
 }
 
-// Flat layout (see launch_generate_flat).  Workgroup b writes the R rows of
-// kFlatPerBlock outputs from element kFlatPerBlock*R*b on, lane l the pair
-// 2l of each row, and exits.  Its start is two multiplications by uniform
+// The chunk that workgroup w writes: w itself (G = 0), or its XCD-run
+// chunk (G = kFlatXcdRun, in launches of whole runs).
+template <int G>
+__device__ __forceinline__ uint64_t flat_chunk(uint64_t w) {
+    static_assert(G == 0 || G == (int)kFlatXcdRun, "XCD runs of kFlatXcdRun chunks");
+    if constexpr (G == 0)
+        return w;
+    else
+        return xcd_run_index(w);
+}
+
+// Flat layout (see launch_generate_flat).  Workgroup w writes the R rows of
+// kFlatPerBlock outputs of chunk b = flat_chunk<G>(w), from element
+// kFlatPerBlock*R*b on, lane l the pair 2l of each row, and exits.  Its start is two multiplications by uniform
 // table entries (scalar loads that hit L2), then one by the lane's offset;
 // after that one multiplication per output.  Each row: its store, then the
 // two multiplications to the next.
@@ -296,13 +307,13 @@ hipError_t upload_flat_symbol(const Mult* entries) {
 // whole-chunk kernel takes no count and tests nothing, and the table
 // indices are in range for every lane.  A ragged last chunk goes to
 // k_generate_flat_tail.
-template <class V, int KIND, bool NT, int R>
+template <class V, int KIND, bool NT, int R, int G>
 __global__ __launch_bounds__(kFlatBlock) void k_generate_flat(uint64_t base,
                                                               uint64_t* __restrict__ out,
                                                               Mult M1, Mult J) {
     extern __shared__ char occupancy_cap[];  // dynamic LDS only limits residency
     (void)occupancy_cap;
-    const uint64_t b = blockIdx.x;
+    const uint64_t b = flat_chunk<G>(blockIdx.x);
     const uint32_t l = threadIdx.x;
     typename V::S za, zb;
     flat_start_sym<V>(b, l, R, base, M1, za, zb);
@@ -357,23 +368,23 @@ __global__ __launch_bounds__(kFlatBlock) void k_generate_flat_tail(uint64_t base
 // place of its multiplications, so the stores wait for the same loads:
 // the generator minus its arithmetic.  (The entries are positive, so the
 // comparison always keeps `value`.)
-template <bool NT, int R, bool START>
+template <bool NT, int R, bool START, int G>
 __global__ __launch_bounds__(kFlatBlock) void k_fill_flat(uint64_t* __restrict__ out,
                                                           uint64_t value) {
     extern __shared__ char occupancy_cap[];
     (void)occupancy_cap;
+    const uint64_t b = flat_chunk<G>(blockIdx.x);
     u64x2 v;
     v.x = value;
     if constexpr (START) {
-        const uint64_t u = (uint64_t)blockIdx.x * R;
+        const uint64_t u = b * R;
         const double hi = flat_sym[kFlatSymHi + u / kFlatLoSize].v;
         const double lo = flat_sym[kFlatSymLo + u % kFlatLoSize].v;
         const double lane = flat_sym[kFlatSymLane + threadIdx.x].v;
         v.x = hi + lo + lane > 0.0 ? value : 0;
     }
     v.y = v.x;
-    u64x2* p = reinterpret_cast<u64x2*>(out + (uint64_t)kFlatPerBlock * R * blockIdx.x +
-                                        2u * threadIdx.x);
+    u64x2* p = reinterpret_cast<u64x2*>(out + (uint64_t)kFlatPerBlock * R * b + 2u * threadIdx.x);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         put<NT>(p + r * kFlatBlock, v);
@@ -402,9 +413,21 @@ static hipError_t flat_one(uint32_t lds, hipStream_t s, const FlatArgs& a) {
     const uint64_t per = (uint64_t)kFlatPerBlock * R;
     const uint64_t full = a.count / per;  // whole chunks
     const uint64_t tail = a.count - full * per;
-    if (full) {
-        hipLaunchKernelGGL((k_generate_flat<V, KIND, NT, R>), dim3((uint32_t)full),
-                           dim3(kFlatBlock), lds, s, a.base, a.out, a.M1, a.J);
+    const uint64_t runs = flat_run_chunks(R, full);  // whole chunks in XCD runs
+    if constexpr (R == 4) {
+        if (runs) {
+            hipLaunchKernelGGL((k_generate_flat<V, KIND, NT, R, kFlatXcdRun>),
+                               dim3((uint32_t)runs), dim3(kFlatBlock), lds, s, a.base, a.out,
+                               a.M1, a.J);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (full > runs) {
+        // the whole chunks after the last run, in workgroup order from their own base
+        hipLaunchKernelGGL((k_generate_flat<V, KIND, NT, R, 0>), dim3((uint32_t)(full - runs)),
+                           dim3(kFlatBlock), lds, s, runs ? a.mid_base : a.base,
+                           a.out + runs * per, a.M1, a.J);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -448,20 +471,38 @@ hipError_t launch_generate_flat(int mulmod, int kind, bool nt, int rows, uint32_
     }
 }
 
+template <bool NT, int R, int G>
+static hipError_t fill_flat_launch(uint32_t grid, uint32_t lds, hipStream_t s, bool start,
+                                   uint64_t* out, uint64_t value) {
+    if (start)
+        hipLaunchKernelGGL((k_fill_flat<NT, R, true, G>), dim3(grid), dim3(kFlatBlock), lds, s,
+                           out, value);
+    else
+        hipLaunchKernelGGL((k_fill_flat<NT, R, false, G>), dim3(grid), dim3(kFlatBlock), lds, s,
+                           out, value);
+    return hipGetLastError();
+}
+
+// Whole chunks in the generator's order (XCD runs, then workgroup order),
+// then the tail.
 template <bool NT, int R>
 static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, bool start, uint64_t* out,
                                 uint64_t count, uint64_t value) {
     const uint64_t per = (uint64_t)kFlatPerBlock * R;
     const uint64_t full = count / per;
     const uint64_t tail = count - full * per;
-    if (full) {
-        if (start)
-            hipLaunchKernelGGL((k_fill_flat<NT, R, true>), dim3((uint32_t)full), dim3(kFlatBlock),
-                               lds, s, out, value);
-        else
-            hipLaunchKernelGGL((k_fill_flat<NT, R, false>), dim3((uint32_t)full),
-                               dim3(kFlatBlock), lds, s, out, value);
-        const hipError_t e = hipGetLastError();
+    const uint64_t runs = flat_run_chunks(R, full);
+    if constexpr (R == 4) {
+        if (runs) {
+            const hipError_t e =
+                fill_flat_launch<NT, R, kFlatXcdRun>((uint32_t)runs, lds, s, start, out, value);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (full > runs) {
+        // START: the table indices restart at the first chunk after the runs
+        const hipError_t e = fill_flat_launch<NT, R, 0>((uint32_t)(full - runs), lds, s, start,
+                                                        out + runs * per, value);
         if (e != hipSuccess) return e;
     }
     if (tail) {

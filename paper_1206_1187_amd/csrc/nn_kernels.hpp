@@ -87,10 +87,26 @@ constexpr uint32_t kFlatSymEntries = kFlatSymHi + kFlatHiSize;
 // Copies kFlatSymEntries entries into the current device's array.
 hipError_t upload_flat_symbol(const Mult* entries);
 
+// XCD runs: the 8 XCDs take consecutive workgroups in turn, so with chunks in
+// workgroup order each XCD writes every eighth 16 KiB chunk.  With four rows
+// per workgroup the whole chunks are taken in runs of 8*kFlatXcdRun
+// workgroups instead, in which XCD x writes the kFlatXcdRun consecutive
+// chunks [x kFlatXcdRun, (x + 1) kFlatXcdRun) of the run (4 MiB).  Whole
+// chunks beyond the last full run keep workgroup order (a launch of their
+// own from mid_base).
+constexpr uint32_t kFlatXcds = 8;
+constexpr uint32_t kFlatXcdRun = 256;
+// Whole chunks of a flat launch that go to the XCD-run kernel.
+inline uint64_t flat_run_chunks(int rows, uint64_t whole_chunks) {
+    const uint64_t run = (uint64_t)kFlatXcds * kFlatXcdRun;
+    return rows == 4 ? whole_chunks / run * run : 0;
+}
+
 struct FlatArgs {
     uint64_t* out;   // 16-byte aligned
     uint64_t count;  // <= kFlatMaxCount
     uint64_t base;   // state of out[0]
+    uint64_t mid_base;   // state of the first output after the XCD runs (flat_run_chunks)
     uint64_t tail_base;  // state of the first output of the partial last chunk, if any
     Mult M1;         // 2^53
     Mult J;          // (2^53)^kFlatPerBlock: the next row of a lane

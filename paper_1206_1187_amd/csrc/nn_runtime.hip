@@ -240,9 +240,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     q.ws_bytes = sizeof(BatchHeader) + (size_t)p->cap_desc * sizeof(BatchDesc);
     hipError_t e = hipMalloc(&q.ws_dev, q.ws_bytes);
     if (e == hipSuccess && (p->interleaved || p->chunks))  // grid * per <= rows + clusters + grid
-        // (XCD-major chunk records reach index kChunkRecWays * ceil(rows / kChunkRecWays) - 1)
-        e = hipMalloc((void**)&q.rec,
-                      (p->cap_rows + 2ull * p->grid + kChunkRecWays) * sizeof(RowRec));
+        e = hipMalloc((void**)&q.rec, (p->cap_rows + 2ull * p->grid) * sizeof(RowRec));
     if (e == hipSuccess && p->chunks)
         e = hipMalloc((void**)&q.ext, (size_t)p->cap_desc * sizeof(RowRec));
     if (e != hipSuccess)
@@ -270,11 +268,11 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     q.args.grid = p->grid;
     q.args.block = block;
     if (p->chunks) {
-        // the pre-pass writes chunk records XCD-major: rows of kChunkOuts
-        // outputs, one cluster of kChunkRecWays workgroups
+        // the pre-pass writes chunk records in record order: rows of
+        // kChunkOuts outputs, one cluster of one workgroup
         q.args.row_outs = kChunkOuts;
-        q.args.grid = kChunkRecWays;
-        q.args.cluster = kChunkRecWays;
+        q.args.grid = 1;
+        q.args.cluster = 1;
     }
     q.args.JR = make_mult(MultPowers::get().pow((uint64_t)q.args.row_outs * 256));
     if (!p->use_graph) return NN_OK;

@@ -125,6 +125,28 @@ def test_chunked_batch_bit_exact_mixed_lengths(kind):
             assert f == orc.skip(s, n)
 
 
+@pytest.mark.parametrize("kind", ["u64", "f64"])
+def test_chunked_batch_xcd_runs(kind):
+    """Batches of more records than one XCD run (2048 chunk records): the
+    chunk kernel takes whole runs XCD by XCD and the records after the last
+    run in workgroup order.  Long windows over several runs mixed with short
+    ones and windows sharing chunks; one workgroup per record and persistent
+    grids that wrap around the records; against the oracle."""
+    rng = np.random.default_rng(23)
+    lengths = [3 * 2048 * 2048 + 5, 1, 2047, 777_777, 2048 * 2048 - 3] + \
+        [int(x) for x in rng.integers(1, 5000, 40)] + [1_500_001, 9]
+    states, lengths, offsets, total = _mixed_batch(29, lengths)
+    dt = torch.float64 if kind == "f64" else torch.uint64
+    for grid, temporal in [(0, True), (0, False), (1000, True), (4099, True)]:
+        _say("chunked xcd runs", kind, grid, temporal, total)
+        buf = _sentinel(total)
+        with nn.BatchPlan(kind, 64, total, grid=grid, temporal=temporal, chunks=True) as plan:
+            plan.generate(states, lengths, offsets, buf.view(dt))
+            torch.cuda.synchronize()
+        _check_batch(_bits(buf), states, lengths, offsets, kind)
+        del buf
+
+
 def test_chunked_batch_dense_short_windows():
     """Thousands of windows of 1 to 40 outputs packed back to back, so most
     chunks hold dozens of windows (all written by the chunk's one workgroup

@@ -162,6 +162,28 @@ def test_flat_layout_bit_exact(variant):
             assert np.array_equal(got, ref_f.view(np.uint64)[:99_991]), (rows, temporal)
 
 
+@pytest.mark.parametrize("variant", ["fp64", "shoup"])
+def test_flat_xcd_runs_bit_exact(variant):
+    """Four-row flat launches take their whole chunks in XCD runs of 2048
+    chunks (4,194,304 outputs), then the chunks after the last run in
+    workgroup order from their own start, then the ragged tail: counts below,
+    at and past one run, runs plus leftover chunks plus a tail, both kinds,
+    against the oracle element by element."""
+    run = 2048 * 2048
+    z0 = orc.seed(wl.INDEX_MIN + 271828)
+    top = 3 * run + 2047 * 2048 + 2047
+    ref_u, _ = orc.gen(z0, top, "u64", threads=0)
+    ref_f, _ = orc.gen(z0, top, "f64", threads=0)
+    counts = (run - 2048, run - 1, run, run + 1, run + 2048, 2 * run + 7 * 2048 + 1234, top)
+    for count in counts:
+        for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+            cfg = nn.make_cfg(mulmod=variant, layout="flat", unroll=4, occupancy=4, temporal=True)
+            _say("flat xcd runs", variant, count, kind)
+            got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=512)
+            assert np.array_equal(got, ref.view(np.uint64)[:count]), (variant, count, kind)
+            assert zn == orc.skip(z0, count)
+
+
 def test_pick_plain_layout_returns_a_working_cfg():
     """tune.pick_plain_layout times the row and flat layouts and returns the
     faster; whichever it returns writes the oracle's values."""
@@ -264,6 +286,8 @@ def test_fill_ceiling_kernel_pattern():
     cfgs += [nn.make_cfg(layout="flat", unroll=rows, occupancy=occ, temporal=t)
              for rows, occ, t in [(0, 0, None), (1, 3, None), (4, 4, True), (16, 0, False)]]
     for cfg, count in itertools.product(cfgs, (1 << 20, 100_003, 2049, 3)):
+        if cfg is cfgs[6] and count == 1 << 20:
+            count = 2 * 2048 * 2048 + 3 * 2048 + 5  # XCD runs, leftover chunks, tail
         buf = _sentinel_buffer(count + 512)
         nn.fill(buf[256:256 + count], 0x3FF0000000000001, cfg=cfg)
         torch.cuda.synchronize()
