@@ -357,8 +357,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic_from_profile(),
-            "kernel": "k_generate_flat<VarFP64, 1, false, 4> (f64, flat: 4 rows of 512 per "
-                      "workgroup, temporal stores, residency cap 4)",
+            "kernel": "k_generate_flat<VarFP64, 1, false, 4, 256> (f64, flat: 4 rows of 512 per "
+                      "workgroup in XCD runs of 256 chunks, temporal stores, residency cap 4)",
             "algorithmic_bytes_per_launch": 8 * case.count_f64,
         },
     }
