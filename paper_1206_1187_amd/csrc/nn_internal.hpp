@@ -60,7 +60,8 @@ struct nn_batch_slot {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t main_node = nullptr;  // the batch kernel's node
     uint32_t main_grid = 0;              // its grid as last set (chunked kernel, set per batch)
-    hipGraphNode_t rec_node = nullptr;   // the record pre-pass's node (interleaved, chunked)
+    hipGraphNode_t rec_node = nullptr;   // the record pre-pass's node (interleaved, indexed chunked)
+    hipEvent_t ready = nullptr;          // overlapped plans: this slot's upload and pre-pass done
     uint32_t rec_grid = 0;               // its grid as last set (one workgroup per window)
     nn::BatchArgs args;
 };
@@ -72,6 +73,13 @@ struct nn_batch_plan {
     bool indexed = false;
     uint32_t mulmod = 0, block = 0, grid = 0, cluster = 1;
     bool nontemporal = true, use_graph = true, interleaved = false, chunks = false;
+    // Chunked plans of nn_generate_batch: each batch's descriptor upload and
+    // record pre-pass run on `side`, so they overlap the previous batch's
+    // chunk kernel; the caller's stream waits for them (event `ready` of the
+    // slot) and runs the chunk kernel.  They touch only the slot's own
+    // workspace, which the host has seen free (plan_wait) before reuse.
+    bool overlap = false;
+    hipStream_t side = nullptr;
     uint64_t cap_rows = 0;
     uint32_t map_grid = 0;
     uint32_t max_streams = 0;

@@ -217,11 +217,13 @@ int current_device(DeviceTables** out) {
 // ---------------------------------------------------------------- plans --
 
 void plan_release(nn_batch_plan* p) {
+    if (p->side) (void)hipStreamSynchronize(p->side);
     for (nn_batch_slot& q : p->slot) {
         if (q.done) {
             (void)hipEventSynchronize(q.done);
             (void)hipEventDestroy(q.done);
         }
+        if (q.ready) (void)hipEventDestroy(q.ready);
         if (q.exec) (void)hipGraphExecDestroy(q.exec);
         if (q.graph) (void)hipGraphDestroy(q.graph);
         if (q.ws_dev) (void)hipFree(q.ws_dev);
@@ -229,6 +231,7 @@ void plan_release(nn_batch_plan* p) {
         if (q.ext) (void)hipFree(q.ext);
         if (q.ws_host) (void)hipHostFree(q.ws_host);
     }
+    if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
 }
 
@@ -252,6 +255,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     memset(hdr, 0, sizeof *hdr);
     hdr->states = states;
     e = hipEventCreateWithFlags(&q.done, hipEventDisableTiming);
+    if (e == hipSuccess && p->overlap) e = hipEventCreateWithFlags(&q.ready, hipEventDisableTiming);
     if (e != hipSuccess) return fail(NN_EHIP, "event: %s", hipGetErrorString(e));
     const uint32_t block = p->block, cluster = p->cluster;
     q.args.ws = (const BatchHeader*)q.ws_dev;
@@ -282,7 +286,7 @@ int slot_create(nn_batch_plan* p, nn_batch_slot& q, const DeviceTables& d,
     e = hipGraphCreate(&q.graph, 0);
     hipGraphNode_t last = nullptr;
     void* params[] = {&q.args};
-    if (e == hipSuccess && (p->interleaved || p->chunks)) {
+    if (e == hipSuccess && (p->interleaved || p->chunks) && !p->overlap) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
         kp.func = const_cast<void*>(batch_rec_kernel(p->indexed));
@@ -380,6 +384,7 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->use_graph = !(c.flags & NN_BATCH_NO_GRAPH);
     p->interleaved = (c.flags & NN_BATCH_INTERLEAVED) != 0;
     p->chunks = chunks;
+    p->overlap = chunks && !indexed;
     if (p->interleaved &&
         (mulmod != NN_MULMOD_FP64 || (block & (block - 1)) || block > 256)) {
         plan_release(p);
@@ -401,6 +406,14 @@ int plan_create(int kind, uint32_t max_streams, uint64_t max_outputs, const nn_b
     p->occupancy = c.occupancy ? c.occupancy : kFlatDefaultOccupancy;
     p->flat_lds = (d->lds_per_cu / (p->occupancy + 1) / 512 + 1) * 512;
     if (p->flat_lds > d->lds_per_block) p->flat_lds = 0;
+    if (p->overlap) {
+        // default priority; non-blocking, so it does not wait for the null stream
+        hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            plan_release(p);
+            return fail(NN_EHIP, "batch side stream: %s", hipGetErrorString(e));
+        }
+    }
     for (nn_batch_slot& q : p->slot) {
         st = slot_create(p, q, *d, states);
         if (st) {
@@ -548,7 +561,9 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         p->next ^= 1;
         return NN_OK;
     }
-    e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, stream);
+    // overlapped plans upload and run the pre-pass on the side stream
+    const hipStream_t up = p->overlap ? p->side : stream;
+    e = hipMemcpyAsync(q.ws_dev, q.ws_host, bytes, hipMemcpyHostToDevice, up);
     // the chunked kernel's workgroups: one per record unless the plan fixed a grid;
     // its arguments carry the record count and the output
     const uint32_t chunk_grid = p->grid ? p->grid : (uint32_t)rows;
@@ -557,6 +572,14 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
     // the record pre-pass: a workgroup per window (the window's skip-ahead is
     // its one long dependent chain), at least one
     const uint32_t rec_grid = nd < 1 ? 1u : nd > 65535 ? 65535u : nd;
+    if (e == hipSuccess && p->overlap) {
+        BatchArgs copy = q.args;
+        void* params[] = {&copy};
+        e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(rec_grid), dim3(256), params, 0,
+                            p->side);
+        if (e == hipSuccess) e = hipEventRecord(q.ready, p->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, q.ready, 0);
+    }
     if (e == hipSuccess && p->use_graph && q.rec_node && rec_grid != q.rec_grid) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
@@ -586,8 +609,9 @@ int plan_launch_staged(nn_batch_plan* p, uint32_t nd, void* out, hipStream_t str
         BatchArgs copy = q.args;
         void* params[] = {&copy};
         if (p->interleaved || p->chunks) {
-            e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(rec_grid), dim3(256),
-                                params, 0, stream);
+            if (!p->overlap)
+                e = hipLaunchKernel(batch_rec_kernel(p->indexed), dim3(rec_grid), dim3(256),
+                                    params, 0, stream);
             if (e == hipSuccess && p->chunks)
                 e = hipLaunchKernel(batch_chunks_kernel(p->kind, p->nontemporal),
                                     dim3(chunk_grid), dim3(kFlatBlock), params, p->flat_lds,

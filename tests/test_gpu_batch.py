@@ -147,6 +147,28 @@ def test_chunked_batch_xcd_runs(kind):
         del buf
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_chunked_batches_back_to_back(graph):
+    """A chunked plan uploads each batch and runs its record pre-pass on a
+    side stream, overlapping the previous batch's chunk kernel: six batches
+    with different windows (both slots reused twice over, small batches that
+    travel in the kernel arguments between them) enqueued back to back on
+    one stream into separate outputs, with no host synchronization between
+    them; every output against the oracle."""
+    specs = [(31, [2048 * 2048 * 2 + 17, 5, 70_001, 4097]), (32, [3, 1, 2]),
+             (33, [1_000_003, 2048 * 1500, 1, 64]), (34, [2047, 2049] * 20),
+             (35, [12345]), (36, [2048 * 2048 * 3 + 1])]
+    batches = [_mixed_batch(seed, lengths) for seed, lengths in specs]
+    cap = max(b[3] for b in batches)
+    bufs = [_sentinel(b[3]) for b in batches]
+    with nn.BatchPlan("f64", 64, cap, graph=graph, chunks=True) as plan:
+        for (states, lengths, offsets, total), buf in zip(batches, bufs):
+            plan.generate(states, lengths, offsets, buf.view(torch.float64))
+        torch.cuda.synchronize()
+    for (states, lengths, offsets, total), buf in zip(batches, bufs):
+        _check_batch(_bits(buf), states, lengths, offsets, "f64")
+
+
 def test_chunked_batch_dense_short_windows():
     """Thousands of windows of 1 to 40 outputs packed back to back, so most
     chunks hold dozens of windows (all written by the chunk's one workgroup
