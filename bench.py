@@ -455,8 +455,8 @@ def main():
             shoot["modbarrett_paper_strided_%s_GBps" % kind] = 8.0 * out.numel() / s / 1e9
         extras["mulmod_shootout_default_shape"] = shoot
         # Section 2's larger modulus 3^40: the library default (FP64 step on
-        # base-3^20 limbs; the flat layout with 8 rows per chunk for f64, the
-        # row layout for u64), both layouts explicitly, and the Montgomery step.
+        # base-3^20 limbs, the flat layout with 16 rows per chunk in XCD runs),
+        # the flat layout with 8 rows, the row layout and the Montgomery step.
         # Every configuration is run once before any is timed, then the
         # configurations are timed in turn over two rounds (the best round
         # counts): the first 3^40 launches of a process ran several per cent

@@ -95,6 +95,15 @@ constexpr int kMaxDev = 64;
 std::mutex g_mu;
 Mult40* g_tab[kMaxDev];  // kLo + kHi + kFLo + kFHi entries per device
 
+// The FP64 step's flat-layout multipliers as limbs, in a static device array
+// of this module: the lane offsets (2^53)^k for k < 512, then t_flo and
+// t_fhi.  Its address is a constant of the code, so a workgroup's table
+// loads go out at its start.  Filled per device with the tables.
+constexpr uint32_t kSymLo = 512;
+constexpr uint32_t kSymHi = kSymLo + kFLo;
+constexpr uint32_t kSymEntries = kSymHi + kFHi;
+__device__ Mult40L e40_sym[kSymEntries];
+
 int device_tables(const Mult40** out) {
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
@@ -126,6 +135,14 @@ int device_tables(const Mult40** out) {
         e = hipMalloc(&mem, host.size() * sizeof(Mult40));
         if (e != hipSuccess) return fail(NN_ENOMEM, "hipMalloc e40 tables: %s", hipGetErrorString(e));
         e = hipMemcpy(mem, host.data(), host.size() * sizeof(Mult40), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            const Mult40L* limbs = reinterpret_cast<const Mult40L*>(host.data() + kTabEntries);
+            std::vector<Mult40L> sym(limbs, limbs + kSymLo);  // t_lo's first 512
+            sym.insert(sym.end(), limbs + kFLoOff, limbs + kFLoOff + kFLo);
+            sym.insert(sym.end(), limbs + kFHiOff, limbs + kFHiOff + kFHi);
+            e = hipMemcpyToSymbol(HIP_SYMBOL(e40_sym), sym.data(), sizeof(Mult40L) * kSymEntries,
+                                  0, hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) {
             (void)hipFree(mem);
             return fail(NN_EHIP, "e40 table upload: %s", hipGetErrorString(e));
@@ -275,23 +292,31 @@ struct E40FlatArgs {
     double base_lo, base_hi;  // base as base-B limbs
 };
 
-template <int KIND, int MM, int R, bool NT>
+// Workgroup w writes chunk w, then w + grid, ... (grid <= n_chunks, as the
+// host launches it), or with G > 0 (one workgroup per chunk over whole XCD
+// runs of kFlatXcds*G chunks) chunk x G + i of its run for the run's
+// workgroup kFlatXcds i + x, so XCD x writes G consecutive chunks (4 MiB).
+template <int KIND, int MM, int R, bool NT, int G>
 __global__ __launch_bounds__(256) void k_e40_flat(E40FlatArgs a) {
     extern __shared__ char occupancy_cap[];
     (void)occupancy_cap;
     typedef Step<MM> St;
     typedef typename St::S S;
     uint64_t c = blockIdx.x;
-    if (c >= a.n_chunks) return;
+    if constexpr (G > 0) {
+        constexpr uint64_t run = (uint64_t)kFlatXcds * G;
+        const uint64_t r = c % run;
+        c = c - r + (r % kFlatXcds) * G + r / kFlatXcds;
+    }
     const uint32_t l = threadIdx.x;
     const uint64_t u = c * R;
     S za, zb;
     if constexpr (MM == 1) {
         // in limbs throughout: the chunk's two row multipliers, then the
-        // lane's two offsets (all four loads independent), no Montgomery
-        const Mult40L* lt = reinterpret_cast<const Mult40L*>(a.tabs + kTabEntries);
-        const Mult40L hi = lt[kFHiOff + u / kFLo], lo = lt[kFLoOff + u % kFLo];
-        const Mult40L la = lt[2u * l], lb = lt[2u * l + 1];
+        // lane's two offsets (all four loads independent, from e40_sym), no
+        // Montgomery
+        const Mult40L hi = e40_sym[kSymHi + u / kFLo], lo = e40_sym[kSymLo + u % kFLo];
+        const Mult40L la = e40_sym[2u * l], lb = e40_sym[2u * l + 1];
         const L2 S0 = mul40l(mul40l(L2{a.base_lo, a.base_hi}, hi), lo);
         za = mul40l(S0, la);
         zb = mul40l(S0, lb);
@@ -351,13 +376,43 @@ __global__ __launch_bounds__(256) void k_e40_flat_tail(E40FlatArgs a, uint64_t c
     }
 }
 
+// XCD runs of 4 MiB: chunks of 512 R outputs per XCD run.
+template <int R>
+constexpr int kE40Run = 1024 / R;
+
+// Whole chunks of a launch of one workgroup per chunk that go to the
+// XCD-run kernel.
+inline uint64_t e40_run_chunks(int rows, uint64_t n_chunks) {
+    const uint64_t run = (uint64_t)kFlatXcds * (1024 / rows);
+    return n_chunks / run * run;
+}
+
+// a: the whole chunks (grid workgroups; grid == a.n_chunks: one per chunk,
+// then mid takes the chunks after the XCD runs, mid.n_chunks of them, from
+// its own base); tail: the partial last chunk.
 template <int KIND, int MM, int R, bool NT>
 hipError_t flat_launch(uint32_t grid, uint32_t lds, hipStream_t s, const E40FlatArgs& a,
-                       const E40FlatArgs& tail, uint64_t tail_count) {
+                       const E40FlatArgs& mid, const E40FlatArgs& tail, uint64_t tail_count) {
     if (a.n_chunks) {
-        k_e40_flat<KIND, MM, R, NT><<<grid, 256, lds, s>>>(a);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (grid == a.n_chunks && MM == 1) {
+            const uint64_t runs = e40_run_chunks(R, a.n_chunks);
+            if (runs) {
+                E40FlatArgs r = a;
+                r.n_chunks = runs;
+                k_e40_flat<KIND, MM, R, NT, kE40Run<R>><<<(uint32_t)runs, 256, lds, s>>>(r);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+            if (mid.n_chunks) {
+                k_e40_flat<KIND, MM, R, NT, 0><<<(uint32_t)mid.n_chunks, 256, lds, s>>>(mid);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+        } else {
+            k_e40_flat<KIND, MM, R, NT, 0><<<grid, 256, lds, s>>>(a);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     if (tail_count) {
         k_e40_flat_tail<KIND, MM, R, NT><<<1, 256, 0, s>>>(tail, tail_count);
@@ -368,22 +423,23 @@ hipError_t flat_launch(uint32_t grid, uint32_t lds, hipStream_t s, const E40Flat
 
 template <int KIND, int MM, bool NT>
 hipError_t flat_r(int rows, uint32_t grid, uint32_t lds, hipStream_t s, const E40FlatArgs& a,
-                  const E40FlatArgs& tail, uint64_t tail_count) {
+                  const E40FlatArgs& mid, const E40FlatArgs& tail, uint64_t tail_count) {
     switch (rows) {
-        case 2: return flat_launch<KIND, MM, 2, NT>(grid, lds, s, a, tail, tail_count);
-        case 4: return flat_launch<KIND, MM, 4, NT>(grid, lds, s, a, tail, tail_count);
-        case 8: return flat_launch<KIND, MM, 8, NT>(grid, lds, s, a, tail, tail_count);
-        case 16: return flat_launch<KIND, MM, 16, NT>(grid, lds, s, a, tail, tail_count);
+        case 2: return flat_launch<KIND, MM, 2, NT>(grid, lds, s, a, mid, tail, tail_count);
+        case 4: return flat_launch<KIND, MM, 4, NT>(grid, lds, s, a, mid, tail, tail_count);
+        case 8: return flat_launch<KIND, MM, 8, NT>(grid, lds, s, a, mid, tail, tail_count);
+        case 16: return flat_launch<KIND, MM, 16, NT>(grid, lds, s, a, mid, tail, tail_count);
+        case 32: return flat_launch<KIND, MM, 32, NT>(grid, lds, s, a, mid, tail, tail_count);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_flat(int kind, int mm, int rows, bool nt, uint32_t grid, uint32_t lds,
-                       hipStream_t s, const E40FlatArgs& a, const E40FlatArgs& tail,
-                       uint64_t tail_count) {
+                       hipStream_t s, const E40FlatArgs& a, const E40FlatArgs& mid,
+                       const E40FlatArgs& tail, uint64_t tail_count) {
 #define NN_E40_FLAT(K, M)                                                          \
-    return nt ? flat_r<K, M, true>(rows, grid, lds, s, a, tail, tail_count)         \
-              : flat_r<K, M, false>(rows, grid, lds, s, a, tail, tail_count);
+    return nt ? flat_r<K, M, true>(rows, grid, lds, s, a, mid, tail, tail_count)    \
+              : flat_r<K, M, false>(rows, grid, lds, s, a, mid, tail, tail_count);
     if (kind == 0) {
         if (mm) { NN_E40_FLAT(0, 1) } else { NN_E40_FLAT(0, 0) }
     }
@@ -436,17 +492,19 @@ hipError_t launch(int kind, int mm, int ilp, int unroll, bool nt, uint32_t grid,
 
 }  // namespace
 
-// The library's default layout at modulus 3^40 for a 16-byte aligned f64
-// output with the FP64 step: the flat one, 8 rows of 512 per chunk, since
-// its start moved into the limb domain (2^30 f64 outputs, one MI355X:
-// 5.84-5.87 TB/s against 5.49-5.59 for the row layout; 4 rows 5.73; caps 3
-// to 5 within 1 %).  Raw u64 states keep the row layout (6.19 against 6.08).
-constexpr bool kDefaultFlatF64 = true;
-constexpr uint32_t kE40FlatDefaultRows = 8;
+// The library's default layout at modulus 3^40 for a 16-byte aligned
+// output with the FP64 step: the flat one, 16 rows of 512 per chunk, in XCD
+// runs, its multipliers at a fixed address (2^30 f64 / 2^28 u64 outputs, one
+// MI355X, medians of four interleaved rounds: f64 6.21-6.30 TB/s at caps 3-5
+// against 5.98-6.11 with 8 rows, 5.81-5.96 with 32 rows and 6.12 for the row
+// layout; u64 6.28-6.36 against 6.10-6.21 with 8 rows and 6.05 for the row
+// layout).  The step is VALU-bound, so the longer chunk pays: a lane's
+// start (four limb products) is spread over 32 outputs.
+constexpr uint32_t kE40FlatDefaultRows = 16;
 
 // nn_e40_generate_ex's flat layout (arguments already validated: a valid
 // state, count > 0, an in-range pointer).  cfg: unroll = rows of 512
-// outputs per chunk (2, 4, 8, 16; default 8), grid = workgroups per launch
+// outputs per chunk (2, 4, 8, 16, 32; default 16), grid = workgroups per launch
 // (0: one per chunk), occupancy = residency cap (0: 4), store policy
 // (default temporal).
 int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void* stream,
@@ -456,8 +514,8 @@ int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void
     if ((c.block && c.block != 256) || c.ilp > 1)
         return fail(NN_EINVAL, "the flat layout has 256 threads per workgroup and no ilp");
     const uint32_t rows = c.unroll ? c.unroll : kE40FlatDefaultRows;
-    if (rows != 2 && rows != 4 && rows != 8 && rows != 16)
-        return fail(NN_EINVAL, "unroll %u: the flat layout writes 2, 4, 8 or 16 rows per chunk",
+    if (rows != 2 && rows != 4 && rows != 8 && rows != 16 && rows != 32)
+        return fail(NN_EINVAL, "unroll %u: the flat layout writes 2, 4, 8, 16 or 32 rows per chunk",
                     rows);
     const Mult40* tab = nullptr;
     int st = device_tables(&tab);
@@ -493,12 +551,24 @@ int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void
             a.JN = make_mult40(Powers::get().pow(per * grid - 512ull * (rows - 1)));
             a.JNL = make_mult40l(a.JN.v);
         }
+        // one workgroup per chunk with the FP64 step: XCD runs, then the
+        // chunks after the last run from their own base
+        E40FlatArgs m = a;
+        m.n_chunks = 0;
+        if (a.n_chunks && grid == a.n_chunks && mm == 1) {
+            const uint64_t runs = e40_run_chunks((int)rows, a.n_chunks);
+            m.n_chunks = a.n_chunks - runs;
+            m.out = a.out + runs * per;
+            m.base = h_mul(a.base, Powers::get().pow(runs * per));
+            m.base_lo = (double)(m.base % kLimb);
+            m.base_hi = (double)(m.base / kLimb);
+        }
         E40FlatArgs t = a;
         const uint64_t tail = n - a.n_chunks * per;
         t.out = a.out + a.n_chunks * per;
         t.base = h_mul(a.base, Powers::get().pow(a.n_chunks * per));
         const hipError_t e = launch_flat(kind, mm, (int)rows, nt, grid, lds, (hipStream_t)stream,
-                                         a, t, tail);
+                                         a, m, t, tail);
         if (e != hipSuccess) return fail(NN_EHIP, "e40 launch: %s", hipGetErrorString(e));
     }
     *state = h_mul(s, Powers::get().pow(count));
@@ -556,11 +626,10 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
         return fail(NN_EINVAL, "NN_CFG_TEMPORAL_STORES and NN_CFG_NONTEMPORAL_STORES are exclusive");
     const int mm = c.mulmod == NN_MULMOD_MONTGOMERY ? 0 : 1;
     const bool aligned16 = ((uintptr_t)out_dev % 16) == 0;
-    // No layout flag: the flat layout for a 16-byte aligned f64 output with
-    // the FP64 step unless the cfg sets a row-layout field (block, ilp).
+    // No layout flag: the flat layout for a 16-byte aligned output with the
+    // FP64 step unless the cfg sets a row-layout field (block, ilp).
     const bool flat = (c.flags & NN_CFG_FLAT) ||
-                      (!(c.flags & NN_CFG_ROWS) && aligned16 && kind == NN_OUT_F64 && mm == 1 &&
-                       e40::kDefaultFlatF64 && !c.block && !c.ilp);
+                      (!(c.flags & NN_CFG_ROWS) && aligned16 && mm == 1 && !c.block && !c.ilp);
     if (flat) return e40::generate_flat(state, count, out_dev, kind, stream, c, mm);
     if (c.occupancy) return fail(NN_EINVAL, "occupancy applies to the flat layout only");
     const uint32_t block = c.block ? c.block : 256u;

@@ -70,7 +70,7 @@ def test_e40_bit_exact_shapes_and_tails():
 
 @pytest.mark.parametrize("mulmod", ["fp64", "montgomery"])
 def test_e40_flat_layout_bit_exact(mulmod):
-    """The flat layout at modulus 3^40: 2 to 16 rows of 512 outputs per
+    """The flat layout at modulus 3^40: 2 to 32 rows of 512 outputs per
     chunk, one workgroup per chunk or a smaller grid whose workgroups step
     from chunk to chunk (1, 3 and 7 workgroups), residency caps, both store
     policies, ragged tails around the row and chunk sizes, both kinds."""
@@ -81,7 +81,7 @@ def test_e40_flat_layout_bit_exact(mulmod):
               99_991, 300_000)
     for rows, grid, occ, temporal in [(0, 0, 0, None), (2, 0, 3, None), (4, 1, 0, None),
                                       (4, 3, 0, False), (8, 7, 5, True), (16, 0, 0, False),
-                                      (16, 2, 2, None)]:
+                                      (16, 2, 2, None), (32, 0, 0, None), (32, 3, 4, True)]:
         cfg = nn.make_cfg(layout="flat", mulmod=mulmod, unroll=rows, grid=grid, occupancy=occ,
                           temporal=temporal)
         for count in counts:
@@ -95,6 +95,27 @@ def test_e40_flat_layout_bit_exact(mulmod):
     buf = torch.empty(4097, dtype=torch.float64, device="cuda")
     with pytest.raises(nn.NNError):
         nn.e40_generate_into(z0, buf[1:], cfg=nn.make_cfg(layout="flat"))
+
+
+def test_e40_flat_xcd_runs_bit_exact():
+    """With one workgroup per chunk the FP64 step's flat layout takes whole
+    XCD runs (4,194,304 outputs, at every row count) XCD by XCD, then the
+    chunks after the last run from their own base, then the tail: counts
+    below, at and past one and two runs, every row count, both kinds,
+    against the oracle element by element."""
+    run = 8 * 4 * 1024 * 1024 // 8
+    z0 = orc.e40_seed(orc.E40_INDEX_MIN + 4242)
+    top = 2 * run + 512 * 7 + 1
+    ref_u, _ = orc.e40_gen(z0, top, "u64")
+    ref_f, _ = orc.e40_gen(z0, top, "f64")
+    for rows in (2, 4, 8, 16, 32):
+        cfg = nn.make_cfg(layout="flat", mulmod="fp64", unroll=rows)
+        for count in (run - 1, run, run + 3 * 8192 + 5, top):
+            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                _say("e40 flat xcd runs", rows, count, kind)
+                got, zn = _gen_guarded(z0, count, kind, cfg=cfg)
+                assert np.array_equal(got, ref.view(np.uint64)[:count]), (rows, count, kind)
+                assert zn == orc.e40_skip(z0, count)
 
 
 def test_e40_flat_beyond_one_launch_sampled():
@@ -161,7 +182,7 @@ def test_e40_config_validation():
     out = torch.empty(4096, dtype=torch.float64, device="cuda")
     for cfg in [nn.make_cfg(width=1), nn.make_cfg(mulmod="barrett"),
                 nn.make_cfg(mulmod="shoup"), nn.make_cfg(layout="flat", unroll=3),
-                nn.make_cfg(layout="flat", unroll=32), nn.make_cfg(layout="flat", block=128),
+                nn.make_cfg(layout="flat", unroll=64), nn.make_cfg(layout="flat", block=128),
                 nn.make_cfg(layout="flat", occupancy=1), nn.make_cfg(layout="flat", ilp=2),
                 nn.make_cfg(layout="rows", unroll=8), nn.make_cfg(ilp=3), nn.make_cfg(block=100),
                 nn.make_cfg(layout="rows", occupancy=3), nn.make_cfg(grid=1 << 20, block=1024),

@@ -120,7 +120,7 @@ def test_bench_batched_launch_full_size_bit_exact():
 
 def test_e40_default_launch_full_size_bit_exact():
     """The 3^40 generator's default launch for 2^30 f64 outputs (the flat
-    layout, 8 rows per chunk, FP64 limb step), every output against the
+    layout, 16 rows per chunk in XCD runs, FP64 limb step), every output against the
     3^40 oracle: slices of 2^26 filled on host threads, each from the
     oracle's own skip-ahead."""
     n = 1 << 30
