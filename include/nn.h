@@ -72,11 +72,13 @@ typedef enum nn_mulmod {
 /* Launch configuration.  Any field left 0 takes the library default.
  *
  * Three layouts write the same values (serial order in memory):
- *  - flat (NN_CFG_FLAT; the default for a 16-byte aligned output and a cfg
- *    that sets none of block, grid, ilp or width 1): every 256-thread
- *    workgroup writes `unroll` rows of 512 consecutive outputs (one
- *    contiguous chunk), two per lane in one 16-byte store per row, and
- *    exits (needs a 16-byte aligned output).  With 4 rows the chunks are
+ *  - flat (NN_CFG_FLAT; the default for a cfg that sets none of block,
+ *    grid, ilp or width 1, nor width 2 on an output that is only 8-byte
+ *    aligned): every 256-thread workgroup writes `unroll` rows of 512
+ *    consecutive outputs (one contiguous chunk), two per lane in one
+ *    16-byte store per row, and exits; an output that is only 8-byte
+ *    aligned gets its first element from a one-workgroup launch and the
+ *    rest 16-byte aligned.  With 4 rows the chunks are
  *    taken in XCD runs: of every 2048 consecutive chunks, each of the 8
  *    XCDs (which take consecutive workgroups in turn) writes 256
  *    consecutive ones (4 MiB); chunks after the last full run, and every

@@ -129,13 +129,16 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     if (r->mulmod == NN_MULMOD_MODBARRETT)
         return fail(NN_EINVAL, "NN_MULMOD_MODBARRETT steps by 2^53 only: consecutive layout");
     if (r->mulmod > NN_MULMOD_MONTGOMERY) return fail(NN_EINVAL, "mulmod %u unknown", r->mulmod);
-    // No layout flag: the flat layout for a 16-byte aligned output unless the
-    // cfg sets a field only the row layout has (block, grid, ilp, width 1);
-    // it wrote faster than the row layout on every MI355X measured, for both
+    // No layout flag: the flat layout unless the cfg sets a field only the
+    // row layout has (block, grid, ilp, width 1; on an output that is only
+    // 8-byte aligned any width, which asks for the row layout's stores); it
+    // wrote faster than the row layout on every MI355X measured, for both
     // kinds (2^30 f64: 6.9 against 6.7 TB/s; 2^28 u64: 6.65 against 6.05).
+    // An output that is only 8-byte aligned gets its first element from a
+    // one-workgroup launch and the rest, 16-byte aligned, as usual.
     r->flat = (c.flags & NN_CFG_FLAT) != 0 ||
-              (!(c.flags & NN_CFG_ROWS) && aligned16 && !c.block && !c.grid && !c.ilp &&
-               (c.width == 0 || c.width == 2));
+              (!(c.flags & NN_CFG_ROWS) && !c.block && !c.grid && !c.ilp &&
+               (c.width == 0 || (c.width == 2 && aligned16)));
     r->occupancy = c.occupancy ? c.occupancy : (r->flat ? kFlatDefaultOccupancy : 0u);
     r->lds = 0;
     if (r->occupancy) {
@@ -147,8 +150,6 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
             return fail(NN_EINVAL, "occupancy %u not expressible on this device", r->occupancy);
     }
     if (r->flat) {
-        if (!aligned16)
-            return fail(NN_EINVAL, "the flat layout needs a 16-byte aligned output (got %p)", out);
         if ((c.block && c.block != kFlatBlock) || c.grid || (c.width && c.width != 2))
             return fail(NN_EINVAL, "the flat layout has a fixed shape (block 256, width 2)");
         if (c.ilp > 1) return fail(NN_EINVAL, "ilp applies to the row layout only");
@@ -325,7 +326,19 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
         FlatArgs f;
         f.M1 = make_mult(kMult);
         f.J = make_mult(MultPowers::get().pow(kFlatPerBlock));
-        for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
+        // an output that is only 8-byte aligned: its first element alone
+        // (the tail kernel with one output), then the 16-byte aligned rest
+        const uint64_t head = ((uintptr_t)out_dev % 16) ? 1 : 0;
+        if (head) {
+            f.out = (uint64_t*)out_dev;
+            f.count = 1;
+            f.base = f.mid_base = f.tail_base = h_skip(s, 1);
+            hipError_t e = launch_generate_flat((int)r.mulmod, kind, r.nontemporal, (int)r.unroll,
+                                                r.lds, (hipStream_t)stream, f);
+            if (e != hipSuccess)
+                return fail(NN_EHIP, "generate launch: %s", hipGetErrorString(e));
+        }
+        for (uint64_t off = head; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
             f.out = (uint64_t*)out_dev + off;
             f.count = n;
@@ -439,7 +452,15 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
     if (r.consec || r.strided) return fail(NN_EINVAL, "nn_fill has no consecutive layout");
     if (with_start && !r.flat) return fail(NN_EINVAL, "NN_FILL_WITH_START needs the flat layout");
     if (r.flat) {
-        for (uint64_t off = 0; off < count; off += kFlatMaxCount) {
+        // as nn_generate: an 8-byte aligned output's first element alone
+        const uint64_t head = ((uintptr_t)out_dev % 16) ? 1 : 0;
+        if (head) {
+            hipError_t e = launch_fill_flat(r.nontemporal, (int)r.unroll, r.lds,
+                                            (hipStream_t)stream, with_start, (uint64_t*)out_dev,
+                                            1, value);
+            if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
+        }
+        for (uint64_t off = head; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
             hipError_t e = launch_fill_flat(r.nontemporal, (int)r.unroll, r.lds,
                                             (hipStream_t)stream, with_start,

@@ -122,12 +122,32 @@ def test_thread_count_independence(block):
 
 
 def test_output_alignment():
-    """An output that is only 8-byte aligned takes 8-byte stores by default;
-    asking for 16-byte stores there is an error and writes nothing."""
+    """An output that is only 8-byte aligned takes the flat layout by
+    default, its first element from a one-workgroup launch and the rest
+    16-byte aligned (also explicitly, in both kinds, with ragged tails, past
+    the XCD runs, and for the fill); the row layout takes 8-byte stores
+    there, and asking it for 16-byte stores is an error that writes nothing."""
     z0 = orc.seed(wl.INDEX_MIN + 99)
     ref, zr = orc.gen(z0, 50_001, "u64", threads=0)
     got, zn = _gen_guarded(z0, 50_001, "u64", guard=4097)
     assert np.array_equal(got, ref) and zn == zr
+    big = 2 * 2048 * 2048 + 3 * 2048 + 3
+    ref_u, _ = orc.gen(z0, big, "u64", threads=0)
+    ref_f, _ = orc.gen(z0, big, "f64", threads=0)
+    for cfg in (None, nn.make_cfg(layout="flat"), nn.make_cfg(layout="flat", unroll=1),
+                nn.make_cfg(layout="rows")):
+        for count in (1, 2, 3, 2048, 2049, 4097, big):
+            for kind, r in (("u64", ref_u), ("f64", ref_f)):
+                got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=513)
+                assert np.array_equal(got, r.view(np.uint64)[:count]), (cfg, count, kind)
+                assert zn == orc.skip(z0, count)
+    for count in (1, 2, 4097, big):
+        buf = _sentinel_buffer(count + 2 * 513)
+        nn.fill(buf[513:513 + count], 0x3FF0000000000001, cfg=nn.make_cfg(layout="flat"))
+        torch.cuda.synchronize()
+        h = _bits(buf)
+        assert (h[:513] == SENTINEL).all() and (h[513 + count:] == SENTINEL).all()
+        assert (h[513:513 + count] == 0x3FF0000000000001).all()
     buf = _sentinel_buffer(50_001 + 2)
     with pytest.raises(nn.NNError):
         nn.generate_into(z0, buf[1:50_002].view(torch.uint64), cfg=nn.make_cfg(width=2))
@@ -199,9 +219,13 @@ def test_pick_plain_layout_returns_a_working_cfg():
     assert zn == orc.skip(z0, n)
     ref, _ = orc.gen(z0, 8192, "f64", threads=0)
     assert np.array_equal(_bits(out)[:8192], ref.view(np.uint64))
-    # an output that is only 8-byte aligned keeps the row layout
-    cfg2, times2 = tune.pick_plain_layout(rows, out[1:], z0)
-    assert times2 == {} and not (cfg2.flags & nn._native.NN_CFG_FLAT)
+    # an output that is only 8-byte aligned: both layouts are timed there too
+    cfg2, times2 = tune.pick_plain_layout(rows, out[1:], z0, rounds=1, reps=2)
+    assert set(times2) == {"rows", "flat"}
+    zn = nn.generate_into(z0, out[1:], cfg=cfg2)
+    torch.cuda.synchronize()
+    assert zn == orc.skip(z0, n - 1)
+    assert np.array_equal(_bits(out)[1:8193], ref.view(np.uint64))
 
 
 def test_config_validation():
@@ -222,8 +246,8 @@ def test_config_validation():
             nn.generate_into(z0, out, cfg=cfg)
     with pytest.raises(nn.NNError):
         nn.fill(out, 0, cfg=nn.make_cfg(layout="flat", unroll=3))
-    with pytest.raises(nn.NNError):
-        nn.generate_into(z0, out[1:].view(torch.float64), cfg=nn.make_cfg(layout="flat"))
+    with pytest.raises(nn.NNError):  # the row layout's 16-byte stores need 16-byte alignment
+        nn.generate_into(z0, out[1:].view(torch.float64), cfg=nn.make_cfg(layout="rows", width=2))
     # the default for an aligned output is the flat layout; a row-only field
     # (block, grid, ilp, width 1) selects the row layout
     d = nn.default_cfg("f64", 1 << 30)
