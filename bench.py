@@ -380,6 +380,21 @@ def main():
         rows_u_s = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out_u,
                                                           cfg=cfg_rows_u), reps, torch)
         extras["rows_layout_u64_GBps"] = 8.0 * case.count_u64 / rows_u_s / 1e9
+        # the flat layout's XCD runs against its chunks in address order
+        # (NN_CFG_ADDRESS_ORDER), the benchmark's own launches otherwise,
+        # timed in turn over three rounds (best round each)
+        order = {}
+        for kind, out, cfg in (("f64", out_f, cfg_f), ("u64", out_u, cfg_u)):
+            addr = nn._native.LaunchCfg.from_buffer_copy(cfg)
+            addr.flags |= nn._native.NN_CFG_ADDRESS_ORDER
+            best = {}
+            for _ in range(3):
+                for name, c in (("xcd_runs", cfg), ("address_order", addr)):
+                    t = _timed_kernel(lambda: nn.generate_into(nn.seed(case.index), out, cfg=c),
+                                      reps, torch)
+                    best[name] = min(best.get(name, t), t)
+            order[kind] = {k + "_GBps": 8.0 * out.numel() / v / 1e9 for k, v in best.items()}
+        extras["flat_chunk_order"] = order
         # The paper's "Constant" kernel (Section 4.2, Tables 1-2): the f64
         # generator's own launch (same layout, rows, store policy and cap)
         # with the arithmetic taken out -- bare stores, and the same stores

@@ -137,6 +137,9 @@ typedef struct nn_launch_cfg {
  * NN_MULMOD_MODBARRETT; grid, width, ilp and occupancy must be 0. */
 #define NN_CFG_PAPER_STRIDED 16u
 #define NN_CFG_NONTEMPORAL_STORES 32u
+/* Flat layout with 4 rows: the whole chunks in address order (workgroup w
+ * writes chunk w) instead of the default XCD runs; for comparison. */
+#define NN_CFG_ADDRESS_ORDER 128u
 
 /* ---------------------------------------------------------------- host -- */
 

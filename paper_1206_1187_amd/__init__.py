@@ -53,12 +53,14 @@ def init(device=0):
 
 
 def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=None, width=0, layout=None,
-             occupancy=0, ilp=0):
+             occupancy=0, ilp=0, address_order=False):
     """Launch configuration (include/nn.h, nn_launch_cfg); ``layout`` is
     None (library default), "flat", "rows", "consecutive" or "paper_strided"
     (the paper's transposed order: out[t + i*T] = element t*E + i).
     ``temporal``: None keeps the layout's default store policy, True asks for
-    temporal stores, False for non-temporal ones."""
+    temporal stores, False for non-temporal ones.  ``address_order``: the
+    flat layout's chunks in address order instead of XCD runs
+    (NN_CFG_ADDRESS_ORDER)."""
     if isinstance(mulmod, str):
         mulmod = MULMOD_NAMES[mulmod]
     flags = {None: 0, True: _native.NN_CFG_TEMPORAL_STORES,
@@ -74,6 +76,8 @@ def make_cfg(block=0, grid=0, mulmod=0, unroll=0, temporal=None, width=0, layout
     elif layout is not None:
         raise NNError(_native.NN_EINVAL, "layout must be None, 'flat', 'rows', 'consecutive' "
                       "or 'paper_strided'")
+    if address_order:
+        flags |= _native.NN_CFG_ADDRESS_ORDER
     return LaunchCfg(int(block), int(grid), int(mulmod), int(unroll), flags, int(width),
                      int(occupancy), int(ilp))
 

@@ -19,6 +19,7 @@ NN_CFG_FLAT = 4
 NN_CFG_CONSECUTIVE = 8
 NN_CFG_PAPER_STRIDED = 16
 NN_CFG_NONTEMPORAL_STORES = 32
+NN_CFG_ADDRESS_ORDER = 128
 NN_FILL_WITH_START = 64
 NN_DEBUG_DEVICE_MULMOD = 100
 

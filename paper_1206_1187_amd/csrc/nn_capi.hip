@@ -28,6 +28,7 @@ namespace {
 struct Resolved {
     uint32_t block, grid, mulmod, unroll, width, occupancy, ilp;
     bool nontemporal, flat, consec, strided;
+    bool xcd_runs;  // flat, 4 rows: whole chunks in XCD runs (NN_CFG_ADDRESS_ORDER clears it)
     uint32_t lds;  // dynamic LDS bytes per workgroup that cap residency
 };
 
@@ -44,8 +45,9 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     if (cfg) c = *cfg;
     const bool aligned16 = ((uintptr_t)out % 16) == 0;
     const uint32_t known = NN_CFG_TEMPORAL_STORES | NN_CFG_ROWS | NN_CFG_FLAT | NN_CFG_CONSECUTIVE |
-                           NN_CFG_PAPER_STRIDED | NN_CFG_NONTEMPORAL_STORES;
+                           NN_CFG_PAPER_STRIDED | NN_CFG_NONTEMPORAL_STORES | NN_CFG_ADDRESS_ORDER;
     if (c.flags & ~known) return fail(NN_EINVAL, "unknown flags 0x%x", c.flags);
+    r->xcd_runs = !(c.flags & NN_CFG_ADDRESS_ORDER);
     const uint32_t store_flags = c.flags & (NN_CFG_TEMPORAL_STORES | NN_CFG_NONTEMPORAL_STORES);
     if (store_flags == (NN_CFG_TEMPORAL_STORES | NN_CFG_NONTEMPORAL_STORES))
         return fail(NN_EINVAL, "NN_CFG_TEMPORAL_STORES and NN_CFG_NONTEMPORAL_STORES are exclusive");
@@ -55,6 +57,8 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     r->nontemporal = !(c.flags & NN_CFG_TEMPORAL_STORES);
     r->consec = (c.flags & NN_CFG_CONSECUTIVE) != 0;
     r->strided = (c.flags & NN_CFG_PAPER_STRIDED) != 0;
+    if ((c.flags & NN_CFG_ADDRESS_ORDER) && (r->consec || r->strided || (c.flags & NN_CFG_ROWS)))
+        return fail(NN_EINVAL, "NN_CFG_ADDRESS_ORDER applies to the flat layout only");
     r->flat = false;
     if (r->strided) {
         // The paper's layout: E consecutive elements per thread, stored
@@ -139,6 +143,8 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     r->flat = (c.flags & NN_CFG_FLAT) != 0 ||
               (!(c.flags & NN_CFG_ROWS) && !c.block && !c.grid && !c.ilp &&
                (c.width == 0 || (c.width == 2 && aligned16)));
+    if ((c.flags & NN_CFG_ADDRESS_ORDER) && !r->flat)
+        return fail(NN_EINVAL, "NN_CFG_ADDRESS_ORDER applies to the flat layout only");
     r->occupancy = c.occupancy ? c.occupancy : (r->flat ? kFlatDefaultOccupancy : 0u);
     r->lds = 0;
     if (r->occupancy) {
@@ -163,6 +169,7 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
             return fail(NN_EINVAL, "unroll %u: the flat layout writes 1, 2, 4, 8 or 16 rows "
                                    "per workgroup", r->unroll);
         if (!store_flags) r->nontemporal = false;
+        if (r->unroll != 4) r->xcd_runs = false;
         const uint64_t chunk = count < kFlatMaxCount ? count : kFlatMaxCount;
         const uint64_t per = (uint64_t)kFlatPerBlock * r->unroll;
         r->grid = (uint32_t)((chunk + per - 1) / per);
@@ -326,6 +333,7 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
         FlatArgs f;
         f.M1 = make_mult(kMult);
         f.J = make_mult(MultPowers::get().pow(kFlatPerBlock));
+        f.xcd_runs = r.xcd_runs;
         // an output that is only 8-byte aligned: its first element alone
         // (the tail kernel with one output), then the 16-byte aligned rest
         const uint64_t head = ((uintptr_t)out_dev % 16) ? 1 : 0;
@@ -344,7 +352,7 @@ int nn_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind, voi
             f.count = n;
             f.base = h_skip(s, off + 1);  // the first output of this chunk
             const uint64_t per = (uint64_t)kFlatPerBlock * r.unroll;
-            f.mid_base = h_skip(f.base, flat_run_chunks((int)r.unroll, n / per) * per);
+            f.mid_base = h_skip(f.base, flat_run_chunks((int)r.unroll, r.xcd_runs, n / per) * per);
             f.tail_base = h_skip(f.base, n / per * per);
             hipError_t e = launch_generate_flat((int)r.mulmod, kind, r.nontemporal, (int)r.unroll,
                                                 r.lds, (hipStream_t)stream, f);
@@ -456,14 +464,14 @@ int nn_fill(uint64_t count, void* out_dev, uint64_t value, void* stream, const n
         const uint64_t head = ((uintptr_t)out_dev % 16) ? 1 : 0;
         if (head) {
             hipError_t e = launch_fill_flat(r.nontemporal, (int)r.unroll, r.lds,
-                                            (hipStream_t)stream, with_start, (uint64_t*)out_dev,
-                                            1, value);
+                                            (hipStream_t)stream, with_start, r.xcd_runs,
+                                            (uint64_t*)out_dev, 1, value);
             if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
         }
         for (uint64_t off = head; off < count; off += kFlatMaxCount) {
             const uint64_t n = count - off < kFlatMaxCount ? count - off : kFlatMaxCount;
             hipError_t e = launch_fill_flat(r.nontemporal, (int)r.unroll, r.lds,
-                                            (hipStream_t)stream, with_start,
+                                            (hipStream_t)stream, with_start, r.xcd_runs,
                                             (uint64_t*)out_dev + off, n, value);
             if (e != hipSuccess) return fail(NN_EHIP, "fill launch: %s", hipGetErrorString(e));
         }

@@ -413,7 +413,7 @@ static hipError_t flat_one(uint32_t lds, hipStream_t s, const FlatArgs& a) {
     const uint64_t per = (uint64_t)kFlatPerBlock * R;
     const uint64_t full = a.count / per;  // whole chunks
     const uint64_t tail = a.count - full * per;
-    const uint64_t runs = flat_run_chunks(R, full);  // whole chunks in XCD runs
+    const uint64_t runs = flat_run_chunks(R, a.xcd_runs, full);  // whole chunks in XCD runs
     if constexpr (R == 4) {
         if (runs) {
             hipLaunchKernelGGL((k_generate_flat<V, KIND, NT, R, kFlatXcdRun>),
@@ -486,12 +486,12 @@ static hipError_t fill_flat_launch(uint32_t grid, uint32_t lds, hipStream_t s, b
 // Whole chunks in the generator's order (XCD runs, then workgroup order),
 // then the tail.
 template <bool NT, int R>
-static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, bool start, uint64_t* out,
-                                uint64_t count, uint64_t value) {
+static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, bool start, bool xcd_runs,
+                                uint64_t* out, uint64_t count, uint64_t value) {
     const uint64_t per = (uint64_t)kFlatPerBlock * R;
     const uint64_t full = count / per;
     const uint64_t tail = count - full * per;
-    const uint64_t runs = flat_run_chunks(R, full);
+    const uint64_t runs = flat_run_chunks(R, xcd_runs, full);
     if constexpr (R == 4) {
         if (runs) {
             const hipError_t e =
@@ -514,22 +514,22 @@ static hipError_t fill_flat_one(uint32_t lds, hipStream_t s, bool start, uint64_
 }
 
 template <bool NT>
-static hipError_t fill_flat_r(int rows, uint32_t lds, hipStream_t s, bool start,
+static hipError_t fill_flat_r(int rows, uint32_t lds, hipStream_t s, bool start, bool xcd_runs,
                               uint64_t* out, uint64_t count, uint64_t value) {
     switch (rows) {
-        case 1: return fill_flat_one<NT, 1>(lds, s, start, out, count, value);
-        case 2: return fill_flat_one<NT, 2>(lds, s, start, out, count, value);
-        case 4: return fill_flat_one<NT, 4>(lds, s, start, out, count, value);
-        case 8: return fill_flat_one<NT, 8>(lds, s, start, out, count, value);
-        case 16: return fill_flat_one<NT, 16>(lds, s, start, out, count, value);
+        case 1: return fill_flat_one<NT, 1>(lds, s, start, xcd_runs, out, count, value);
+        case 2: return fill_flat_one<NT, 2>(lds, s, start, xcd_runs, out, count, value);
+        case 4: return fill_flat_one<NT, 4>(lds, s, start, xcd_runs, out, count, value);
+        case 8: return fill_flat_one<NT, 8>(lds, s, start, xcd_runs, out, count, value);
+        case 16: return fill_flat_one<NT, 16>(lds, s, start, xcd_runs, out, count, value);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_fill_flat(bool nt, int rows, uint32_t lds, hipStream_t s, bool start,
-                            uint64_t* out, uint64_t count, uint64_t value) {
-    return nt ? fill_flat_r<true>(rows, lds, s, start, out, count, value)
-              : fill_flat_r<false>(rows, lds, s, start, out, count, value);
+                            bool xcd_runs, uint64_t* out, uint64_t count, uint64_t value) {
+    return nt ? fill_flat_r<true>(rows, lds, s, start, xcd_runs, out, count, value)
+              : fill_flat_r<false>(rows, lds, s, start, xcd_runs, out, count, value);
 }
 
 // Kernel selector: W = 1, W = 2, or W = 2 with IL = 2 or 4 rows in flight.

@@ -96,10 +96,11 @@ hipError_t upload_flat_symbol(const Mult* entries);
 // own from mid_base).
 constexpr uint32_t kFlatXcds = 8;
 constexpr uint32_t kFlatXcdRun = 256;
-// Whole chunks of a flat launch that go to the XCD-run kernel.
-inline uint64_t flat_run_chunks(int rows, uint64_t whole_chunks) {
+// Whole chunks of a flat launch that go to the XCD-run kernel (runs: the
+// launch takes XCD runs at all).
+inline uint64_t flat_run_chunks(int rows, bool runs, uint64_t whole_chunks) {
     const uint64_t run = (uint64_t)kFlatXcds * kFlatXcdRun;
-    return rows == 4 ? whole_chunks / run * run : 0;
+    return rows == 4 && runs ? whole_chunks / run * run : 0;
 }
 
 struct FlatArgs {
@@ -110,6 +111,7 @@ struct FlatArgs {
     uint64_t tail_base;  // state of the first output of the partial last chunk, if any
     Mult M1;         // 2^53
     Mult J;          // (2^53)^kFlatPerBlock: the next row of a lane
+    bool xcd_runs;   // 4 rows: whole chunks in XCD runs (else address order)
 };
 
 // rows: rows per workgroup (1, 2, 4, 8, 16); lds_bytes > 0 caps the
@@ -118,7 +120,8 @@ hipError_t launch_generate_flat(int mulmod, int kind, bool nontemporal, int rows
                                 uint32_t lds_bytes, hipStream_t stream, const FlatArgs& a);
 // start: the fill that keeps the generator's table loads (NN_FILL_WITH_START).
 hipError_t launch_fill_flat(bool nontemporal, int rows, uint32_t lds_bytes, hipStream_t stream,
-                            bool start, uint64_t* out, uint64_t count, uint64_t value);
+                            bool start, bool xcd_runs, uint64_t* out, uint64_t count,
+                            uint64_t value);
 
 // Consecutive layout: the output is cut into tiles of block*E elements;
 // workgroup w makes tiles w, w + grid, ...  In a tile, thread t makes

@@ -64,8 +64,10 @@ def _lookup(form, kind, size, path=CACHE):
 #: run exactly these, so the timed kernels are the compared ones.
 BENCH_PLAIN = {
     "f64": dict(layout="flat", mulmod="fp64", unroll=4, occupancy=4, temporal=True),
-    # raw states: Shoup's reduction keeps the state an integer (no conversion)
-    "u64": dict(layout="flat", mulmod="shoup", unroll=4, occupancy=4, temporal=True),
+    # raw states: the FP64 reduction too (the library default and the
+    # autotuner's pick with the chunks in XCD runs; Shoup's, which keeps the
+    # state an integer, ties or trails by 1-2 % there)
+    "u64": dict(layout="flat", mulmod="fp64", unroll=4, occupancy=4, temporal=True),
 }
 
 
@@ -211,6 +213,10 @@ def tune_plain(kind, count, reps=9, log=print):
     cands += [dict(layout="flat", mulmod=mulmod, unroll=rows, occupancy=occ, temporal=temporal)
               for mulmod, rows, occ, temporal in itertools.product(
                   ("fp64", "shoup"), (2, 4, 8), (3, 4, 5, 6), (False, True))]
+    # four-row chunks in address order instead of XCD runs
+    cands += [dict(layout="flat", mulmod=mulmod, unroll=4, occupancy=occ, temporal=True,
+                   address_order=True)
+              for mulmod, occ in itertools.product(("fp64", "shoup"), (3, 4, 5))]
     for kw in cands:
         cfg = nn.make_cfg(**kw)
         ms = _median_ms(lambda: nn.generate_into(s0, out, cfg=cfg), reps)

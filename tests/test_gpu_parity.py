@@ -197,11 +197,13 @@ def test_flat_xcd_runs_bit_exact(variant):
     counts = (run - 2048, run - 1, run, run + 1, run + 2048, 2 * run + 7 * 2048 + 1234, top)
     for count in counts:
         for kind, ref in (("u64", ref_u), ("f64", ref_f)):
-            cfg = nn.make_cfg(mulmod=variant, layout="flat", unroll=4, occupancy=4, temporal=True)
-            _say("flat xcd runs", variant, count, kind)
-            got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=512)
-            assert np.array_equal(got, ref.view(np.uint64)[:count]), (variant, count, kind)
-            assert zn == orc.skip(z0, count)
+            for order in (False, True):  # XCD runs, then NN_CFG_ADDRESS_ORDER
+                cfg = nn.make_cfg(mulmod=variant, layout="flat", unroll=4, occupancy=4,
+                                  temporal=True, address_order=order)
+                _say("flat xcd runs", variant, count, kind, order)
+                got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=512)
+                assert np.array_equal(got, ref.view(np.uint64)[:count]), (variant, count, kind)
+                assert zn == orc.skip(z0, count)
 
 
 def test_pick_plain_layout_returns_a_working_cfg():
@@ -237,7 +239,9 @@ def test_config_validation():
            nn.make_cfg(layout="rows", occupancy=4), nn.make_cfg(mulmod=9),
            nn.make_cfg(ilp=3), nn.make_cfg(width=1, ilp=2), nn.make_cfg(layout="flat", ilp=2),
            nn.make_cfg(grid=1 << 20, block=1024), nn.make_cfg(layout="flat", unroll=3),
-           nn.make_cfg(layout="flat", unroll=32), nn.make_cfg(layout="flat", grid=4)]
+           nn.make_cfg(layout="flat", unroll=32), nn.make_cfg(layout="flat", grid=4),
+           nn.make_cfg(layout="rows", address_order=True),
+           nn.make_cfg(layout="consecutive", address_order=True)]
     both = nn.make_cfg(layout="flat", temporal=True)
     both.flags |= nn._native.NN_CFG_NONTEMPORAL_STORES
     bad.append(both)
