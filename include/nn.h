@@ -538,12 +538,12 @@ int nn_e40_skip(uint64_t state, uint64_t k, uint64_t *state_out);
  * workgroup per CU, ilp 2, unroll 1) or NN_MULMOD_MONTGOMERY (64-bit
  * states, R = 2^64; defaults 256 threads, three workgroups per CU, ilp 4,
  * unroll 2).  Layouts: the row layout, or (NN_CFG_FLAT, and the default for
- * a 16-byte aligned output of either kind with the FP64 step) the flat
- * layout: one 256-thread workgroup per chunk of `unroll` rows of 512
- * outputs (2, 4, 8, 16, 32; default 16), residency capped by `occupancy`
- * (default 4); with one workgroup per chunk (grid 0) the chunks are taken
- * in XCD runs of 4 MiB per XCD as in the 3^33 flat layout; NN_CFG_ROWS
- * forces the row layout.  16-byte stores in both.  Both
+ * either kind with the FP64 step) the flat layout: one 256-thread workgroup
+ * per chunk of `unroll` rows of 512 outputs (2, 4, 8, 16, 32; default 16),
+ * residency capped by `occupancy` (default 4); with one workgroup per chunk
+ * (grid 0) the chunks are taken in XCD runs of 4 MiB per XCD as in the 3^33
+ * flat layout; an output that is only 8-byte aligned gets its first element
+ * alone; NN_CFG_ROWS forces the row layout.  16-byte stores in both.  Both
  * reductions give the same bits.  Errors as nn_generate_ex. */
 int nn_e40_generate_ex(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream,
                        const nn_launch_cfg *cfg);

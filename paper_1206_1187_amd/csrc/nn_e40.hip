@@ -509,8 +509,6 @@ constexpr uint32_t kE40FlatDefaultRows = 16;
 // (default temporal).
 int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void* stream,
                   const nn_launch_cfg& c, int mm) {
-    if ((uintptr_t)out_dev % 16)
-        return fail(NN_EINVAL, "the flat layout needs a 16-byte aligned output (got %p)", out_dev);
     if ((c.block && c.block != 256) || c.ilp > 1)
         return fail(NN_EINVAL, "the flat layout has 256 threads per workgroup and no ilp");
     const uint32_t rows = c.unroll ? c.unroll : kE40FlatDefaultRows;
@@ -538,7 +536,19 @@ int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void
     a.M1L = make_mult40l(a.M1.v);
     a.JL = make_mult40l(a.J.v);
     a.tabs = tab;
-    for (uint64_t off = 0; off < count; off += max_launch) {
+    // an output that is only 8-byte aligned: its first element alone (the
+    // tail kernel with one output), then the 16-byte aligned rest
+    const uint64_t head = ((uintptr_t)out_dev % 16) ? 1 : 0;
+    if (head) {
+        E40FlatArgs h = a;
+        h.n_chunks = 0;
+        h.out = (uint64_t*)out_dev;
+        h.base = h_mul(s, Powers::get().pow(1));
+        const hipError_t e =
+            launch_flat(kind, mm, (int)rows, nt, 1, lds, (hipStream_t)stream, h, h, h, 1);
+        if (e != hipSuccess) return fail(NN_EHIP, "e40 launch: %s", hipGetErrorString(e));
+    }
+    for (uint64_t off = head; off < count; off += max_launch) {
         const uint64_t n = count - off < max_launch ? count - off : max_launch;
         a.out = (uint64_t*)out_dev + off;
         a.base = h_mul(s, Powers::get().pow(off + 1));  // the state of this slice's first output
@@ -625,11 +635,11 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
     if ((c.flags & NN_CFG_TEMPORAL_STORES) && (c.flags & NN_CFG_NONTEMPORAL_STORES))
         return fail(NN_EINVAL, "NN_CFG_TEMPORAL_STORES and NN_CFG_NONTEMPORAL_STORES are exclusive");
     const int mm = c.mulmod == NN_MULMOD_MONTGOMERY ? 0 : 1;
-    const bool aligned16 = ((uintptr_t)out_dev % 16) == 0;
-    // No layout flag: the flat layout for a 16-byte aligned output with the
-    // FP64 step unless the cfg sets a row-layout field (block, ilp).
+    // No layout flag: the flat layout with the FP64 step unless the cfg sets
+    // a row-layout field (block, ilp); an output that is only 8-byte aligned
+    // gets its first element alone.
     const bool flat = (c.flags & NN_CFG_FLAT) ||
-                      (!(c.flags & NN_CFG_ROWS) && aligned16 && mm == 1 && !c.block && !c.ilp);
+                      (!(c.flags & NN_CFG_ROWS) && mm == 1 && !c.block && !c.ilp);
     if (flat) return e40::generate_flat(state, count, out_dev, kind, stream, c, mm);
     if (c.occupancy) return fail(NN_EINVAL, "occupancy applies to the flat layout only");
     const uint32_t block = c.block ? c.block : 256u;

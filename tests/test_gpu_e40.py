@@ -91,10 +91,14 @@ def test_e40_flat_layout_bit_exact(mulmod):
                 assert np.array_equal(got, ref.view(np.uint64)[:count]), \
                     (rows, grid, occ, temporal, count, kind)
                 assert zn == orc.e40_skip(z0, count)
-    # an output that is only 8-byte aligned cannot take the flat layout
-    buf = torch.empty(4097, dtype=torch.float64, device="cuda")
-    with pytest.raises(nn.NNError):
-        nn.e40_generate_into(z0, buf[1:], cfg=nn.make_cfg(layout="flat"))
+    # an output that is only 8-byte aligned: its first element alone, the
+    # rest 16-byte aligned (the default there too, with the FP64 step)
+    for cfg in (nn.make_cfg(layout="flat", mulmod=mulmod), nn.make_cfg(mulmod=mulmod)):
+        for count in (1, 2, 3, 4097, 300_000 - 1):
+            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=513)
+                assert np.array_equal(got, ref.view(np.uint64)[:count]), ("8-aligned", count, kind)
+                assert zn == orc.e40_skip(z0, count)
 
 
 def test_e40_flat_xcd_runs_bit_exact():
