@@ -80,7 +80,7 @@ def traffic_from_profile():
         return None
 
 
-def batched_leg(nn, torch):
+def batched_leg(nn, torch, per_stream=True):
     """Config 4: 10,000 streams (lengths log-uniform in [1, 2^22]) as one
     batched launch replayed from the plan's hipGraph, in the shape
     tune.bench_batch_kw gives (the one the full-size parity test compares),
@@ -122,6 +122,10 @@ def batched_leg(nn, torch):
     res["variates_per_s"] = total / graph_s
     res["GBps"] = 8.0 * total / graph_s / 1e9
     res["frac_of_hbm_peak"] = res["GBps"] / (HBM_PEAK_GBPS)
+    if not per_stream:
+        del out
+        torch.cuda.empty_cache()
+        return res
     batched_bits = out.view(torch.int64)[:4096].cpu().numpy().copy()
     # one launch per stream, same output, same stream
     views = [(int(s), out[int(o):int(o) + int(n)]) for s, n, o in zip(states, lengths, offsets)]
@@ -249,6 +253,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fill ceiling and reduction comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form replay")
+    ap.add_argument("--no-per-stream", action="store_true",
+                    help="skip the batched leg's one-launch-per-stream baseline (10,000 launches; "
+                         "for the hardware-counter runs)")
     ap.add_argument("--only", choices=["batched", "served"],
                     help="run only this leg and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -280,7 +287,8 @@ def main():
         return
     nn.init(0)
     if args.only:
-        leg = batched_leg(nn, torch) if args.only == "batched" else served_leg(nn, torch)
+        leg = (batched_leg(nn, torch, not args.no_per_stream) if args.only == "batched"
+               else served_leg(nn, torch))
         print(json.dumps({args.only: leg}), flush=True)
         return
     case = wl.plain_bulk()
@@ -496,7 +504,7 @@ def main():
     del out_f, out_u
     torch.cuda.empty_cache()
     if not args.no_extras:
-        result["batched"] = batched_leg(nn, torch)
+        result["batched"] = batched_leg(nn, torch, not args.no_per_stream)
         log("batched", json.dumps(result["batched"]))
         if not args.no_served:
             result["served"] = served_leg(nn, torch)
