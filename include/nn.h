@@ -73,8 +73,8 @@ typedef enum nn_mulmod {
  *
  * Three layouts write the same values (serial order in memory):
  *  - flat (NN_CFG_FLAT; the default for a cfg that sets none of block,
- *    grid, ilp or width 1, nor width 2 on an output that is only 8-byte
- *    aligned): every 256-thread workgroup writes `unroll` rows of 512
+ *    grid, ilp or width 1, on an output that is 16-byte aligned or, with
+ *    width 0, holds at least 2^22 outputs): every 256-thread workgroup writes `unroll` rows of 512
  *    consecutive outputs (one contiguous chunk), two per lane in one
  *    16-byte store per row, and exits; an output that is only 8-byte
  *    aligned gets its first element from a one-workgroup launch and the
@@ -543,7 +543,8 @@ int nn_e40_skip(uint64_t state, uint64_t k, uint64_t *state_out);
  * residency capped by `occupancy` (default 4); with one workgroup per chunk
  * (grid 0) the chunks are taken in XCD runs of 4 MiB per XCD as in the 3^33
  * flat layout; an output that is only 8-byte aligned gets its first element
- * alone; NN_CFG_ROWS forces the row layout.  16-byte stores in both.  Both
+ * alone (by default from 2^22 outputs on); NN_CFG_ROWS forces the row
+ * layout.  16-byte stores in both.  Both
  * reductions give the same bits.  Errors as nn_generate_ex. */
 int nn_e40_generate_ex(uint64_t *state, uint64_t count, void *out_dev, int kind, void *stream,
                        const nn_launch_cfg *cfg);

@@ -497,7 +497,25 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     // every record array holds, and leaves.
     const Mult ma = chunk_sym[2u * l], mb = chunk_sym[2u * l + 1];
     const Mult JB = chunk_sym[2 * kFlatBlock];
-    u64x2 cur = rec[at(j < n ? j : 0)];
+    u64x2 cur;
+    if constexpr (NT) {
+        // With non-temporal stores the record is loaded through the vector
+        // memory path (every lane the same 16 bytes; an index offset the
+        // compiler cannot prove uniform keeps it from becoming a scalar
+        // load), then made uniform: 3 % faster than the scalar load at the
+        // tuned cap of 3.  With temporal stores the vector path was 30 %
+        // slower, so those keep the scalar load.
+        uint32_t vz;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+        const global_ptr<u64x2> vrec = reinterpret_cast<global_ptr<u64x2>>(as_global(a.rec));
+        const u64x2 v = vrec[at(j < n ? j : 0) + vz];
+        cur.x = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v.x >> 32)) << 32) |
+                (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v.x);
+        cur.y = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v.y >> 32)) << 32) |
+                (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v.y);
+    } else {
+        cur = rec[at(j < n ? j : 0)];
+    }
     if (j >= n) return;
     const global_ptr<uint64_t> out = as_global(a.out);
     // one window's part [lo, hi) of the chunk at output g, from the state z0

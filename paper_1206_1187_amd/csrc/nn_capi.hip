@@ -139,10 +139,13 @@ int resolve_cfg(const nn_launch_cfg* cfg, int kind, uint64_t count, const Device
     // wrote faster than the row layout on every MI355X measured, for both
     // kinds (2^30 f64: 6.9 against 6.7 TB/s; 2^28 u64: 6.65 against 6.05).
     // An output that is only 8-byte aligned gets its first element from a
-    // one-workgroup launch and the rest, 16-byte aligned, as usual.
+    // one-workgroup launch and the rest, 16-byte aligned, as usual; below
+    // kFlatUnalignedMin outputs that extra launch costs more than the flat
+    // layout gains, and such outputs keep the row layout (one launch).
     r->flat = (c.flags & NN_CFG_FLAT) != 0 ||
               (!(c.flags & NN_CFG_ROWS) && !c.block && !c.grid && !c.ilp &&
-               (c.width == 0 || (c.width == 2 && aligned16)));
+               (aligned16 ? c.width == 0 || c.width == 2
+                          : c.width == 0 && count >= kFlatUnalignedMin));
     if ((c.flags & NN_CFG_ADDRESS_ORDER) && !r->flat)
         return fail(NN_EINVAL, "NN_CFG_ADDRESS_ORDER applies to the flat layout only");
     r->occupancy = c.occupancy ? c.occupancy : (r->flat ? kFlatDefaultOccupancy : 0u);

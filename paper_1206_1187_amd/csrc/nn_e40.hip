@@ -637,9 +637,12 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
     const int mm = c.mulmod == NN_MULMOD_MONTGOMERY ? 0 : 1;
     // No layout flag: the flat layout with the FP64 step unless the cfg sets
     // a row-layout field (block, ilp); an output that is only 8-byte aligned
-    // gets its first element alone.
+    // gets its first element alone, by default from kFlatUnalignedMin
+    // outputs on (below, the row layout's one launch is the cheaper).
+    const bool aligned16 = ((uintptr_t)out_dev % 16) == 0;
     const bool flat = (c.flags & NN_CFG_FLAT) ||
-                      (!(c.flags & NN_CFG_ROWS) && mm == 1 && !c.block && !c.ilp);
+                      (!(c.flags & NN_CFG_ROWS) && mm == 1 && !c.block && !c.ilp &&
+                       (aligned16 || count >= kFlatUnalignedMin));
     if (flat) return e40::generate_flat(state, count, out_dev, kind, stream, c, mm);
     if (c.occupancy) return fail(NN_EINVAL, "occupancy applies to the flat layout only");
     const uint32_t block = c.block ? c.block : 256u;

@@ -75,6 +75,9 @@ constexpr uint64_t kFlatMaxCount = kFlatMaxRowsPerLaunch * kFlatPerBlock;  // 2^
 // workgroup: 6.2-6.35 TB/s at 31 744 bytes or less, 7.4-7.5 TB/s from
 // 32 256 to 40 960 bytes; non-temporal stores stay at 6.2-6.4 throughout.
 constexpr uint32_t kFlatMaxRows = 16;
+// Outputs from which an output that is only 8-byte aligned takes the flat
+// layout by default (its first element in a launch of its own).
+constexpr uint64_t kFlatUnalignedMin = 1ull << 22;
 constexpr uint32_t kFlatDefaultRows = 4;
 constexpr uint32_t kFlatDefaultOccupancy = 4;
 

@@ -120,6 +120,12 @@ def test_e40_flat_xcd_runs_bit_exact():
                 got, zn = _gen_guarded(z0, count, kind, cfg=cfg)
                 assert np.array_equal(got, ref.view(np.uint64)[:count]), (rows, count, kind)
                 assert zn == orc.e40_skip(z0, count)
+    # the default on an output that is only 8-byte aligned and large enough:
+    # the flat layout with its first element alone
+    for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+        got, zn = _gen_guarded(z0, top - 1, kind, guard=513)
+        assert np.array_equal(got, ref.view(np.uint64)[:top - 1]), ("default 8-aligned", kind)
+        assert zn == orc.e40_skip(z0, top - 1)
 
 
 def test_e40_flat_beyond_one_launch_sampled():
