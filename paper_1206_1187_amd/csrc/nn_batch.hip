@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kFlatBlock) void k_batch_chunks(BatchArgs a) {
     // workgroup's record go out before anything waits.  A workgroup past the
     // last record (a fixed grid larger than the batch) reads record 0, which
     // every record array holds, and leaves.
-    const Mult ma = chunk_sym[2u * l], mb = chunk_sym[2u * l + 1];
+    const Mult ma = chunk_sym[l], mb = chunk_sym[kFlatBlock + l];
     const Mult JB = chunk_sym[2 * kFlatBlock];
     u64x2 cur;
     if constexpr (NT) {

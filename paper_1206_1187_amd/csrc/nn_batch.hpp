@@ -128,7 +128,8 @@ const void* batch_rows_kernel(int kind, bool nontemporal);
 constexpr uint32_t kChunkRows = 4;
 constexpr uint32_t kChunkOuts = kChunkRows * 512;
 // The chunked kernel's multipliers in a static device array of its module:
-// (2^53)^k for k < 2*kFlatBlock (a lane's pair), then (2^53)^kFlatPerBlock
+// (2^53)^(2l) for l < kFlatBlock, then (2^53)^(2l+1) (a lane's pair, each
+// half contiguous so a wave's loads of either are), then (2^53)^kFlatPerBlock
 // (one row).  Filled per device at set-up.
 constexpr uint32_t kChunkSymEntries = 2 * kFlatBlock + 1;
 hipError_t upload_chunk_symbol(const Mult* entries);

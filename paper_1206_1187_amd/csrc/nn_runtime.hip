@@ -180,8 +180,11 @@ int ensure_device_current(int dev, DeviceTables** out) {
             for (uint32_t l = 0; l < kFlatBlock; ++l) sym[kFlatSymLane + l] = h[2u * l];
             std::copy(hb.begin(), hb.end(), sym.begin() + kFlatSymLo);
             e = upload_flat_symbol(sym.data());
-            // the chunked batch kernel's: t_lo's first 2*kFlatBlock entries, one row's step
-            std::vector<Mult> cs(h.begin(), h.begin() + 2 * kFlatBlock);
+            // the chunked batch kernel's: t_lo's even entries below 2*kFlatBlock,
+            // then its odd ones, then one row's step
+            std::vector<Mult> cs;
+            for (uint32_t l = 0; l < kFlatBlock; ++l) cs.push_back(h[2u * l]);
+            for (uint32_t l = 0; l < kFlatBlock; ++l) cs.push_back(h[2u * l + 1]);
             cs.push_back(make_mult(MultPowers::get().pow(kFlatPerBlock)));
             if (e == hipSuccess) e = upload_chunk_symbol(cs.data());
             if (e != hipSuccess) {
