@@ -314,13 +314,21 @@ typedef struct nn_batch_cfg {
 
 /* Opaque batch plan: device workspace, pinned staging and a hipGraph of
  * (staging -> workspace copy, persistent kernel) whose arguments never
- * change, owned by the library until nn_batch_plan_destroy. */
+ * change, owned by the library until nn_batch_plan_destroy.  A chunked
+ * plan (NN_BATCH_CHUNKS) also owns a stream (non-blocking, default
+ * priority) that carries each batch's descriptor upload and record
+ * pre-pass, so they run during the previous batch's kernel; its graph holds
+ * the chunk kernel alone. */
 typedef struct nn_batch_plan nn_batch_plan;
 
 /* nn_batch_plan_create -- a plan on the current device for batches of at
  * most `max_streams` streams and `max_outputs` outputs in total, writing
- * `kind` outputs.  Allocates the workspace (40 bytes per stream, plus one
- * per 2^24 outputs) in device and pinned host memory.
+ * `kind` outputs.  Allocates two slots (batches alternate between them),
+ * each a workspace of 40 bytes per descriptor (one per stream, plus one per
+ * 2^24 outputs for the split of long streams) in device and pinned host
+ * memory; the interleaved and chunked kernels add 16 bytes of device
+ * memory per record (one per row of 2*block outputs or chunk of 2048, plus
+ * two per descriptor, and for chunks one more per descriptor).
  * Errors: NN_EINVAL (kind, cfg), NN_ERANGE (capacity), NN_ENOMEM, NN_EHIP. */
 int nn_batch_plan_create(int kind, uint32_t max_streams, uint64_t max_outputs,
                          const nn_batch_cfg *cfg, nn_batch_plan **plan_out);
@@ -343,8 +351,11 @@ int nn_batch_plan_cfg(const nn_batch_plan *plan, nn_batch_cfg *cfg_out);
  * Outputs are identical to nn_generate on each stream alone.  final_states
  * (host array of n, or NULL) receives each stream's state after its window.
  * Asynchronous; the call blocks only while the plan's previous batch is
- * still copying its descriptors.  A plan serves one call at a time (calls
- * on one plan are serialised).  Errors: NN_EINVAL (states, pointers, wrong
+ * still copying its descriptors.  In a chunked plan the upload and the
+ * pre-pass go to the plan's own stream and `stream` waits for them through
+ * an event before the chunk kernel, so the call is not meant for a stream
+ * under capture (the plan replays graphs of its own).  A plan serves one
+ * call at a time (calls on one plan are serialised).  Errors: NN_EINVAL (states, pointers, wrong
  * device), NN_ERANGE (more streams or outputs than the plan holds; nothing
  * is enqueued), NN_EHIP. */
 int nn_generate_batch(nn_batch_plan *plan, const nn_stream_desc *descs, uint32_t n,
