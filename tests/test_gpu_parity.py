@@ -182,6 +182,25 @@ def test_flat_layout_bit_exact(variant):
             assert np.array_equal(got, ref_f.view(np.uint64)[:99_991]), (rows, temporal)
 
 
+def test_flat_residency_cap_bounds():
+    """The flat layout at the residency caps' bounds, 2 and 16 workgroups
+    per compute unit (the LDS that a workgroup reserves is largest at 2),
+    four and eight rows, both kinds, a count with whole XCD runs, leftover
+    chunks and a ragged tail, against the oracle element by element."""
+    z0 = orc.seed(wl.INDEX_MIN + 4242)
+    count = 2048 * 2048 + 5 * 2048 + 777
+    ref_u, _ = orc.gen(z0, count, "u64", threads=0)
+    ref_f, _ = orc.gen(z0, count, "f64", threads=0)
+    for occ in (2, 16):
+        for rows in (4, 8):
+            cfg = nn.make_cfg(layout="flat", unroll=rows, occupancy=occ)
+            for kind, ref in (("u64", ref_u), ("f64", ref_f)):
+                _say("flat cap", occ, rows, kind)
+                got, zn = _gen_guarded(z0, count, kind, cfg=cfg, guard=512)
+                assert np.array_equal(got, ref.view(np.uint64)), (occ, rows, kind)
+                assert zn == orc.skip(z0, count)
+
+
 @pytest.mark.parametrize("variant", ["fp64", "shoup"])
 def test_flat_xcd_runs_bit_exact(variant):
     """Four-row flat launches take their whole chunks in XCD runs of 2048
