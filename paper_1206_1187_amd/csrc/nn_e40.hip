@@ -289,7 +289,7 @@ struct E40FlatArgs {
     Mult40 M1, J, JN;
     Mult40L M1L, JL, JNL;
     const Mult40* tabs;  // t_lo, t_hi, t_flo, t_fhi, then the same as limbs
-    double base_lo, base_hi;  // base as base-B limbs
+    double base_lo, base_hi;  // base as base-B limbs (limbs())
 };
 
 // Workgroup w writes chunk w, then w + grid, ... (grid <= n_chunks, as the
@@ -552,8 +552,8 @@ int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void
         const uint64_t n = count - off < max_launch ? count - off : max_launch;
         a.out = (uint64_t*)out_dev + off;
         a.base = h_mul(s, Powers::get().pow(off + 1));  // the state of this slice's first output
-        a.base_lo = (double)(a.base % kLimb);
-        a.base_hi = (double)(a.base / kLimb);
+        a.base_lo = limbs(a.base).lo;
+        a.base_hi = limbs(a.base).hi;
         a.n_chunks = n / per;
         uint32_t grid = 1;
         if (a.n_chunks) {
@@ -570,8 +570,8 @@ int generate_flat(uint64_t* state, uint64_t count, void* out_dev, int kind, void
             m.n_chunks = a.n_chunks - runs;
             m.out = a.out + runs * per;
             m.base = h_mul(a.base, Powers::get().pow(runs * per));
-            m.base_lo = (double)(m.base % kLimb);
-            m.base_hi = (double)(m.base / kLimb);
+            m.base_lo = limbs(m.base).lo;
+            m.base_hi = limbs(m.base).hi;
         }
         E40FlatArgs t = a;
         const uint64_t tail = n - a.n_chunks * per;

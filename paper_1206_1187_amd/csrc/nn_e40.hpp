@@ -59,9 +59,10 @@ NN_HD double to_f64(uint64_t z) { return (double)z * kRecip; }
 // FP64: the product as ph + pl (two-product, exact), a quotient rounded
 // from ph/B (off by at most one from the nearest), the remainder formed by
 // one FMA and one add, both exact because it is an integer below 2^34.
-// States stay redundant between steps: x0 = r in about [-B/2, B/2] and
-// x1 the unreduced sum, below 2.01 B in magnitude; canon() reduces both
-// limbs to [0, B) for output.  Multipliers are canonical: 0 <= j0, j1 < B.
+// States stay redundant (limbs() starts them so): x0 = r in about
+// [-B/2, B/2] and x1 the unreduced sum, below 2.01 B in magnitude; the
+// output takes z from them directly (top() below).  Multipliers are
+// canonical: 0 <= j0, j1 < B.
 constexpr uint64_t kLimb = 3486784401ULL;  // 3^20
 constexpr double kB = 3486784401.0;
 constexpr double kRB = 1.0 / 3486784401.0;      // RN(1/B)
@@ -95,32 +96,35 @@ NN_HD L2 mul40l(L2 z, Mult40L v) {
     return L2{r, ta + tb + c};
 }
 
-NN_HD L2 limbs(uint64_t z) { return L2{(double)(z % kLimb), (double)(z / kLimb)}; }
-
-// The canonical limbs (z = hi B + lo, 0 <= lo, hi < B) of a redundant state.
-// g = floor(x0 / B) is -1 or 0 (x0 is a nonzero integer in (-B, B)); the
-// quotient floor((y + 1/2) / B) of the carried x1 is at least 1/(2B) away
-// from an integer, far beyond its rounding error, so its floor is exact.
-NN_HD void canon(L2 z, double* hi, double* lo) {
-    const double g = __builtin_floor(z.lo * kRB);
-    *lo = __builtin_fma(-g, kB, z.lo);
-    const double y = z.hi + g;
-    const double f = __builtin_floor(__builtin_fma(y, kRB, kHalfRB));
-    *hi = __builtin_fma(-f, kB, y);
+// A state's limbs in the form the step keeps: z = x1 B + x0 with
+// |x0| <= B/2 (x0 = z mod B, less B above B/2) and 0 <= x1 <= B.
+NN_HD L2 limbs(uint64_t z) {
+    const uint64_t q = z / kLimb, r = z % kLimb;
+    return r > kLimb / 2 ? L2{(double)r - kB, (double)(q + 1)} : L2{(double)r, (double)q};
 }
 
+// The output needs z = x1 B + x0 mod m in [0, m), not canonical limbs:
+// z = (x1 - f B) B + x0 for f = floor((x1 + x0/B) / B).  x0 is a nonzero
+// integer in (-B, B) (a state is a unit, so x0 is not a multiple of B), so
+// x1 + x0/B lies strictly between x1 and x1 + 1 for x0 > 0 and between
+// x1 - 1 and x1 for x0 < 0, and neither open interval holds a multiple of
+// B: f = floor((x1 + 1/2) / B) or floor((x1 - 1/2) / B), the half taking
+// x0's sign.  That quotient is at least 1/(2B) away from an integer, far
+// beyond the rounding of the one FMA that forms it, so its floor is exact.
+// top() returns x1 - f B, in [0, B) for x0 > 0 and [1, B] for x0 < 0, and
+// z = top B + x0 lies in (0, m).
+NN_HD double top(L2 z) {
+    const double f = __builtin_floor(__builtin_fma(z.hi, kRB, __builtin_copysign(kHalfRB, z.lo)));
+    return __builtin_fma(-f, kB, z.hi);
+}
+
+// top < 2^32 and |x0| < 2^31: z formed modulo 2^64, where it is exact.
 NN_HD uint64_t to_u64(L2 z) {
-    double hi, lo;
-    canon(z, &hi, &lo);
-    return (uint64_t)(uint32_t)hi * kLimb + (uint32_t)lo;
+    return (uint64_t)(uint32_t)top(z) * kLimb + (uint64_t)(int64_t)(int32_t)z.lo;
 }
 
-// RN(z) = RN(hi B + lo) is one FMA: the exact sum rounded once.
-NN_HD double to_f64(L2 z) {
-    double hi, lo;
-    canon(z, &hi, &lo);
-    return __builtin_fma(hi, kB, lo) * kRecip;
-}
+// RN(z) is one FMA: top B + x0 formed exactly and rounded once.
+NN_HD double to_f64(L2 z) { return __builtin_fma(top(z), kB, z.lo) * kRecip; }
 
 inline Mult40L make_mult40l(uint64_t v) { return Mult40L{(double)(v % kLimb), (double)(v / kLimb)}; }
 

@@ -99,6 +99,15 @@ int main() {
     const uint64_t l_edge[] = {1,           2,           nn::e40::kLimb - 1, nn::e40::kLimb + 1,
                                m40 - 1,     m40 - 2,     nn::e40::kHalf,     nn::e40::kMult,
                                m40 - nn::e40::kLimb + 1, (nn::e40::kLimb - 1) * nn::e40::kLimb + 1};
+    auto l_edge_of = [&](int i) { return l_edge[i]; };
+    // a state converted straight from its limbs (a launch's first outputs),
+    // and the limbs' bound, which the conversions rely on
+    for (int c = 0; c < 20000; ++c) {
+        const uint64_t s = c < 10 ? l_edge_of(c) : unit(m40);
+        const nn::e40::L2 z = nn::e40::limbs(s);
+        CHECK(fabs(z.lo) <= 0.5 * nn::e40::kB && z.hi >= 0.0 && z.hi <= nn::e40::kB);
+        CHECK(nn::e40::to_u64(z) == s && nn::e40::to_f64(z) == orc_e40_to_f64(s));
+    }
     for (uint64_t v : l_edge)
         for (uint64_t s : l_edge) {
             const nn::e40::L2 r = nn::e40::mul40l(nn::e40::limbs(s), nn::e40::make_mult40l(v));
@@ -115,9 +124,9 @@ int main() {
             s = nn::e40::mul40l(s, mv);
             want = (uint64_t)(((nn::u128)want * v) % m40);
             CHECK(nn::e40::to_u64(s) == want);
+            CHECK(nn::e40::to_f64(s) == orc_e40_to_f64(want));
             CHECK(fabs(s.hi) < 2.01 * nn::e40::kB && fabs(s.lo) <= 0.5001 * nn::e40::kB);
         }
-        CHECK(nn::e40::to_f64(s) == orc_e40_to_f64(want));
     }
     // the generator's own multiplier, stepped, against the oracle's steps
     {
