@@ -481,9 +481,10 @@ def main():
         # base-3^20 limbs, the flat layout with 16 rows per chunk in XCD runs),
         # the flat layout with 8 rows, the row layout and the Montgomery step.
         # Every configuration is run once before any is timed, then the
-        # configurations are timed in turn over four rounds (the best round
-        # counts): the first few dozen 3^40 launches of a process ran several
-        # per cent slower than later ones of the same kernel.
+        # configurations are timed in turn over four rounds, in reverse order
+        # every other round (the best round counts): the first few dozen 3^40
+        # launches of a process ran several per cent slower than later ones
+        # of the same kernel.
         z40 = nn.e40_seed(nn.E40_INDEX_MIN)
         for kind, out in (("f64", out_f), ("u64", out_u)):
             e40_cfgs = (("", None), ("_flat", nn.make_cfg(layout="flat", unroll=8)),
@@ -492,8 +493,8 @@ def main():
             for _, cfg in e40_cfgs:
                 nn.e40_generate_into(z40, out, cfg=cfg)
             best = {}
-            for _ in range(4):
-                for name, cfg in e40_cfgs:
+            for rnd in range(4):
+                for name, cfg in (e40_cfgs if rnd % 2 == 0 else e40_cfgs[::-1]):
                     s = _timed_kernel(lambda: nn.e40_generate_into(z40, out, cfg=cfg), 10, torch)
                     best[name] = min(best.get(name, s), s)
             for name, s in best.items():
