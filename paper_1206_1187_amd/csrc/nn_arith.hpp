@@ -68,7 +68,7 @@ struct Mult {
 // below 2^53, r an integer below m.  Three more instructions than
 // nn_dev_mulmod's single fused q m; the kernels that store every output use
 // this form because their stores, spaced by the longer instruction stream,
-// write faster on MI355X (same box, same shapes: plain u64 6.8-6.9 against
+// write faster on MI355X (same GPU, same shapes: plain u64 6.8-6.9 against
 // 5.8 TB/s, interleaved batch 6.1 against 5.8 TB/s).  The fused consumer,
 // bound by its arithmetic, uses nn_dev_mulmod (VarFP64Fused).  Translation
 // units are built with FP contraction off so no product is fused into a

@@ -650,7 +650,7 @@ int nn_e40_generate_ex(uint64_t* state, uint64_t count, void* out_dev, int kind,
         return fail(NN_EINVAL, "block %u: must be a multiple of 64 in [64, 1024]", block);
     // Defaults from sweeps on MI355X (2^30 f64 outputs, 256 threads):
     //  * FP64 limb step: one workgroup per CU, two rows in flight, no
-    //    unrolling: 6.1-6.3 TB/s on two boxes (ilp 4 within 2 %).  Grids that
+    //    unrolling: 6.1-6.3 TB/s on two GPUs (ilp 4 within 2 %).  Grids that
     //    are not a multiple of the CU count lose badly (272 workgroups: 3.9
     //    TB/s), since every workgroup carries the same number of rows;
     //  * Montgomery: three workgroups per CU, four rows in flight, unroll 2:

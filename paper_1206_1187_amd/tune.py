@@ -132,7 +132,7 @@ def _min_ms(fn, reps, rounds):
 def pick_plain_grid(cfg, out, state, deltas, rounds=3, reps=5):
     """The launch shape `cfg` (an nn_launch_cfg) with the grid that runs
     fastest on the current device among cfg.grid + d, d in `deltas`: the best
-    grid of a tuned shape differs between MI355X boxes by about one such
+    grid of a tuned shape differs between MI355X GPUs by about one such
     step.  Times generate_into(state, out) for each candidate, interleaving
     the candidates over `rounds` rounds.  Returns (cfg, {grid: ms})."""
     import paper_1206_1187_amd as nn
